@@ -1,0 +1,169 @@
+/*
+ * sorsvd.h - C ABI of the MI355X (gfx950) Subspace-Orbit Randomized SVD library.
+ *
+ * Method: Kaloorazi & de Lamare, "Subspace-Orbit Randomized Decomposition for
+ * Low-rank Matrix Approximation", Sec. III, Alg. 3 (basic SOR-SVD) and Alg. 4
+ * (SOR-SVD with power method), eqs. (T1), (AT1), (M), the rank-k truncated SVD
+ * of M and the lift A_hat = (Q1 U~_k) S~_k (Q2 V~_k)^T.
+ *
+ * Conventions for every entry point
+ *   - Matrices are ROW-MAJOR with a leading dimension in elements (lda >= cols).
+ *   - Every matrix pointer is a DEVICE pointer (HIP global memory) unless the
+ *     comment says "host". The library never allocates device memory: the
+ *     caller passes a workspace of at least the size the matching
+ *     *_workspace_bytes() call returns. The library keeps no state between calls.
+ *   - `stream` is a hipStream_t (NULL = the default stream). All work is
+ *     enqueued on it asynchronously; results are valid once the stream has
+ *     completed. Argument errors are detected synchronously, before anything is
+ *     enqueued, and reported by the return value.
+ *   - Return value: SORSVD_OK or a negative sorsvd_status. Conditions found on
+ *     the device (non-finite input, Jacobi sweep cap reached) are recorded in
+ *     the sorsvd_info record at the start of the workspace; read it with
+ *     sorsvd_read_info() after the stream has run.
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef SORSVD_H
+#define SORSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sorsvd_status {
+  SORSVD_OK = 0,
+  SORSVD_EINVAL = -1,        /* bad shape, leading dimension, null pointer or dtype */
+  SORSVD_EWORKSPACE = -2,    /* workspace smaller than *_workspace_bytes() */
+  SORSVD_EHIP = -3,          /* a HIP launch or runtime call failed */
+  SORSVD_ENOCONV = -4,       /* (info flag) Jacobi reached its sweep cap */
+  SORSVD_ENONFINITE = -5,    /* (info flag) A holds Inf or NaN */
+  SORSVD_EUNSUPPORTED = -7   /* valid request outside what this build implements */
+} sorsvd_status;
+
+/* Element types. A's type sets the arithmetic of the passes over A:
+ *   F64  -> FP64 MFMA, FP64 accumulation;
+ *   F32  -> FP32 MFMA, FP32 accumulation (partials summed in FP64);
+ *   BF16 -> BF16 MFMA, FP32 accumulation; the skinny operands are rounded to
+ *           BF16 (with opts.refine the projection pass splits Q2 into a BF16
+ *           high and low part).
+ * QR, the core SVD and the lift always run in FP64. */
+typedef enum sorsvd_dtype { SORSVD_F64 = 0, SORSVD_F32 = 1, SORSVD_BF16 = 2 } sorsvd_dtype;
+
+/* Optional settings; pass NULL for the defaults (all fields 0). */
+typedef struct sorsvd_opts {
+  int64_t l;          /* sketch width l, k <= l <= min(m, n); 0 means l = k */
+  int32_t max_sweeps; /* Jacobi sweep cap of the core SVD; 0 means 40 */
+  int32_t refine;     /* BF16 A only: 1 = projection pass with Q2 split hi+lo */
+  int32_t residual;   /* 1 = also compute ||A - U S V^T||_F explicitly (one more pass) */
+  int32_t split;      /* split of the contraction in the passes; 0 = automatic */
+  int32_t reserved0;
+  int32_t reserved1;
+} sorsvd_opts;
+
+/* Result record, kept by the library in the first 256 bytes of the workspace. */
+typedef struct sorsvd_info {
+  double a_fro;            /* ||A||_F, accumulated in FP64 during the first pass */
+  double err_fro;          /* sqrt(||A||_F^2 - sum_j s_j^2) / ||A||_F (Th. 2 split) */
+  double err_fro_explicit; /* ||A - U S V^T||_F / ||A||_F if opts.residual, else -1 */
+  int32_t sweeps;          /* Jacobi sweeps taken by the core SVD */
+  int32_t flags;           /* bit 0: sweep cap reached; bit 1: non-finite entry in A */
+} sorsvd_info;
+
+/* Workspace size in bytes for sorsvd() with the same arguments. Returns 0 for
+ * invalid arguments. */
+size_t sorsvd_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t q,
+                              int32_t a_type, const sorsvd_opts* opts);
+
+/*
+ * sorsvd - rank-k SOR-SVD of A (Alg. 3 for q = 0, Alg. 4 for q > 0).
+ *
+ *   A    m x n, type a_type, leading dimension lda >= n. Read only.
+ *   k    target rank, 1 <= k <= min(m, n).  q >= 0 power steps.
+ *   seed Philox key word of Omega: Omega[i][j] is N(0,1) draw number i + j*n of
+ *        key (seed, 0) (see sorsvd_philox_normal).
+ *   U    m x k FP64, ldu >= k.   S  k FP64 (descending).   V  n x k FP64, ldv >= k.
+ *
+ * Steps (Sec. III): T1 = A Omega; Q1 = qr(T1); Q2 = qr(A^T Q1); q times
+ * {Q1 = qr(A Q2); Q2 = qr(A^T Q1)}; M = Q1^T A Q2; M = U~ S~ V~^T (FP64 one-sided
+ * Jacobi); U = Q1 U~_k, V = Q2 V~_k. Orthonormalising after every product
+ * spans exactly what Alg. 4's unorthonormalised products span (Lemma 1).
+ * Sign convention: the largest-|.| entry of each U column is positive (lowest
+ * row on ties); V's column is flipped with it.
+ */
+int sorsvd(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
+           int64_t k, int32_t q, uint64_t seed,
+           double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+           void* workspace, size_t ws_bytes, void* stream, const sorsvd_opts* opts);
+
+/* Copy the sorsvd_info record out of `workspace` into host memory `out`,
+ * after waiting for `stream`. */
+int sorsvd_read_info(const void* workspace, sorsvd_info* out, void* stream);
+
+/*
+ * sorsvd_philox_normal - the Gaussian draw of Alg. 3 / Alg. 4 step 1.
+ * out (device, FP64) is rows x cols COLUMN-major with leading dimension rows:
+ * element (i, j) is draw e = i + j*rows of key (seed, stream_id): Philox4x64-10
+ * block with counter (e / 4, 0, word2, 0), Box-Muller pair of that block, member
+ * e % 4. Bitwise equal to the CPU reference of the same definition.
+ */
+int sorsvd_philox_normal(uint64_t seed, uint64_t stream_id, uint64_t word2,
+                         int64_t rows, int64_t cols, double* out, void* stream);
+
+/*
+ * Single steps of the path, for callers that compose their own pipeline and
+ * for per-step checks. Skinny operands are FP64 row-major with leading
+ * dimension l; they are rounded to A's compute type inside the pass.
+ *
+ * sorsvd_step_sketch: T (m x l) = A X, X n x l           (eq. T1; Alg. 4 T1 update)
+ * sorsvd_step_orbit:  T (n x l) = A^T Y, Y m x l         (eq. AT1; Alg. 4 T2 update)
+ * sorsvd_step_qr:     T (rows x l) = Q R, Q rows x l orthonormal, R l x l upper
+ *                     triangular with positive diagonal (QR step of Alg. 3/4).
+ *                     Q may alias T. Requires l <= rows.
+ * sorsvd_step_project: M (l x l) = Q1^T A Q2              (eq. M)
+ * sorsvd_step_core_svd: M (l x l) = U~ diag(s) V~^T, descending; writes the
+ *                     first k columns of U~ and V~ (l x k each) and s (k).
+ * Each needs the workspace size returned by sorsvd_step_workspace_bytes(m, n, l, a_type).
+ */
+size_t sorsvd_step_workspace_bytes(int64_t m, int64_t n, int64_t l, int32_t a_type);
+int sorsvd_step_sketch(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
+                       const double* X, int64_t l, double* T,
+                       void* workspace, size_t ws_bytes, void* stream);
+int sorsvd_step_orbit(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
+                      const double* Y, int64_t l, double* T,
+                      void* workspace, size_t ws_bytes, void* stream);
+int sorsvd_step_qr(const double* T, int64_t rows, int64_t l, double* Q, double* R,
+                   void* workspace, size_t ws_bytes, void* stream);
+int sorsvd_step_project(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
+                        const double* Q1, const double* Q2, int64_t l, double* M,
+                        void* workspace, size_t ws_bytes, void* stream);
+int sorsvd_step_core_svd(const double* M, int64_t l, int64_t k, double* Ut, double* s,
+                         double* Vt, int32_t max_sweeps,
+                         void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Profiling aid (not part of the method). sorsvd_pass_timing(1, capacity)
+ * creates 2*capacity HIP events; from then on every launch of the pass kernel
+ * over A (the sketch, orbit and projection products) is bracketed by a pair of
+ * events recorded on the call's stream, until `capacity` launches have been
+ * recorded. sorsvd_pass_timing_read() waits for the recorded events and
+ * returns the summed kernel time in ms, the number of launches, and the
+ * algorithmic bytes of A (m n element-size per launch) and flops (2 m n l per
+ * launch) they covered, then starts a new count. sorsvd_pass_timing(0, 0)
+ * destroys the events. Process-wide; not for concurrent use from several threads.
+ */
+int sorsvd_pass_timing(int32_t enable, int32_t capacity);
+int sorsvd_pass_timing_read(double* total_ms, int64_t* launches, double* bytes, double* flops);
+
+/* Human-readable text of a status code (static storage). */
+const char* sorsvd_status_string(int status);
+
+/* Library version string (static storage). */
+const char* sorsvd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SORSVD_H */

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) Subspace-Orbit Randomized SVD.
+
+The computation lives in ``libsorsvd.so`` (HIP kernels behind the C ABI of
+``include/sorsvd.h``); this package only marshals arguments. Importing it does
+not load the library; the first call does, and fails loudly if it is missing.
+"""
+from . import _lib
+from ._lib import SORSVD_BF16, SORSVD_F32, SORSVD_F64, SorsvdError, load
+from .api import (Plan, dtype_code, pass_timing, pass_timing_read, philox_normal, sorsvd, step_core_svd, step_orbit, step_project,
+                  step_qr, step_sketch, workspace_bytes)
+
+__all__ = ["Plan", "SorsvdError", "SORSVD_BF16", "SORSVD_F32", "SORSVD_F64", "dtype_code", "load",
+           "pass_timing", "pass_timing_read", "philox_normal", "sorsvd", "step_core_svd", "step_orbit", "step_project", "step_qr",
+           "step_sketch", "workspace_bytes"]

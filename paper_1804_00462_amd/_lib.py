@@ -1,0 +1,85 @@
+"""ctypes loader for libsorsvd.so: argument marshalling only, no arithmetic.
+
+The library must have been built (``paper_1804_00462_amd.build.build()``);
+a missing library is an error, never a silent fallback.
+"""
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsorsvd.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sorsvd.h")
+
+c_i32, c_i64, c_u64, c_sz, c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
+c_vp = ctypes.c_void_p
+
+SORSVD_F64, SORSVD_F32, SORSVD_BF16 = 0, 1, 2
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error",
+          -4: "Jacobi sweep cap reached", -5: "non-finite input", -7: "unsupported in this build"}
+
+
+class SorsvdError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {STATUS.get(status, 'unknown')} ({status})")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("l", c_i64), ("max_sweeps", c_i32), ("refine", c_i32), ("residual", c_i32),
+                ("split", c_i32), ("reserved0", c_i32), ("reserved1", c_i32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("a_fro", c_dbl), ("err_fro", c_dbl), ("err_fro_explicit", c_dbl),
+                ("sweeps", c_i32), ("flags", c_i32)]
+
+
+_SIGS = {
+    "sorsvd_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i32, c_i32, c_vp]),
+    "sorsvd": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_i64, c_i32, c_u64,
+                       c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp, c_vp]),
+    "sorsvd_read_info": (c_i32, [c_vp, c_vp, c_vp]),
+    "sorsvd_philox_normal": (c_i32, [c_u64, c_u64, c_u64, c_i64, c_i64, c_vp, c_vp]),
+    "sorsvd_step_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i32]),
+    "sorsvd_step_sketch": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "sorsvd_step_orbit": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "sorsvd_step_qr": (c_i32, [c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "sorsvd_step_project": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "sorsvd_step_core_svd": (c_i32, [c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_i32, c_vp, c_sz, c_vp]),
+    "sorsvd_pass_timing": (c_i32, [c_i32, c_i32]),
+    "sorsvd_pass_timing_read": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "sorsvd_status_string": (ctypes.c_char_p, [c_i32]),
+    "sorsvd_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def header_symbols():
+    """Function names declared in include/sorsvd.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sorsvd\w*)\s*\(", text)))
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1804_00462_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status, where):
+    if status != 0:
+        raise SorsvdError(status, where)

@@ -1,0 +1,200 @@
+"""Python binding of the SOR-SVD C ABI (include/sorsvd.h).
+
+PyTorch provides device memory and the current HIP stream; every step of the
+computation runs in the library's kernels. Names follow the C entry points.
+"""
+import ctypes
+
+from . import _lib
+from ._lib import SORSVD_BF16, SORSVD_F32, SORSVD_F64, Info, Opts, check
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(dtype):
+    torch = _torch()
+    if dtype == torch.float64:
+        return SORSVD_F64
+    if dtype == torch.float32:
+        return SORSVD_F32
+    if dtype == torch.bfloat16:
+        return SORSVD_BF16
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_matrix(A):
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor")
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major (unit column stride)")
+
+
+def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0):
+    return Opts(l=l, max_sweeps=max_sweeps, refine=refine, residual=residual, split=split)
+
+
+def workspace_bytes(m, n, k, q, dtype_or_code, **opts):
+    code = dtype_or_code if isinstance(dtype_or_code, int) else dtype_code(dtype_or_code)
+    o = make_opts(**opts)
+    return int(_lib.load().sorsvd_workspace_bytes(m, n, k, q, code, ctypes.byref(o)))
+
+
+class Plan:
+    """Outputs and workspace for repeated SOR-SVDs of one shape (no allocation per call)."""
+
+    def __init__(self, m, n, k, q, dtype, device="cuda", **opts):
+        torch = _torch()
+        self.m, self.n, self.k, self.q = m, n, k, q
+        self.code = dtype_code(dtype)
+        self.opts = make_opts(**opts)
+        lib = _lib.load()
+        nbytes = int(lib.sorsvd_workspace_bytes(m, n, k, q, self.code, ctypes.byref(self.opts)))
+        if nbytes == 0:
+            raise _lib.SorsvdError(-1, "sorsvd_workspace_bytes")
+        self.ws_bytes = nbytes
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.U = torch.empty(m, k, dtype=torch.float64, device=device)
+        self.S = torch.empty(k, dtype=torch.float64, device=device)
+        self.V = torch.empty(n, k, dtype=torch.float64, device=device)
+
+    def run(self, A, seed=0, stream=None):
+        _check_matrix(A)
+        if tuple(A.shape) != (self.m, self.n) or dtype_code(A.dtype) != self.code:
+            raise ValueError("A does not match the plan")
+        lib = _lib.load()
+        st = lib.sorsvd(_ptr(A), A.stride(0), self.code, self.m, self.n, self.k, self.q, seed,
+                        _ptr(self.U), self.k, _ptr(self.S), _ptr(self.V), self.k,
+                        _ptr(self.ws), self.ws_bytes, _stream(stream), ctypes.byref(self.opts))
+        check(st, "sorsvd")
+        return self.U, self.S, self.V
+
+    def info(self, stream=None):
+        out = Info()
+        check(_lib.load().sorsvd_read_info(_ptr(self.ws), ctypes.byref(out), _stream(stream)), "sorsvd_read_info")
+        return {"a_fro": out.a_fro, "err_fro": out.err_fro, "err_fro_explicit": out.err_fro_explicit,
+                "sweeps": out.sweeps, "flags": out.flags}
+
+
+def sorsvd(A, k, q=0, seed=0, **opts):
+    """Rank-k SOR-SVD of the device matrix A. Returns (U, S, V, info) as FP64 tensors."""
+    plan = Plan(A.shape[0], A.shape[1], k, q, A.dtype, device=A.device, **opts)
+    U, S, V = plan.run(A, seed)
+    return U, S, V, plan.info()
+
+
+def philox_normal(seed, rows, cols, stream_id=0, word2=0, device="cuda"):
+    """rows x cols N(0,1) draws (element (i, j) = draw i + j*rows), as a device FP64 tensor."""
+    torch = _torch()
+    out = torch.empty(cols, rows, dtype=torch.float64, device=device)  # column-major storage
+    check(_lib.load().sorsvd_philox_normal(seed, stream_id, word2, rows, cols, _ptr(out), _stream()),
+          "sorsvd_philox_normal")
+    return out.t()
+
+
+def _step_ws(m, n, l, code, device):
+    torch = _torch()
+    nbytes = int(_lib.load().sorsvd_step_workspace_bytes(m, n, l, code))
+    if nbytes == 0:
+        raise _lib.SorsvdError(-1, "sorsvd_step_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def step_sketch(A, X):
+    """T = A X (X: n x l FP64 device tensor)."""
+    torch = _torch()
+    _check_matrix(A)
+    m, n = A.shape
+    l = X.shape[1]
+    code = dtype_code(A.dtype)
+    X = X.contiguous().to(torch.float64)
+    T = torch.empty(m, l, dtype=torch.float64, device=A.device)
+    ws, nb = _step_ws(m, n, l, code, A.device)
+    check(_lib.load().sorsvd_step_sketch(_ptr(A), A.stride(0), code, m, n, _ptr(X), l, _ptr(T),
+                                         _ptr(ws), nb, _stream()), "sorsvd_step_sketch")
+    return T
+
+
+def step_orbit(A, Y):
+    """T = A^T Y (Y: m x l FP64 device tensor)."""
+    torch = _torch()
+    _check_matrix(A)
+    m, n = A.shape
+    l = Y.shape[1]
+    code = dtype_code(A.dtype)
+    Y = Y.contiguous().to(torch.float64)
+    T = torch.empty(n, l, dtype=torch.float64, device=A.device)
+    ws, nb = _step_ws(m, n, l, code, A.device)
+    check(_lib.load().sorsvd_step_orbit(_ptr(A), A.stride(0), code, m, n, _ptr(Y), l, _ptr(T),
+                                        _ptr(ws), nb, _stream()), "sorsvd_step_orbit")
+    return T
+
+
+def step_qr(T):
+    """T = Q R with orthonormal Q and upper-triangular R (positive diagonal)."""
+    torch = _torch()
+    T = T.contiguous().to(torch.float64)
+    rows, l = T.shape
+    Q = torch.empty(rows, l, dtype=torch.float64, device=T.device)
+    R = torch.empty(l, l, dtype=torch.float64, device=T.device)
+    ws, nb = _step_ws(rows, l, l, SORSVD_F64, T.device)
+    check(_lib.load().sorsvd_step_qr(_ptr(T), rows, l, _ptr(Q), _ptr(R), _ptr(ws), nb, _stream()),
+          "sorsvd_step_qr")
+    return Q, R
+
+
+def step_project(A, Q1, Q2):
+    """M = Q1^T A Q2."""
+    torch = _torch()
+    _check_matrix(A)
+    m, n = A.shape
+    l = Q1.shape[1]
+    code = dtype_code(A.dtype)
+    Q1 = Q1.contiguous().to(torch.float64)
+    Q2 = Q2.contiguous().to(torch.float64)
+    M = torch.empty(l, l, dtype=torch.float64, device=A.device)
+    ws, nb = _step_ws(m, n, l, code, A.device)
+    check(_lib.load().sorsvd_step_project(_ptr(A), A.stride(0), code, m, n, _ptr(Q1), _ptr(Q2), l,
+                                          _ptr(M), _ptr(ws), nb, _stream()), "sorsvd_step_project")
+    return M
+
+
+def step_core_svd(M, k, max_sweeps=0):
+    """M = U~ diag(s) V~^T; returns the first k columns of U~, s, V~."""
+    torch = _torch()
+    M = M.contiguous().to(torch.float64)
+    l = M.shape[0]
+    Ut = torch.empty(l, k, dtype=torch.float64, device=M.device)
+    Vt = torch.empty(l, k, dtype=torch.float64, device=M.device)
+    s = torch.empty(k, dtype=torch.float64, device=M.device)
+    ws, nb = _step_ws(l, l, l, SORSVD_F64, M.device)
+    check(_lib.load().sorsvd_step_core_svd(_ptr(M), l, k, _ptr(Ut), _ptr(s), _ptr(Vt), max_sweeps,
+                                           _ptr(ws), nb, _stream()), "sorsvd_step_core_svd")
+    info = Info()
+    check(_lib.load().sorsvd_read_info(_ptr(ws), ctypes.byref(info), _stream()), "sorsvd_read_info")
+    return Ut, s, Vt, {"sweeps": info.sweeps, "flags": info.flags}
+
+
+def pass_timing(enable, capacity=256):
+    """Turn the per-launch event timing of the pass kernel over A on or off."""
+    check(_lib.load().sorsvd_pass_timing(1 if enable else 0, capacity if enable else 0), "sorsvd_pass_timing")
+
+
+def pass_timing_read():
+    """(total_ms, launches, algorithmic_bytes, flops) recorded since the last read."""
+    ms, n, b, f = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    check(_lib.load().sorsvd_pass_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
+                                              ctypes.byref(f)), "sorsvd_pass_timing_read")
+    return ms.value, n.value, b.value, f.value

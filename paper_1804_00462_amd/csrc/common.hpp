@@ -1,0 +1,58 @@
+// Shared device definitions of the SOR-SVD library (gfx950 / CDNA4, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t bf16_t;  // storage type of BF16 data (raw bits)
+
+namespace sor {
+
+constexpr int kWave = 64;
+constexpr int kTile = 16;  // MFMA output tile edge
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// Round-to-nearest-even FP32 -> BF16 (finite inputs; NaN kept quiet).
+__device__ inline bf16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(r >> 16);
+}
+__device__ inline float bf16_to_f32(bf16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// FP64 -> BF16 with a single rounding: round to FP32 with round-to-odd
+// (exact results unchanged, inexact ones truncated toward zero with the last
+// bit set), then round that to BF16 to nearest-even. FP32 carries more than
+// two extra bits beyond BF16, so the result equals direct rounding of d.
+__device__ inline bf16_t f64_to_bf16(double d) {
+  float f = (float)d;
+  double back = (double)f;
+  if (back != d && back - back == 0.0) {
+    uint32_t u = __float_as_uint(f);
+    if (fabs(back) > fabs(d)) u -= 1u;
+    u |= 1u;
+    f = __uint_as_float(u);
+  }
+  return f32_to_bf16(f);
+}
+
+// Sum over a full wavefront (64 lanes); every lane gets the total.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over aligned groups of `width` lanes (width a power of two <= 64).
+__device__ inline double group_sum(double v, int width) {
+  for (int off = width >> 1; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+}  // namespace sor

@@ -1,0 +1,555 @@
+// Host orchestration and C ABI of the SOR-SVD library (see include/sorsvd.h).
+//
+// One call enqueues, on the caller's stream, the sequence of Sec. III:
+//   Omega (Philox) -> T1 = A Omega -> QR -> T2 = A^T Q1 -> QR
+//   -> q x {T1 = A Q2 -> QR -> T2 = A^T Q1 -> QR}
+//   -> M = Q1^T (A Q2) -> core SVD -> U = Q1 U~_k, V = Q2 V~_k -> signs, error.
+// Nothing is allocated and nothing waits for the device; argument checks come
+// first and fail before any launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/sorsvd.h"
+#include "common.hpp"
+
+namespace sor {
+
+// gemm.hip
+hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
+                             const double* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
+                             double* P, double* normp, const int* skipflag, hipStream_t st);
+hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OUT, int64_t K,
+                             const float* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
+                             float* P, double* normp, const int* skipflag, hipStream_t st);
+hipError_t launch_reduce_f64(const double* P, int64_t OUT, int LP, int nsplit, double* out,
+                             int64_t ldo, int ncols, hipStream_t st);
+hipError_t launch_reduce_f32(const float* P, int64_t OUT, int LP, int nsplit, double* out,
+                             int64_t ldo, int ncols, hipStream_t st);
+hipError_t launch_pack_f64(const double* src, int64_t rows, int cols, int64_t lds, double* dst,
+                           int LP, hipStream_t st);
+hipError_t launch_pack_f32(const double* src, int64_t rows, int cols, int64_t lds, float* dst,
+                           int LP, hipStream_t st);
+hipError_t launch_cast_f32(const double* Q, int64_t n_elem, float* Xc, hipStream_t st);
+hipError_t launch_zero_lower(double* R, int l, hipStream_t st);
+int skinny_rows_per_block(int a_type);
+int skinny_step(int a_type);
+// philox.hip
+hipError_t launch_omega_f64_colmajor(uint64_t seed, uint64_t stream_id, uint64_t word2,
+                                     int64_t rows, int64_t cols, double* out, hipStream_t st);
+hipError_t launch_omega_rowmajor_f64(uint64_t seed, int64_t rows, int64_t cols, double* out,
+                                     int64_t ldx, hipStream_t st);
+hipError_t launch_omega_rowmajor_f32(uint64_t seed, int64_t rows, int64_t cols, float* out,
+                                     int64_t ldx, hipStream_t st);
+// small.hip
+hipError_t launch_chol_inv(const double* G, int LP, int l, int64_t rows, int shifted, int may_skip,
+                           double* Rinv, int* skip, void* info, hipStream_t st);
+hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, double* Ut,
+                         double* sv, double* Vt, int ldk, double* Vg, void* info, hipStream_t st);
+hipError_t launch_signfix(const double* U64, int64_t m, const double* V64, int64_t n, int ld, int k,
+                          double* pval, int64_t* pidx, int nblocks_max, double* sgn, double* U,
+                          int64_t ldu, double* V, int64_t ldv, hipStream_t st);
+hipError_t launch_finalize(const double* normp, int nparts, const double* sv, int k, void* info,
+                           hipStream_t st);
+hipError_t launch_info_init(void* info, hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+
+namespace {
+
+constexpr int kMaxLP = 128;        // widest sketch handled by the pass kernels
+constexpr int kSignBlocks = 1024;  // max row blocks of the sign search
+constexpr size_t kAlign = 256;
+
+struct Split {
+  int64_t kchunk = 0;
+  int nsplit = 1;
+};
+
+// Split of a contraction of length K for OUT output rows: enough workgroups
+// to fill 256 CUs several times over, each split at least 8 steps long, and
+// partial sums no larger than 1/8 of the bytes of the streamed operand.
+Split choose_split(int64_t OUT, int64_t K, int rows_per_block, int KS, int LP, int es_a,
+                   int acc_bytes, int forced) {
+  Split sp;
+  if (K <= 0) { sp.kchunk = KS; sp.nsplit = 1; return sp; }
+  const int64_t tiles = std::max<int64_t>(1, ceil_div(OUT, rows_per_block));
+  int64_t s = std::max<int64_t>(1, ceil_div(2048, tiles));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, K / (8 * KS)));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, (K * es_a) / (8 * (int64_t)LP * acc_bytes)));
+  if (forced > 0) s = forced;
+  sp.kchunk = round_up(ceil_div(K, s), KS);
+  sp.nsplit = (int)ceil_div(K, sp.kchunk);
+  return sp;
+}
+
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    const size_t off = total;
+    total += round_up((int64_t)bytes, kAlign);
+    return off;
+  }
+};
+
+struct Plan {
+  int a_type;
+  int64_t m, n, k, l, LP, KP;
+  int q;
+  int es;
+  int max_sweeps;
+  Split nn, tn, gram_m, gram_n, proj;
+  int nn_blocks;
+  size_t off_info, off_xc, off_t1, off_t2, off_w, off_u64, off_v64, off_p, off_normp;
+  size_t off_g, off_rinv, off_m, off_ut, off_vt, off_vg, off_pval, off_pidx, off_sgn, off_skip;
+  size_t total;
+};
+
+int elem_size(int t) { return t == SORSVD_F64 ? 8 : (t == SORSVD_F32 ? 4 : 2); }
+
+size_t partial_bytes(int64_t OUT, int64_t LP, const Split& s, int acc) {
+  return (size_t)s.nsplit * OUT * LP * acc;
+}
+
+int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const sorsvd_opts* o,
+              Plan* p) {
+  if (a_type != SORSVD_F64 && a_type != SORSVD_F32) {
+    if (a_type == SORSVD_BF16) return SORSVD_EUNSUPPORTED;
+    return SORSVD_EINVAL;
+  }
+  if (m < 1 || n < 1 || k < 1 || q < 0) return SORSVD_EINVAL;
+  const int64_t l = (o && o->l > 0) ? o->l : k;
+  if (k > l || l > std::min(m, n)) return SORSVD_EINVAL;
+  const int64_t LP = round_up(l, kTile), KP = round_up(k, kTile);
+  if (LP > kMaxLP) return SORSVD_EUNSUPPORTED;
+  if (o && o->residual) return SORSVD_EUNSUPPORTED;
+  p->a_type = a_type; p->m = m; p->n = n; p->k = k; p->l = l; p->LP = LP; p->KP = KP; p->q = q;
+  p->es = elem_size(a_type);
+  p->max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
+  const int forced = o ? o->split : 0;
+  const int rpb = skinny_rows_per_block(a_type), ks = skinny_step(a_type);
+  const int acc = a_type == SORSVD_F64 ? 8 : 4;
+  p->nn = choose_split(m, n, rpb, ks, (int)LP, p->es, acc, forced);
+  p->tn = choose_split(n, m, rpb, ks, (int)LP, p->es, acc, forced);
+  const int rpb64 = skinny_rows_per_block(SORSVD_F64), ks64 = skinny_step(SORSVD_F64);
+  p->gram_m = choose_split(LP, m, rpb64, ks64, (int)LP, 8, 8, 0);
+  p->gram_n = choose_split(LP, n, rpb64, ks64, (int)LP, 8, 8, 0);
+  p->proj = p->gram_m;
+  p->nn_blocks = (int)(ceil_div(m, rpb) * p->nn.nsplit);
+
+  Layout L;
+  p->off_info = L.take(256);
+  const int64_t rows = std::max(m, n);
+  p->off_xc = L.take((size_t)rows * LP * p->es);
+  p->off_t1 = L.take((size_t)m * LP * 8);
+  p->off_t2 = L.take((size_t)n * LP * 8);
+  p->off_w = L.take((size_t)m * LP * 8);
+  p->off_u64 = L.take((size_t)m * KP * 8);
+  p->off_v64 = L.take((size_t)n * KP * 8);
+  size_t pb = 0;
+  pb = std::max(pb, partial_bytes(m, LP, p->nn, acc));
+  pb = std::max(pb, partial_bytes(n, LP, p->tn, acc));
+  pb = std::max(pb, partial_bytes(LP, LP, p->gram_m, 8));
+  pb = std::max(pb, partial_bytes(LP, LP, p->gram_n, 8));
+  p->off_p = L.take(pb);
+  p->off_normp = L.take((size_t)std::max(p->nn_blocks, 1) * 8);
+  p->off_g = L.take((size_t)LP * LP * 8);
+  p->off_rinv = L.take((size_t)LP * LP * 8);
+  p->off_m = L.take((size_t)LP * LP * 8);
+  p->off_ut = L.take((size_t)LP * KP * 8);
+  p->off_vt = L.take((size_t)LP * KP * 8);
+  p->off_vg = L.take((size_t)LP * LP * 8);
+  p->off_pval = L.take((size_t)kSignBlocks * KP * 8);
+  p->off_pidx = L.take((size_t)kSignBlocks * KP * 8);
+  p->off_sgn = L.take((size_t)KP * 8);
+  p->off_skip = L.take(64);
+  p->total = L.total;
+  return SORSVD_OK;
+}
+
+#define SORSVD_TRY(expr)                          \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return SORSVD_EHIP;     \
+  } while (0)
+
+template <typename T> T* at(void* ws, size_t off) { return reinterpret_cast<T*>((char*)ws + off); }
+
+// Cholesky QR of T (rows x LP, FP64, padding columns zero) in place:
+// shifted step, plain step, and a third step that only runs when the second
+// left T measurably non-orthonormal.
+int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void* ws, hipStream_t st) {
+  double* P = at<double>(ws, p.off_p);
+  double* G = at<double>(ws, p.off_g);
+  double* Rinv = at<double>(ws, p.off_rinv);
+  int* skip = at<int>(ws, p.off_skip);
+  void* info = at<void>(ws, p.off_info);
+  const int LP = (int)p.LP;
+  for (int it = 0; it < 3; ++it) {
+    SORSVD_TRY(launch_skinny_f64(true, T, LP, LP, rows, T, LP, LP, gram.kchunk, gram.nsplit, P,
+                                     nullptr, nullptr, st));
+    SORSVD_TRY(launch_reduce_f64(P, LP, LP, gram.nsplit, G, LP, LP, st));
+    SORSVD_TRY(launch_chol_inv(G, LP, (int)p.l, rows, it == 0 ? 1 : 0, it == 2 ? 1 : 0, Rinv, skip,
+                               info, st));
+    SORSVD_TRY(launch_skinny_f64(false, T, LP, rows, LP, Rinv, LP, LP, LP, 1, T, nullptr,
+                                     it == 2 ? skip : nullptr, st));
+  }
+  return SORSVD_OK;
+}
+
+// Optional per-launch timing of the pass kernel over A (profiling aid):
+// a pair of HIP events is recorded around each launch on the call's stream.
+struct PassTimer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  double bytes = 0.0, flops = 0.0;
+};
+PassTimer& timer() {
+  static PassTimer t;
+  return t;
+}
+
+// T (OUT x LP, FP64) = A X   (trans = false, X in compute type, K = n)
+//                    = A^T Y (trans = true,  Y in compute type, K = m)
+int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, double* T,
+         double* normp, void* ws, hipStream_t st) {
+  const int LP = (int)p.LP;
+  const int64_t OUT = trans ? p.n : p.m;
+  const int64_t K = trans ? p.m : p.n;
+  const Split& sp = trans ? p.tn : p.nn;
+  PassTimer& tm = timer();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (tm.on) {
+    std::lock_guard<std::mutex> g(tm.mu);
+    if (tm.used + 2 <= tm.ev.size()) {
+      e0 = tm.ev[tm.used];
+      e1 = tm.ev[tm.used + 1];
+      tm.used += 2;
+      tm.bytes += (double)p.m * p.n * p.es;
+      tm.flops += 2.0 * p.m * p.n * p.l;
+    }
+  }
+  if (e0) SORSVD_TRY(hipEventRecord(e0, st));
+  if (p.a_type == SORSVD_F64) {
+    double* P = at<double>(ws, p.off_p);
+    SORSVD_TRY(launch_skinny_f64(trans, (const double*)A, lda, OUT, K, (const double*)Xc, LP, LP,
+                                     sp.kchunk, sp.nsplit, P, normp, nullptr, st));
+    if (e1) SORSVD_TRY(hipEventRecord(e1, st));
+    SORSVD_TRY(launch_reduce_f64(P, OUT, LP, sp.nsplit, T, LP, LP, st));
+  } else {
+    float* P = at<float>(ws, p.off_p);
+    SORSVD_TRY(launch_skinny_f32(trans, (const float*)A, lda, OUT, K, (const float*)Xc, LP, LP,
+                                    sp.kchunk, sp.nsplit, P, normp, nullptr, st));
+    if (e1) SORSVD_TRY(hipEventRecord(e1, st));
+    SORSVD_TRY(launch_reduce_f32(P, OUT, LP, sp.nsplit, T, LP, LP, st));
+  }
+  return SORSVD_OK;
+}
+
+// Skinny operand of the next pass: Q (rows x LP, FP64) in A's compute type.
+const void* as_operand(const Plan& p, const double* Q, int64_t rows, void* ws, hipStream_t st, int* rc) {
+  *rc = SORSVD_OK;
+  if (p.a_type == SORSVD_F64) return Q;
+  float* Xc = at<float>(ws, p.off_xc);
+  if (launch_cast_f32(Q, rows * p.LP, Xc, st) != hipSuccess) *rc = SORSVD_EHIP;
+  return Xc;
+}
+
+int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int64_t ldu, double* S,
+        double* V, int64_t ldv, void* ws, hipStream_t st) {
+  const int LP = (int)p.LP, KP = (int)p.KP;
+  void* info = at<void>(ws, p.off_info);
+  double* T1 = at<double>(ws, p.off_t1);
+  double* T2 = at<double>(ws, p.off_t2);
+  double* W = at<double>(ws, p.off_w);
+  double* normp = at<double>(ws, p.off_normp);
+  int rc;
+  SORSVD_TRY(launch_info_init(info, st));
+
+  // Omega, n x l (Alg. 3 / Alg. 4 step 1), straight into the compute-type operand.
+  void* Xc = at<void>(ws, p.off_xc);
+  SORSVD_TRY(launch_fill((double*)Xc, (p.n * LP * p.es + 7) / 8, 0.0, st));
+  if (p.a_type == SORSVD_F64)
+    SORSVD_TRY(launch_omega_rowmajor_f64(seed, p.n, p.l, (double*)Xc, LP, st));
+  else
+    SORSVD_TRY(launch_omega_rowmajor_f32(seed, p.n, p.l, (float*)Xc, LP, st));
+
+  // T1 = A Omega (eq. T1), with ||A||_F^2 accumulated on the way; Q1 = qr(T1).
+  if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
+  if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+  // T2 = A^T Q1 (eq. AT1; the span of A^T T1 by Lemma 1); Q2 = qr(T2).
+  const void* Y = as_operand(p, T1, p.m, ws, st, &rc);
+  if (rc) return rc;
+  if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
+  if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st))) return rc;
+  // Power method (Alg. 4 loop), orthonormalising after each product.
+  for (int it = 0; it < p.q; ++it) {
+    const void* X = as_operand(p, T2, p.n, ws, st, &rc);
+    if (rc) return rc;
+    if ((rc = pass(p, false, A, lda, X, T1, nullptr, ws, st))) return rc;
+    if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+    Y = as_operand(p, T1, p.m, ws, st, &rc);
+    if (rc) return rc;
+    if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
+    if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st))) return rc;
+  }
+  // M = Q1^T (A Q2) (eq. M): W = A Q2 in the pass kernel, then the FP64 Q1^T W.
+  const void* X = as_operand(p, T2, p.n, ws, st, &rc);
+  if (rc) return rc;
+  if ((rc = pass(p, false, A, lda, X, W, nullptr, ws, st))) return rc;
+  double* P = at<double>(ws, p.off_p);
+  double* M = at<double>(ws, p.off_m);
+  SORSVD_TRY(launch_skinny_f64(true, T1, LP, LP, p.m, W, LP, LP, p.proj.kchunk, p.proj.nsplit, P,
+                                   nullptr, nullptr, st));
+  SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.proj.nsplit, M, LP, LP, st));
+
+  // Core SVD M = U~ S~ V~^T, truncated to k (Alg. 3 step 6).
+  double* Ut = at<double>(ws, p.off_ut);
+  double* Vt = at<double>(ws, p.off_vt);
+  SORSVD_TRY(launch_fill(Ut, (int64_t)LP * KP, 0.0, st));
+  SORSVD_TRY(launch_fill(Vt, (int64_t)LP * KP, 0.0, st));
+  SORSVD_TRY(launch_jacobi(M, LP, (int)p.l, (int)p.k, p.max_sweeps, Ut, S, Vt, KP,
+                           at<double>(ws, p.off_vg), info, st));
+
+  // Lift: U = Q1 U~_k, V = Q2 V~_k (Alg. 3 step 7), then the sign convention.
+  double* U64 = at<double>(ws, p.off_u64);
+  double* V64 = at<double>(ws, p.off_v64);
+  SORSVD_TRY(launch_skinny_f64(false, T1, LP, p.m, LP, Ut, KP, KP, LP, 1, U64, nullptr, nullptr, st));
+  SORSVD_TRY(launch_skinny_f64(false, T2, LP, p.n, LP, Vt, KP, KP, LP, 1, V64, nullptr, nullptr, st));
+  SORSVD_TRY(launch_signfix(U64, p.m, V64, p.n, KP, (int)p.k, at<double>(ws, p.off_pval),
+                            at<int64_t>(ws, p.off_pidx), kSignBlocks, at<double>(ws, p.off_sgn), U, ldu,
+                            V, ldv, st));
+  SORSVD_TRY(launch_finalize(normp, p.nn_blocks, S, (int)p.k, info, st));
+  return SORSVD_OK;
+}
+
+}  // namespace
+}  // namespace sor
+
+using namespace sor;
+
+extern "C" {
+
+size_t sorsvd_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type,
+                              const sorsvd_opts* opts) {
+  Plan p;
+  if (make_plan(m, n, k, q, a_type, opts, &p) != SORSVD_OK) return 0;
+  return p.total;
+}
+
+int sorsvd(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, int64_t k, int32_t q,
+           uint64_t seed, double* U, int64_t ldu, double* S, double* V, int64_t ldv, void* workspace,
+           size_t ws_bytes, void* stream, const sorsvd_opts* opts) {
+  Plan p;
+  const int rc = make_plan(m, n, k, q, a_type, opts, &p);
+  if (rc != SORSVD_OK) return rc;
+  if (!A || !U || !S || !V || !workspace) return SORSVD_EINVAL;
+  if (lda < n || ldu < k || ldv < k) return SORSVD_EINVAL;
+  if (ws_bytes < p.total) return SORSVD_EWORKSPACE;
+  if (((uintptr_t)workspace) % kAlign) return SORSVD_EINVAL;
+  return run(p, A, lda, seed, U, ldu, S, V, ldv, workspace, (hipStream_t)stream);
+}
+
+int sorsvd_read_info(const void* workspace, sorsvd_info* out, void* stream) {
+  if (!workspace || !out) return SORSVD_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SORSVD_EHIP;
+  if (hipMemcpy(out, workspace, sizeof(sorsvd_info), hipMemcpyDeviceToHost) != hipSuccess) return SORSVD_EHIP;
+  return SORSVD_OK;
+}
+
+int sorsvd_philox_normal(uint64_t seed, uint64_t stream_id, uint64_t word2, int64_t rows,
+                         int64_t cols, double* out, void* stream) {
+  if (rows < 0 || cols < 0 || (!out && rows * cols > 0)) return SORSVD_EINVAL;
+  if (launch_omega_f64_colmajor(seed, stream_id, word2, rows, cols, out, (hipStream_t)stream) != hipSuccess)
+    return SORSVD_EHIP;
+  return SORSVD_OK;
+}
+
+// ------------------------------------------------------------- single steps
+
+size_t sorsvd_step_workspace_bytes(int64_t m, int64_t n, int64_t l, int32_t a_type) {
+  sorsvd_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.l = l;
+  Plan p;
+  if (make_plan(m, n, l, 0, a_type, &o, &p) != SORSVD_OK) return 0;
+  // room for packed FP64 copies of two skinny operands (QR input copy, projection)
+  return p.total + 2 * round_up((int64_t)std::max(m, n) * p.LP * 8, kAlign);
+}
+
+static int step_plan(int64_t m, int64_t n, int64_t l, int32_t a_type, size_t ws_bytes, Plan* p) {
+  sorsvd_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.l = l;
+  const int rc = make_plan(m, n, l, 0, a_type, &o, p);
+  if (rc != SORSVD_OK) return rc;
+  if (ws_bytes < sorsvd_step_workspace_bytes(m, n, l, a_type)) return SORSVD_EWORKSPACE;
+  return SORSVD_OK;
+}
+
+static int pack_operand(const Plan& p, const double* src, int64_t rows, int64_t l, void* ws,
+                        hipStream_t st, const void** out) {
+  if (p.a_type == SORSVD_F64) {
+    double* d = at<double>(ws, p.off_xc);
+    SORSVD_TRY(launch_pack_f64(src, rows, (int)l, l, d, (int)p.LP, st));
+    *out = d;
+  } else {
+    float* d = at<float>(ws, p.off_xc);
+    SORSVD_TRY(launch_pack_f32(src, rows, (int)l, l, d, (int)p.LP, st));
+    *out = d;
+  }
+  return SORSVD_OK;
+}
+
+int sorsvd_step_sketch(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
+                       const double* X, int64_t l, double* T, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = step_plan(m, n, l, a_type, ws_bytes, &p);
+  if (rc) return rc;
+  if (!A || !X || !T || lda < n) return SORSVD_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const void* Xc;
+  if ((rc = pack_operand(p, X, n, l, ws, st, &Xc))) return rc;
+  double* Tp = at<double>(ws, p.off_t1);
+  if ((rc = pass(p, false, A, lda, Xc, Tp, nullptr, ws, st))) return rc;
+  SORSVD_TRY(launch_pack_f64(Tp, m, (int)l, p.LP, T, (int)l, st));
+  return SORSVD_OK;
+}
+
+int sorsvd_step_orbit(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
+                      const double* Y, int64_t l, double* T, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = step_plan(m, n, l, a_type, ws_bytes, &p);
+  if (rc) return rc;
+  if (!A || !Y || !T || lda < n) return SORSVD_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const void* Yc;
+  if ((rc = pack_operand(p, Y, m, l, ws, st, &Yc))) return rc;
+  double* Tp = at<double>(ws, p.off_t2);
+  if ((rc = pass(p, true, A, lda, Yc, Tp, nullptr, ws, st))) return rc;
+  SORSVD_TRY(launch_pack_f64(Tp, n, (int)l, p.LP, T, (int)l, st));
+  return SORSVD_OK;
+}
+
+int sorsvd_step_qr(const double* T, int64_t rows, int64_t l, double* Q, double* R, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (!T || !Q || !R || l < 1 || rows < l) return SORSVD_EINVAL;
+  Plan p;
+  int rc = step_plan(rows, l, l, SORSVD_F64, ws_bytes, &p);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int LP = (int)p.LP;
+  double* Tq = at<double>(ws, p.off_t1);
+  double* Tc = at<double>(ws, p.total);  // packed copy of the input
+  SORSVD_TRY(launch_info_init(at<void>(ws, p.off_info), st));
+  SORSVD_TRY(launch_pack_f64(T, rows, (int)l, l, Tq, LP, st));
+  SORSVD_TRY(launch_pack_f64(T, rows, (int)l, l, Tc, LP, st));
+  if ((rc = tsqr_inplace(p, Tq, rows, p.gram_m, ws, st))) return rc;
+  // R = Q^T T (upper triangular up to rounding; the strict lower part is cleared)
+  double* P = at<double>(ws, p.off_p);
+  double* G = at<double>(ws, p.off_g);
+  SORSVD_TRY(launch_skinny_f64(true, Tq, LP, LP, rows, Tc, LP, LP, p.gram_m.kchunk, p.gram_m.nsplit,
+                                   P, nullptr, nullptr, st));
+  SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.gram_m.nsplit, G, LP, LP, st));
+  SORSVD_TRY(launch_pack_f64(Tq, rows, (int)l, LP, Q, (int)l, st));
+  SORSVD_TRY(launch_pack_f64(G, l, (int)l, LP, R, (int)l, st));
+  SORSVD_TRY(launch_zero_lower(R, (int)l, st));
+  return SORSVD_OK;
+}
+
+int sorsvd_step_project(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
+                        const double* Q1, const double* Q2, int64_t l, double* M, void* ws,
+                        size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = step_plan(m, n, l, a_type, ws_bytes, &p);
+  if (rc) return rc;
+  if (!A || !Q1 || !Q2 || !M || lda < n) return SORSVD_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int LP = (int)p.LP;
+  const void* Xc;
+  if ((rc = pack_operand(p, Q2, n, l, ws, st, &Xc))) return rc;
+  double* W = at<double>(ws, p.off_w);
+  if ((rc = pass(p, false, A, lda, Xc, W, nullptr, ws, st))) return rc;
+  double* Q1p = at<double>(ws, p.total);
+  SORSVD_TRY(launch_pack_f64(Q1, m, (int)l, l, Q1p, LP, st));
+  double* P = at<double>(ws, p.off_p);
+  double* Mp = at<double>(ws, p.off_m);
+  SORSVD_TRY(launch_skinny_f64(true, Q1p, LP, LP, m, W, LP, LP, p.proj.kchunk, p.proj.nsplit, P,
+                                   nullptr, nullptr, st));
+  SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.proj.nsplit, Mp, LP, LP, st));
+  SORSVD_TRY(launch_pack_f64(Mp, l, (int)l, LP, M, (int)l, st));
+  return SORSVD_OK;
+}
+
+int sorsvd_step_core_svd(const double* M, int64_t l, int64_t k, double* Ut, double* s, double* Vt,
+                         int32_t max_sweeps, void* ws, size_t ws_bytes, void* stream) {
+  if (!M || !Ut || !s || !Vt || l < 1 || k < 1 || k > l) return SORSVD_EINVAL;
+  Plan p;
+  int rc = step_plan(l, l, l, SORSVD_F64, ws_bytes, &p);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  SORSVD_TRY(launch_info_init(at<void>(ws, p.off_info), st));
+  SORSVD_TRY(launch_fill(Ut, l * k, 0.0, st));
+  SORSVD_TRY(launch_fill(Vt, l * k, 0.0, st));
+  SORSVD_TRY(launch_jacobi(M, (int)l, (int)l, (int)k, max_sweeps > 0 ? max_sweeps : 40, Ut, s, Vt,
+                           (int)k, at<double>(ws, p.off_vg), at<void>(ws, p.off_info), st));
+  return SORSVD_OK;
+}
+
+int sorsvd_pass_timing(int32_t enable, int32_t capacity) {
+  PassTimer& tm = timer();
+  std::lock_guard<std::mutex> g(tm.mu);
+  if (enable && capacity < 1) return SORSVD_EINVAL;
+  for (hipEvent_t e : tm.ev) hipEventDestroy(e);
+  tm.ev.clear();
+  tm.used = 0;
+  tm.bytes = tm.flops = 0.0;
+  tm.on = false;
+  if (!enable) return SORSVD_OK;
+  tm.ev.resize(2 * (size_t)capacity, nullptr);
+  for (auto& e : tm.ev)
+    if (hipEventCreate(&e) != hipSuccess) return SORSVD_EHIP;
+  tm.on = true;
+  return SORSVD_OK;
+}
+
+int sorsvd_pass_timing_read(double* total_ms, int64_t* launches, double* bytes, double* flops) {
+  if (!total_ms || !launches || !bytes || !flops) return SORSVD_EINVAL;
+  PassTimer& tm = timer();
+  std::lock_guard<std::mutex> g(tm.mu);
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < tm.used; i += 2) {
+    if (hipEventSynchronize(tm.ev[i + 1]) != hipSuccess) return SORSVD_EHIP;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, tm.ev[i], tm.ev[i + 1]) != hipSuccess) return SORSVD_EHIP;
+    ms += t;
+  }
+  *total_ms = ms;
+  *launches = (int64_t)(tm.used / 2);
+  *bytes = tm.bytes;
+  *flops = tm.flops;
+  tm.used = 0;
+  tm.bytes = tm.flops = 0.0;
+  return SORSVD_OK;
+}
+
+const char* sorsvd_status_string(int status) {
+  switch (status) {
+    case SORSVD_OK: return "ok";
+    case SORSVD_EINVAL: return "invalid argument";
+    case SORSVD_EWORKSPACE: return "workspace too small";
+    case SORSVD_EHIP: return "HIP runtime error";
+    case SORSVD_ENOCONV: return "Jacobi sweep cap reached";
+    case SORSVD_ENONFINITE: return "non-finite input";
+    case SORSVD_EUNSUPPORTED: return "unsupported in this build";
+    default: return "unknown status";
+  }
+}
+
+const char* sorsvd_version(void) { return "sorsvd-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances (stated from the arithmetic of each path):
+  FP64 passes: sigma normwise max_j |s_j - s_j^or| / s_1^or <= 1e-10; factors
+               equal up to column sign to 1e-8 where the spectrum gap allows;
+               Q^T Q - I <= 1e-12.
+  FP32 passes: the oracle runs on the stored FP32 values (exact in FP64); the
+               passes commit a backward error of about u32 ||A|| sqrt(K), so
+               sigma normwise <= 1e-4 (observed ~1e-6).
+  Omega and other integer-determined results: bitwise.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import normal as onormal
+from oracle import sorsvd as osvd
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def normwise(s, s_ref):
+    return float(np.max(np.abs(np.asarray(s) - np.asarray(s_ref))) / np.asarray(s_ref)[0])
+
+
+def align_signs(X, X_ref):
+    d = np.sign(np.sum(X * X_ref, axis=0))
+    d[d == 0] = 1
+    return X * d[None, :]
+
+
+# ------------------------------------------------------------------ Omega
+
+@pytest.mark.parametrize("seed,rows,cols", [(1, 800, 20), (7, 37, 5), (12345, 1001, 33), (2**63 + 5, 4, 1)])
+def test_omega_bitwise_equal_to_oracle(lib, seed, rows, cols):
+    got = host(lib.philox_normal(seed, rows, cols))
+    ref = onormal.gaussian_matrix(seed, rows, cols)
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+def test_omega_streams_and_word2(lib):
+    got = host(lib.philox_normal(3, 50, 4, stream_id=9, word2=2))
+    ref = onormal.gaussian_matrix(3, 50, 4, stream=9, word2=2)
+    assert np.array_equal(got, ref)
+
+
+# ------------------------------------------------------------------ single steps
+
+@pytest.mark.parametrize("m,n,l", [(1000, 800, 20), (257, 131, 7), (64, 4000, 48), (3000, 129, 128)])
+def test_sketch_and_orbit_fp64(lib, m, n, l):
+    gen = W.rng(m + n + l)
+    A = gen.standard_normal((m, n))
+    X = gen.standard_normal((n, l))
+    Y = gen.standard_normal((m, l))
+    Ad = dev(A)
+    T = host(lib.step_sketch(Ad, dev(X)))
+    ref = osvd.sketch(A, X)
+    assert np.abs(T - ref).max() <= 1e-13 * np.abs(A).max() * np.abs(X).max() * n
+    T2 = host(lib.step_orbit(Ad, dev(Y)))
+    ref2 = osvd.orbit(A, Y)
+    assert np.abs(T2 - ref2).max() <= 1e-13 * np.abs(A).max() * np.abs(Y).max() * m
+
+
+def test_sketch_and_orbit_fp64_strided_lda(lib):
+    gen = W.rng(5)
+    big = gen.standard_normal((300, 211))
+    A = big[:, :197]
+    Ad = dev(big)[:, :197]
+    assert Ad.stride(0) == 211
+    X = gen.standard_normal((197, 19))
+    Y = gen.standard_normal((300, 19))
+    assert np.abs(host(lib.step_sketch(Ad, dev(X))) - A @ X).max() < 1e-11
+    assert np.abs(host(lib.step_orbit(Ad, dev(Y))) - A.T @ Y).max() < 1e-11
+
+
+@pytest.mark.parametrize("m,n,l", [(2000, 1500, 100), (513, 77, 9)])
+def test_sketch_and_orbit_fp32(lib, m, n, l):
+    gen = W.rng(m * 3 + l)
+    A32 = gen.standard_normal((m, n)).astype(np.float32)
+    A = A32.astype(np.float64)  # stored values, exact
+    X = gen.standard_normal((n, l))
+    Y = gen.standard_normal((m, l))
+    Ad = dev(A32, torch.float32)
+    T = host(lib.step_sketch(Ad, dev(X)))
+    ref = A @ X.astype(np.float32).astype(np.float64)
+    scale = np.sqrt(n) * np.abs(A).max() * np.abs(X).max()
+    assert np.abs(T - ref).max() <= 2e-6 * scale
+    T2 = host(lib.step_orbit(Ad, dev(Y)))
+    ref2 = A.T @ Y.astype(np.float32).astype(np.float64)
+    assert np.abs(T2 - ref2).max() <= 2e-6 * np.sqrt(m) * np.abs(A).max() * np.abs(Y).max()
+
+
+@pytest.mark.parametrize("rows,l,cond", [(1000, 20, 1e2), (20000, 100, 1e4), (333, 17, 1e7), (64, 64, 10.0)])
+def test_qr_matches_householder_with_positive_diagonal(lib, rows, l, cond):
+    gen = W.rng(rows + l)
+    U = W.haar_columns(rows, l, gen)
+    V = W.haar_columns(l, l, gen)
+    s = np.geomspace(1.0, 1.0 / cond, l)
+    T = (U * s) @ V.T
+    Q, R = lib.step_qr(dev(T))
+    Q, R = host(Q), host(R)
+    Qo, Ro = osvd.qr_pos(T)
+    assert np.abs(Q.T @ Q - np.eye(l)).max() <= 1e-13
+    assert np.abs(Q @ R - T).max() <= 1e-13 * np.abs(T).max() * cond
+    assert np.all(np.diag(R) > 0)
+    assert np.abs(np.tril(R, -1)).max() == 0.0
+    # unique thin QR: agreement limited by conditioning
+    assert np.abs(Q - Qo).max() <= 1e-15 * cond * 100 * np.sqrt(rows)
+
+
+def test_project_fp64(lib):
+    gen = W.rng(11)
+    A = gen.standard_normal((700, 500))
+    Q1 = W.haar_columns(700, 30, gen)
+    Q2 = W.haar_columns(500, 30, gen)
+    M = host(lib.step_project(dev(A), dev(Q1), dev(Q2)))
+    assert np.abs(M - osvd.projection(A, Q1, Q2)).max() < 1e-12
+
+
+@pytest.mark.parametrize("l,k", [(20, 20), (100, 100), (64, 10), (128, 128), (7, 3), (1, 1)])
+def test_core_svd_against_lapack(lib, l, k):
+    gen = W.rng(l * 7 + k)
+    Mtx = gen.standard_normal((l, l)) @ np.diag(np.geomspace(1, 1e-6, l)) @ gen.standard_normal((l, l))
+    Ut, s, Vt, info = lib.step_core_svd(dev(Mtx), k)
+    Ut, s, Vt = host(Ut), host(s), host(Vt)
+    Ur, sr, Vrt = np.linalg.svd(Mtx)
+    assert normwise(s, sr[:k]) <= 1e-13
+    assert np.all(np.diff(s) <= 0)
+    assert info["flags"] == 0 and 1 <= info["sweeps"] <= 40
+    gap_ok = np.ones(k, dtype=bool)
+    rel_gap = np.abs(np.diff(sr)) / sr[0]
+    gap_ok[:-1] &= rel_gap[:k - 1] > 1e-6
+    gap_ok[1:] &= rel_gap[:k - 1] > 1e-6
+    Ua = align_signs(Ut, Ur[:, :k])
+    Va = align_signs(Vt, Vrt[:k].T)
+    assert np.abs(Ua - Ur[:, :k])[:, gap_ok].max(initial=0) < 1e-8
+    assert np.abs(Va - Vrt[:k].T)[:, gap_ok].max(initial=0) < 1e-8
+    assert np.abs(Ut.T @ Ut - np.eye(k)).max() < 1e-12
+
+
+# ------------------------------------------------------------------ whole method
+
+def check_against_oracle(lib, A_np, A_dev, k, q, seed, l=None, tol_s=1e-10, tol_vec=1e-8):
+    opts = {} if l is None else {"l": l}
+    U, S, V, info = lib.sorsvd(A_dev, k, q=q, seed=seed, **opts)
+    U, S, V = host(U), host(S), host(V)
+    Uo, So, Vo, io = osvd.sorsvd(A_np, k, q=q, seed=seed, l=l)
+    assert normwise(S, So) <= tol_s, normwise(S, So)
+    assert np.all(np.diff(S) <= 0)
+    kk = k
+    assert np.abs(U.T @ U - np.eye(kk)).max() < 1e-11
+    assert np.abs(V.T @ V - np.eye(kk)).max() < 1e-11
+    # sign convention holds on the device result
+    idx = np.argmax(np.abs(U), axis=0)
+    assert np.all(U[idx, np.arange(kk)] > 0)
+    # factors equal up to sign where singular values are separated
+    rel_gap = np.abs(np.diff(So)) / So[0]
+    ok = np.ones(kk, dtype=bool)
+    ok[:-1] &= rel_gap > 1e-6
+    ok[1:] &= rel_gap > 1e-6
+    if ok.any():
+        assert np.abs(align_signs(U, Uo) - Uo)[:, ok].max() < tol_vec
+        assert np.abs(align_signs(V, Vo) - Vo)[:, ok].max() < tol_vec
+    assert abs(info["a_fro"] - io["a_fro"]) <= 1e-12 * io["a_fro"]
+    assert info["flags"] == 0
+    return S, So, info, io
+
+
+def test_c1_fp64_end_to_end(lib):
+    A = W.c1()
+    S, So, info, io = check_against_oracle(lib, A, dev(A), 20, 0, 1)
+    # error record (identity) against the oracle's explicit residual
+    assert abs(info["err_fro"] - io["err_fro"]) <= 1e-10 * max(io["err_fro"], 1e-6) + 1e-12
+
+
+@pytest.mark.parametrize("m,n,k,q,l", [
+    (300, 200, 10, 0, None), (300, 200, 10, 2, None), (200, 300, 12, 1, None),
+    (517, 389, 17, 1, 29), (1000, 64, 64, 0, None), (64, 1000, 5, 3, 16), (2000, 1200, 128, 1, None),
+])
+def test_fp64_shapes_and_power_steps(lib, m, n, k, q, l):
+    sigma = 1.0 / np.arange(1, min(m, n) + 1) ** 1.5
+    A, _, _ = W.spectral(m, n, sigma, m + n + k)
+    check_against_oracle(lib, A, dev(A), k, q, 3, l=l, tol_s=1e-10, tol_vec=1e-7)
+
+
+def test_exact_rank_reconstruction_fp64(lib):
+    gen = W.rng(77)
+    A = gen.standard_normal((400, 12)) @ gen.standard_normal((12, 300))
+    U, S, V, info = lib.sorsvd(dev(A), 12, q=1, seed=5)
+    U, S, V = host(U), host(S), host(V)
+    assert np.abs(A - (U * S) @ V.T).max() <= 1e-11 * np.abs(A).max()
+    assert info["err_fro"] < 1e-6
+
+
+def test_full_width_sketch_equals_svd(lib):
+    A = W.rng(8).standard_normal((90, 70))
+    _, S, _, _ = lib.sorsvd(dev(A), 70, q=0, seed=2)
+    assert normwise(host(S), np.linalg.svd(A, compute_uv=False)) <= 1e-12
+
+
+@pytest.mark.parametrize("m,n,k,q", [(2000, 1500, 100, 1), (1500, 2000, 64, 0), (777, 555, 33, 2)])
+def test_fp32_against_oracle_on_stored_values(lib, m, n, k, q):
+    sigma = 1.0 / np.arange(1, min(m, n) + 1) ** 2
+    A, _, _ = W.spectral(m, n, sigma, 2)
+    A32 = A.astype(np.float32)
+    S, So, info, io = check_against_oracle(lib, A32.astype(np.float64), dev(A32, torch.float32), k, q, 9,
+                                           tol_s=1e-4, tol_vec=1e9)
+    assert normwise(S, So) <= 1e-5  # observed accuracy margin
+
+
+def test_deterministic_repeat(lib):
+    A = dev(W.c1())
+    plan = lib.Plan(1000, 800, 20, 1, torch.float64)
+    U1, S1, V1 = [t.clone() for t in plan.run(A, seed=4)]
+    U2, S2, V2 = plan.run(A, seed=4)
+    assert torch.equal(U1, U2) and torch.equal(S1, S2) and torch.equal(V1, V2)
+
+
+def test_nonfinite_input_is_flagged(lib):
+    A = W.rng(3).standard_normal((200, 150))
+    A[17, 33] = np.nan
+    _, _, _, info = lib.sorsvd(dev(A), 5, q=0, seed=1)
+    assert info["flags"] & 2
+
+
+def test_seed_changes_draw_not_leading_values(lib):
+    # with l = k the trailing estimates depend on the draw (Th. 4: the factor
+    # (sigma_{l-p+1}/sigma_j)^(4q+4) is close to 1 for j near k); the leading
+    # ones do not, and all stay below the true values (Th. 3).
+    sigma = 0.7 ** np.arange(120)
+    A, _, _ = W.spectral(300, 120, sigma, 4)
+    _, S1, _, _ = lib.sorsvd(dev(A), 10, q=1, seed=1)
+    _, S2, _, _ = lib.sorsvd(dev(A), 10, q=1, seed=2)
+    S1, S2 = host(S1), host(S2)
+    assert not np.array_equal(S1, S2)
+    assert np.all(S1 <= sigma[:10] * (1 + 1e-12)) and np.all(S2 <= sigma[:10] * (1 + 1e-12))
+    assert normwise(S1[:5], S2[:5]) < 1e-4
