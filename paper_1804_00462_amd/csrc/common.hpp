@@ -49,6 +49,37 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// DPP lane exchange of a double within a row of 16 lanes (no LDS traffic).
+// Controls: 0xB1 = quad_perm [1,0,3,2] (lane ^ 1), 0x4E = quad_perm [2,3,0,1]
+// (lane ^ 2), 0x141 = row_half_mirror (lane i <-> 7 - i within 8),
+// 0x140 = row_mirror (lane i <-> 15 - i within 16).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi2, lo2);
+}
+
+// All-reduce sums over aligned groups of 4, 8 or 16 lanes by DPP. Each step
+// adds two partial sums that are identical up to operand order, and IEEE
+// addition is commutative, so every lane of a group ends with the same bits.
+__device__ inline double sum4(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  return v;
+}
+__device__ inline double sum8(double v) {
+  v = sum4(v);
+  v += dpp_f64<0x141>(v);
+  return v;
+}
+__device__ inline double sum16(double v) {
+  v = sum8(v);
+  v += dpp_f64<0x140>(v);
+  return v;
+}
+
 // Sum over aligned groups of `width` lanes (width a power of two <= 64).
 __device__ inline double group_sum(double v, int width) {
   for (int off = width >> 1; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);

@@ -46,7 +46,7 @@ template <> struct Traits<double> {
 template <> struct Traits<float> {
   using acc_t = float;
   using accv = f32x4;
-  static constexpr int VK = 16;
+  static constexpr int VK = 8;
   __device__ static inline accv mfma(float a, float b, accv c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -61,11 +61,11 @@ template <> struct VecLoad<double, 8> {
     for (int i = 0; i < 4; ++i) { double2 v = q[i]; a[2 * i] = v.x; a[2 * i + 1] = v.y; }
   }
 };
-template <> struct VecLoad<float, 16> {
-  __device__ static inline void run(const float* p, float (&a)[16]) {
+template <> struct VecLoad<float, 8> {
+  __device__ static inline void run(const float* p, float (&a)[8]) {
     const float4* q = reinterpret_cast<const float4*>(p);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
       float4 v = q[i];
       a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
     }
@@ -77,7 +77,7 @@ __device__ inline int xcd_remap(int b, int nb) {
 }
 
 template <typename T, bool TRANS, int RT, int CT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
          const T* __restrict__ X, int64_t ldx, int64_t kchunk, int tiles, int nsplit,
          int vec_ok, typename Traits<T>::acc_t* P, double* __restrict__ normp,
@@ -195,19 +195,25 @@ k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
   }
 }
 
-// out[r][c] = sum_{s = 0..nsplit-1} P[s][r][c] in FP64, in order of s, for c < ncols.
+// out[r][c] = sum_{s = 0..nsplit-1} P[s][r][c] in FP64, for c < ncols, in a
+// fixed order: lane t of an 8-lane group sums s = t, t + 8, ... in turn, then
+// the 8 lane sums are combined by a fixed DPP tree.
 template <typename Acc>
 __global__ void __launch_bounds__(256)
 k_reduce(const Acc* __restrict__ P, int64_t OUT, int LP, int nsplit, double* __restrict__ out,
          int64_t ldo, int ncols) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= OUT * LP) return;
-  const int64_t r = idx / LP;
-  const int c = (int)(idx % LP);
-  if (c >= ncols) return;
+  const int64_t total = OUT * LP;
+  const int64_t idx = (int64_t)blockIdx.x * 32 + threadIdx.x / 8;
+  const int ln = threadIdx.x % 8;
   double acc = 0.0;
-  for (int s = 0; s < nsplit; ++s) acc += (double)P[(int64_t)s * OUT * LP + idx];
-  out[r * ldo + c] = acc;
+  if (idx < total)
+    for (int s = ln; s < nsplit; s += 8) acc += (double)P[(int64_t)s * total + idx];
+  acc = sum8(acc);
+  if (idx < total && ln == 0) {
+    const int64_t r = idx / LP;
+    const int c = (int)(idx % LP);
+    if (c < ncols) out[r * ldo + c] = acc;
+  }
 }
 
 // dst[r][c] = src[r][c] for c < cols, 0 for cols <= c < LP (row-major, element type T).
@@ -261,22 +267,37 @@ static hipError_t launch_ct(int CT, const T* A, int64_t lda, int64_t OUT, int64_
   return hipGetLastError();
 }
 
-// Rows of output per workgroup for each element type.
-template <typename T> constexpr int rt_of() { return 1; }
-template <> constexpr int rt_of<float>() { return 2; }
+// Output rows per workgroup (64 * RT): FP32 always uses RT = 2; FP64 uses
+// RT = 2 only when one workgroup then covers all output rows (the l x l Gram
+// and projection products), so the tall operand is read once.
+template <typename T> constexpr bool has_rt1() { return true; }
+template <> constexpr bool has_rt1<float>() { return false; }
 
-template <typename T>
-hipError_t launch_skinny(bool trans, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
-                         int64_t ldx, int LP, int64_t kchunk, int nsplit,
-                         typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
-                         hipStream_t st) {
-  constexpr int RT = rt_of<T>();
+int skinny_rt(int a_type, int64_t OUT) { return (a_type == 1 || OUT <= 128) ? 2 : 1; }
+
+template <typename T, int RT>
+static hipError_t launch_rt(bool trans, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
+                            int64_t ldx, int LP, int64_t kchunk, int nsplit,
+                            typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
+                            hipStream_t st) {
   const int tiles = (int)ceil_div(OUT, 64 * RT);
   if (tiles == 0 || nsplit == 0) return hipSuccess;
   const int vec_ok = ((lda * (int64_t)sizeof(T)) % 16 == 0) && (((uintptr_t)A) % 16 == 0);
   if (trans)
     return launch_ct<T, true, RT>(LP / kTile, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, st);
   return launch_ct<T, false, RT>(LP / kTile, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, st);
+}
+
+template <typename T>
+hipError_t launch_skinny(bool trans, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
+                         int64_t ldx, int LP, int64_t kchunk, int nsplit,
+                         typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
+                         hipStream_t st) {
+  if constexpr (has_rt1<T>()) {
+    if (OUT > 128)
+      return launch_rt<T, 1>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, st);
+  }
+  return launch_rt<T, 2>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, st);
 }
 
 hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
@@ -291,14 +312,14 @@ hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OU
   return launch_skinny<float>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, st);
 }
 
-int skinny_rows_per_block(int a_type) { return a_type == 1 ? 128 : 64; }
-int skinny_step(int a_type) { return a_type == 0 ? 32 : (a_type == 1 ? 64 : 128); }
+int skinny_rows_per_block(int a_type, int64_t OUT) { return 64 * skinny_rt(a_type, OUT); }
+int skinny_step(int a_type) { return a_type == 0 ? 32 : (a_type == 1 ? 32 : 128); }
 
 hipError_t launch_reduce_f64(const double* P, int64_t OUT, int LP, int nsplit, double* out,
                              int64_t ldo, int ncols, hipStream_t st) {
   const int64_t total = OUT * LP;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_reduce<double>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_reduce<double>), dim3((unsigned)ceil_div(total, 32)), dim3(256), 0, st,
                      P, OUT, LP, nsplit, out, ldo, ncols);
   return hipGetLastError();
 }
@@ -307,7 +328,7 @@ hipError_t launch_reduce_f32(const float* P, int64_t OUT, int LP, int nsplit, do
                              int64_t ldo, int ncols, hipStream_t st) {
   const int64_t total = OUT * LP;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_reduce<float>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_reduce<float>), dim3((unsigned)ceil_div(total, 32)), dim3(256), 0, st,
                      P, OUT, LP, nsplit, out, ldo, ncols);
   return hipGetLastError();
 }

@@ -35,7 +35,7 @@ hipError_t launch_pack_f32(const double* src, int64_t rows, int cols, int64_t ld
                            int LP, hipStream_t st);
 hipError_t launch_cast_f32(const double* Q, int64_t n_elem, float* Xc, hipStream_t st);
 hipError_t launch_zero_lower(double* R, int l, hipStream_t st);
-int skinny_rows_per_block(int a_type);
+int skinny_rows_per_block(int a_type, int64_t OUT);
 int skinny_step(int a_type);
 // philox.hip
 hipError_t launch_omega_f64_colmajor(uint64_t seed, uint64_t stream_id, uint64_t word2,
@@ -45,8 +45,8 @@ hipError_t launch_omega_rowmajor_f64(uint64_t seed, int64_t rows, int64_t cols, 
 hipError_t launch_omega_rowmajor_f32(uint64_t seed, int64_t rows, int64_t cols, float* out,
                                      int64_t ldx, hipStream_t st);
 // small.hip
-hipError_t launch_chol_inv(const double* G, int LP, int l, int64_t rows, int shifted, int may_skip,
-                           double* Rinv, int* skip, void* info, hipStream_t st);
+hipError_t launch_chol_inv(const double* G, int LP, int l, int64_t rows, int mode, double* Rinv,
+                           int* skip3, void* info, hipStream_t st);
 hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, double* Ut,
                          double* sv, double* Vt, int ldk, double* Vg, void* info, hipStream_t st);
 hipError_t launch_signfix(const double* U64, int64_t m, const double* V64, int64_t n, int ld, int k,
@@ -69,16 +69,17 @@ struct Split {
 };
 
 // Split of a contraction of length K for OUT output rows: enough workgroups
-// to fill 256 CUs several times over, each split at least 8 steps long, and
-// partial sums no larger than 1/8 of the bytes of the streamed operand.
+// to fill 256 CUs several times over, each split at least `min_steps` steps
+// long, and partial sums no larger than 1/`part_div` of the bytes of the
+// streamed operand.
 Split choose_split(int64_t OUT, int64_t K, int rows_per_block, int KS, int LP, int es_a,
-                   int acc_bytes, int forced) {
+                   int acc_bytes, int forced, int min_steps = 8, int part_div = 8) {
   Split sp;
   if (K <= 0) { sp.kchunk = KS; sp.nsplit = 1; return sp; }
   const int64_t tiles = std::max<int64_t>(1, ceil_div(OUT, rows_per_block));
   int64_t s = std::max<int64_t>(1, ceil_div(2048, tiles));
-  s = std::min<int64_t>(s, std::max<int64_t>(1, K / (8 * KS)));
-  s = std::min<int64_t>(s, std::max<int64_t>(1, (K * es_a) / (8 * (int64_t)LP * acc_bytes)));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, K / ((int64_t)min_steps * KS)));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, (K * es_a) / ((int64_t)part_div * LP * acc_bytes)));
   if (forced > 0) s = forced;
   sp.kchunk = round_up(ceil_div(K, s), KS);
   sp.nsplit = (int)ceil_div(K, sp.kchunk);
@@ -129,15 +130,18 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->es = elem_size(a_type);
   p->max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
   const int forced = o ? o->split : 0;
-  const int rpb = skinny_rows_per_block(a_type), ks = skinny_step(a_type);
+  const int ks = skinny_step(a_type);
   const int acc = a_type == SORSVD_F64 ? 8 : 4;
-  p->nn = choose_split(m, n, rpb, ks, (int)LP, p->es, acc, forced);
-  p->tn = choose_split(n, m, rpb, ks, (int)LP, p->es, acc, forced);
-  const int rpb64 = skinny_rows_per_block(SORSVD_F64), ks64 = skinny_step(SORSVD_F64);
-  p->gram_m = choose_split(LP, m, rpb64, ks64, (int)LP, 8, 8, 0);
-  p->gram_n = choose_split(LP, n, rpb64, ks64, (int)LP, 8, 8, 0);
+  p->nn = choose_split(m, n, skinny_rows_per_block(a_type, m), ks, (int)LP, p->es, acc, forced);
+  p->tn = choose_split(n, m, skinny_rows_per_block(a_type, n), ks, (int)LP, p->es, acc, forced);
+  // l x l products over a tall FP64 operand: many short splits (the partial
+  // sums are small next to the operand)
+  const int ks64 = skinny_step(SORSVD_F64);
+  const int rpbg = skinny_rows_per_block(SORSVD_F64, LP);
+  p->gram_m = choose_split(LP, m, rpbg, ks64, (int)LP, 8, 8, 0, 4, 2);
+  p->gram_n = choose_split(LP, n, rpbg, ks64, (int)LP, 8, 8, 0, 4, 2);
   p->proj = p->gram_m;
-  p->nn_blocks = (int)(ceil_div(m, rpb) * p->nn.nsplit);
+  p->nn_blocks = (int)(ceil_div(m, skinny_rows_per_block(a_type, m)) * p->nn.nsplit);
 
   Layout L;
   p->off_info = L.take(256);
@@ -177,24 +181,23 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
 
 template <typename T> T* at(void* ws, size_t off) { return reinterpret_cast<T*>((char*)ws + off); }
 
-// Cholesky QR of T (rows x LP, FP64, padding columns zero) in place:
-// shifted step, plain step, and a third step that only runs when the second
-// left T measurably non-orthonormal.
+// Cholesky QR of T (rows x LP, FP64, padding columns zero) in place: two
+// steps T <- T R^{-1}, the first shifted when T is ill-conditioned, and then
+// a third step whose kernels return at once unless the first was shifted.
 int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void* ws, hipStream_t st) {
   double* P = at<double>(ws, p.off_p);
   double* G = at<double>(ws, p.off_g);
   double* Rinv = at<double>(ws, p.off_rinv);
-  int* skip = at<int>(ws, p.off_skip);
+  int* skip3 = at<int>(ws, p.off_skip);
   void* info = at<void>(ws, p.off_info);
   const int LP = (int)p.LP;
   for (int it = 0; it < 3; ++it) {
+    const int* skip = it == 2 ? skip3 : nullptr;
     SORSVD_TRY(launch_skinny_f64(true, T, LP, LP, rows, T, LP, LP, gram.kchunk, gram.nsplit, P,
-                                     nullptr, nullptr, st));
+                                 nullptr, skip, st));
     SORSVD_TRY(launch_reduce_f64(P, LP, LP, gram.nsplit, G, LP, LP, st));
-    SORSVD_TRY(launch_chol_inv(G, LP, (int)p.l, rows, it == 0 ? 1 : 0, it == 2 ? 1 : 0, Rinv, skip,
-                               info, st));
-    SORSVD_TRY(launch_skinny_f64(false, T, LP, rows, LP, Rinv, LP, LP, LP, 1, T, nullptr,
-                                     it == 2 ? skip : nullptr, st));
+    SORSVD_TRY(launch_chol_inv(G, LP, (int)p.l, rows, it, Rinv, skip3, info, st));
+    SORSVD_TRY(launch_skinny_f64(false, T, LP, rows, LP, Rinv, LP, LP, LP, 1, T, nullptr, skip, st));
   }
   return SORSVD_OK;
 }
