@@ -6,12 +6,16 @@ Omega, 2q+3 passes over A, the Cholesky QRs of the sketches, the core
 projection, the core SVD, the lift with the sign convention and the error
 record), enqueued through the C ABI.
 
-Default workload: the plain FP32 configuration, A = U diag(j^-2) V^T with
-m = n = 20000, Haar U and V (seed 2), k = l = 100, q = 1, Omega seed 1.
+Headline workload (the `value` of the JSON line): the plain FP32
+configuration, A = U diag(j^-2) V^T with m = n = 20000, Haar U and V (seed 2),
+k = l = 100, q = 1, Omega seed 1. The same run also measures, under "extra",
+the BF16-stored configuration (200000 x 4000, sigma_j = 0.9^j plus noise of
+s.d. 1e-6, k = 64, q = 1, refinement pass) and the small FP64 configuration
+(1000 x 800, k = 20, q = 0).
 
 Printed: ONE JSON line with throughput (SOR-SVDs/s), the algorithmic HBM rate
 of the passes, the roofline of the dominant kernel (the pass kernel over A,
-timed per launch with HIP events recorded by the library on the same stream
+timed per launch with HIP events that the library records on the same stream
 inside the timed region) and the CPU oracle timed on a bounded sample.
 """
 import argparse
@@ -21,15 +25,20 @@ import sys
 import time
 
 WORKLOADS = {
-    # name: (m, n, k, q, dtype name, description)
-    "c2": (20000, 20000, 100, 1, "float32",
+    # name: (m, n, k, q, dtype name, refine, description)
+    "c2": (20000, 20000, 100, 1, "float32", 0,
            "plain SOR-SVD FP32: A = U diag(j^-2) V^T, 20000 x 20000, Haar U, V (seed 2), k = 100, q = 1"),
-    "c1": (1000, 800, 20, 0, "float64",
+    "c3": (200000, 4000, 64, 1, "bfloat16", 1,
+           "BF16-stored A = U diag(0.9^j) V^T + N(0, (1e-6)^2), 200000 x 4000, k = 64, q = 1, "
+           "BF16 MFMA passes, hi+lo refinement projection, FP64 QR and core SVD"),
+    "c1": (1000, 800, 20, 0, "float64", 0,
            "plain SOR-SVD FP64: A = X Y^T + 1e-3 E (1000 x 800, seed 0), k = 20, q = 0, Omega seed 1"),
 }
 
-PEAK = {"float32": ("mfma", 157.3, "TFLOP/s"), "float64": ("mfma", 78.6, "TFLOP/s")}
-HBM_PEAK_GBS = 8000.0
+# dominant-kernel roofline: (bound, peak, unit)
+PEAK = {"float32": ("mfma", 157.3, "TFLOP/s"), "float64": ("mfma", 78.6, "TFLOP/s"),
+        "bfloat16": ("hbm", 8000.0, "GB/s")}
+DTYPE_TAG = {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}
 
 
 def log(msg):
@@ -40,6 +49,8 @@ def make_input(name, torch):
     import workloads as W
     if name == "c2":
         return W.c2_torch("cuda")
+    if name == "c3":
+        return W.c3_torch("cuda")
     if name == "c1":
         return torch.as_tensor(W.c1()).cuda()
     raise ValueError(name)
@@ -69,12 +80,69 @@ def cpu_baseline(A_host, k, q, seed, budget_s=20.0, max_reps=5):
                       f"(median {med:.3f} s; includes the oracle's explicit residual)"}
 
 
+def run_workload(name, steps, warmup, torch, P):
+    m, n, k, q, dname, refine, desc = WORKLOADS[name]
+    seed = 1
+    log(f"[bench] building input {name}: {desc}")
+    t0 = time.perf_counter()
+    A = make_input(name, torch)
+    torch.cuda.synchronize()
+    log(f"[bench] input ready in {time.perf_counter() - t0:.1f} s; dtype {A.dtype}")
+    plan = P.Plan(m, n, k, q, A.dtype, refine=refine)
+    es = A.element_size()
+
+    for _ in range(warmup):
+        plan.run(A, seed)
+    torch.cuda.synchronize()
+
+    passes = 2 * q + 3
+    P.pass_timing(True, capacity=steps * passes + 8)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        plan.run(A, seed)
+    ev1.record()
+    torch.cuda.synchronize()
+    gpu_ms = ev0.elapsed_time(ev1)
+    kern_ms, launches, kbytes, kflops = P.pass_timing_read()
+    P.pass_timing(False)
+    info = plan.info()
+    ms_per_step = gpu_ms / steps
+    log(f"[bench] {name}: {steps} timed steps, {ms_per_step:.3f} ms/step; pass kernel "
+        f"{kern_ms / launches * 1e3:.1f} us/launch")
+
+    bound, peak, unit = PEAK[dname]
+    avg_launch_s = kern_ms / launches / 1e3
+    per_launch_flops = kflops / launches
+    per_launch_bytes = kbytes / launches
+    if unit == "GB/s":
+        achieved = per_launch_bytes / avg_launch_s / 1e9
+    else:
+        achieved = per_launch_flops / avg_launch_s / 1e12
+    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "pass kernel over A (sketch, orbit, projection products)",
+                "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "per_launch": {"flops": per_launch_flops, "bytes": per_launch_bytes},
+                "hbm_gbps_of_that_kernel": round(per_launch_bytes / avg_launch_s / 1e9, 1),
+                "tflops_of_that_kernel": round(per_launch_flops / avg_launch_s / 1e12, 2)}
+    res = {"workload": desc, "m": m, "n": n, "k": k, "l": k, "q": q, "dtype": DTYPE_TAG[dname],
+           "passes_over_A": passes, "ms_per_step": round(ms_per_step, 4),
+           "value": round(1000.0 / ms_per_step, 3), "unit": "SOR-SVD/s",
+           "hbm_gbps_algorithmic": round(float(m) * n * es * passes / (ms_per_step / 1e3) / 1e9, 1),
+           "roofline": roofline, "err_fro": info["err_fro"], "jacobi_sweeps": info["sweeps"],
+           "flags": info["flags"]}
+    return res, A
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--extra", default="c3,c1", help="comma-separated extra workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -85,76 +153,48 @@ def main():
     import torch
     import paper_1804_00462_amd as P
 
-    m, n, k, q, dname, desc = WORKLOADS[args.workload]
-    seed = 1
-    log(f"[bench] building input {args.workload}: {desc}")
-    t0 = time.perf_counter()
-    A = make_input(args.workload, torch)
-    torch.cuda.synchronize()
-    log(f"[bench] input ready in {time.perf_counter() - t0:.1f} s; dtype {A.dtype}")
-    plan = P.Plan(m, n, k, q, A.dtype)
-    es = A.element_size()
+    head, A = run_workload(args.workload, args.steps, args.warmup, torch, P)
+    m, n, k, q = head["m"], head["n"], head["k"], head["q"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        A_host = A.double().cpu().numpy()
+        del A
+        cpu = cpu_baseline(A_host, k, q, 1)
+        del A_host
+    else:
+        del A
+    torch.cuda.empty_cache()
 
-    for i in range(args.warmup):
-        plan.run(A, seed)
-    torch.cuda.synchronize()
-    log(f"[bench] {args.warmup} warmup steps done")
-
-    passes = 2 * q + 3
-    P.pass_timing(True, capacity=args.steps * passes + 8)
-    torch.cuda.synchronize()
-    start = time.perf_counter()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for i in range(args.steps):
-        plan.run(A, seed)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - start
-    gpu_ms = ev0.elapsed_time(ev1)
-    kern_ms, launches, kbytes, kflops = P.pass_timing_read()
-    P.pass_timing(False)
-    log(f"[bench] {args.steps} timed steps: {gpu_ms:.2f} ms (wall {wall * 1e3:.2f} ms), "
-        f"pass kernel {launches} launches, {kern_ms:.2f} ms")
-
-    info = plan.info()
-    ms_per_step = gpu_ms / args.steps
-    value = 1000.0 / ms_per_step
-    a_bytes_step = float(m) * n * es * passes
-    bound, peak, unit = PEAK[dname]
-    avg_launch_s = kern_ms / launches / 1e3
-    achieved = (kflops / launches) / avg_launch_s / 1e12
-    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "k_skinny (pass over A)", "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "algorithmic_per_launch": {"flops": kflops / launches, "bytes": kbytes / launches},
-                "hbm_gbps_of_that_kernel": round((kbytes / launches) / avg_launch_s / 1e9, 1)}
+    extra = {}
+    for name in [x for x in args.extra.split(",") if x and x != args.workload]:
+        res, A = run_workload(name, args.steps, args.warmup, torch, P)
+        del A
+        torch.cuda.empty_cache()
+        extra[name] = res
 
     out = {
         "metric": "rank-k SOR-SVDs/sec + HBM GB/s; BF16+learned vs FP32 plain at ≤1e-3 rel err",
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "SOR-SVD/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"float32": "f32", "float64": "f64"}[dname],
+        "dtype": head["dtype"],
         "data": "synthetic",
-        "config": {"workload": desc, "m": m, "n": n, "k": k, "l": k, "q": q, "passes_over_A": passes},
-        "hbm_gbps_algorithmic": round(a_bytes_step / (ms_per_step / 1e3) / 1e9, 1),
-        "roofline": roofline,
-        "err_fro": info["err_fro"],
-        "jacobi_sweeps": info["sweeps"],
+        "config": {"workload": head["workload"], "m": m, "n": n, "k": k, "l": head["l"], "q": q,
+                   "passes_over_A": head["passes_over_A"]},
+        "hbm_gbps_algorithmic": head["hbm_gbps_algorithmic"],
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+        "err_fro": head["err_fro"],
+        "jacobi_sweeps": head["jacobi_sweeps"],
+        "extra": extra,
     }
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        A_host = A.double().cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(A_host, k, q, seed)
-    else:
-        out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
     return 0
 

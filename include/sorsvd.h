@@ -58,7 +58,7 @@ typedef struct sorsvd_opts {
   int32_t refine;     /* BF16 A only: 1 = projection pass with Q2 split hi+lo */
   int32_t residual;   /* 1 = also compute ||A - U S V^T||_F explicitly (one more pass) */
   int32_t split;      /* split of the contraction in the passes; 0 = automatic */
-  int32_t reserved0;
+  int32_t tile;       /* BF16 passes: 64*tile rows (columns) of A per workgroup, tile in {1,2,4}; 0 = automatic */
   int32_t reserved1;
 } sorsvd_opts;
 

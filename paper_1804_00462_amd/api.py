@@ -42,8 +42,8 @@ def _check_matrix(A):
         raise ValueError("A must be row-major (unit column stride)")
 
 
-def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0):
-    return Opts(l=l, max_sweeps=max_sweeps, refine=refine, residual=residual, split=split)
+def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0):
+    return Opts(l=l, max_sweeps=max_sweeps, refine=refine, residual=residual, split=split, tile=tile)
 
 
 def workspace_bytes(m, n, k, q, dtype_or_code, **opts):

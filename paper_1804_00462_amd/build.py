@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "libsorsvd.so")
 SOURCES = {
     "philox.hip": ["-ffp-contract=off"],
     "gemm.hip": [],
+    "gemm_bf16.hip": [],
     "small.hip": [],
     "sorsvd.hip": [],
 }

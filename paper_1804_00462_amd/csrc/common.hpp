@@ -42,6 +42,13 @@ __device__ inline bf16_t f64_to_bf16(double d) {
   return f32_to_bf16(f);
 }
 
+// 16-byte streaming load that bypasses cache retention (A is read once per pass).
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ inline uint4 load_stream16(const void* p) {
+  const u32x4_t t = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+  return uint4{t.x, t.y, t.z, t.w};
+}
+
 // Sum over a full wavefront (64 lanes); every lane gets the total.
 __device__ inline double wave_sum(double v) {
 #pragma unroll

@@ -21,10 +21,12 @@ namespace sor {
 // gemm.hip
 hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
                              const double* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
-                             double* P, double* normp, const int* skipflag, hipStream_t st);
+                             double* P, double* normp, const int* skipflag, hipStream_t st,
+                             double* Tout = nullptr);
 hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OUT, int64_t K,
                              const float* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
-                             float* P, double* normp, const int* skipflag, hipStream_t st);
+                             float* P, double* normp, const int* skipflag, hipStream_t st,
+                             double* Tout = nullptr);
 hipError_t launch_reduce_f64(const double* P, int64_t OUT, int LP, int nsplit, double* out,
                              int64_t ldo, int ncols, hipStream_t st);
 hipError_t launch_reduce_f32(const float* P, int64_t OUT, int LP, int nsplit, double* out,
@@ -37,7 +39,18 @@ hipError_t launch_cast_f32(const double* Q, int64_t n_elem, float* Xc, hipStream
 hipError_t launch_zero_lower(double* R, int l, hipStream_t st);
 int skinny_rows_per_block(int a_type, int64_t OUT);
 int skinny_step(int a_type);
+// gemm_bf16.hip
+hipError_t launch_bf16_pass(bool trans, const bf16_t* A, int64_t lda, int64_t OUT, int64_t K,
+                            const bf16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit,
+                            float* P, double* normp, double* Tout, int fold, int rt, hipStream_t st);
+int bf16_step(bool trans, int rt);
+hipError_t launch_cast_bf16_t(const double* Q, int64_t rows, int LP, int64_t ldt, int permute,
+                              int with_lo, bf16_t* QT, hipStream_t st);
+hipError_t launch_reduce_fold(const float* P, int64_t OUT, int LP2, int nsplit, double* out,
+                              int64_t ldo, int ncols, hipStream_t st);
 // philox.hip
+hipError_t launch_omega_bf16_t(uint64_t seed, int64_t rows, int64_t cols, bf16_t* out,
+                               int64_t ldx, hipStream_t st);
 hipError_t launch_omega_f64_colmajor(uint64_t seed, uint64_t stream_id, uint64_t word2,
                                      int64_t rows, int64_t cols, double* out, hipStream_t st);
 hipError_t launch_omega_rowmajor_f64(uint64_t seed, int64_t rows, int64_t cols, double* out,
@@ -101,6 +114,10 @@ struct Plan {
   int q;
   int es;
   int max_sweeps;
+  int refine;     // BF16: projection pass with Q2 = hi + lo
+  int64_t ldt;    // BF16: leading dimension of the transposed skinny operands
+  int rt_nn, rt_tn, rt_proj;  // BF16: rows (NN) / columns (TN) of A per workgroup = 64 rt
+  Split projb;    // BF16: split of the refinement projection pass
   Split nn, tn, gram_m, gram_n, proj;
   int nn_blocks;
   size_t off_info, off_xc, off_t1, off_t2, off_w, off_u64, off_v64, off_p, off_normp;
@@ -116,10 +133,7 @@ size_t partial_bytes(int64_t OUT, int64_t LP, const Split& s, int acc) {
 
 int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const sorsvd_opts* o,
               Plan* p) {
-  if (a_type != SORSVD_F64 && a_type != SORSVD_F32) {
-    if (a_type == SORSVD_BF16) return SORSVD_EUNSUPPORTED;
-    return SORSVD_EINVAL;
-  }
+  if (a_type != SORSVD_F64 && a_type != SORSVD_F32 && a_type != SORSVD_BF16) return SORSVD_EINVAL;
   if (m < 1 || n < 1 || k < 1 || q < 0) return SORSVD_EINVAL;
   const int64_t l = (o && o->l > 0) ? o->l : k;
   if (k > l || l > std::min(m, n)) return SORSVD_EINVAL;
@@ -129,11 +143,24 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->a_type = a_type; p->m = m; p->n = n; p->k = k; p->l = l; p->LP = LP; p->KP = KP; p->q = q;
   p->es = elem_size(a_type);
   p->max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
+  p->refine = (a_type == SORSVD_BF16 && o && o->refine) ? 1 : 0;
+  p->ldt = round_up(std::max(m, n), 128) + 128;  // room for the last step's over-read
   const int forced = o ? o->split : 0;
   const int ks = skinny_step(a_type);
   const int acc = a_type == SORSVD_F64 ? 8 : 4;
-  p->nn = choose_split(m, n, skinny_rows_per_block(a_type, m), ks, (int)LP, p->es, acc, forced);
-  p->tn = choose_split(n, m, skinny_rows_per_block(a_type, n), ks, (int)LP, p->es, acc, forced);
+  // BF16 tiles: wide workgroups amortise the re-read of the skinny operand
+  // (an opts override serves tuning sweeps)
+  const int tile_opt = o ? o->tile : 0;
+  p->rt_nn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
+  p->rt_tn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
+  p->rt_proj = tile_opt ? std::min(tile_opt, p->refine && LP > 32 ? 2 : 4) : (p->refine ? (LP <= 32 ? 4 : 2) : p->rt_nn);
+  const int rpb_m = a_type == SORSVD_BF16 ? 64 * p->rt_nn : skinny_rows_per_block(a_type, m);
+  const int rpb_n = a_type == SORSVD_BF16 ? 64 * p->rt_tn : skinny_rows_per_block(a_type, n);
+  const int ks_nn = a_type == SORSVD_BF16 ? bf16_step(false, p->rt_nn) : ks;
+  const int ks_tn = a_type == SORSVD_BF16 ? bf16_step(true, p->rt_tn) : ks;
+  p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced);
+  p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced);
+  p->projb = choose_split(m, n, 64 * p->rt_proj, 128, (int)LP * (p->refine ? 2 : 1), p->es, acc, forced);
   // l x l products over a tall FP64 operand: many short splits (the partial
   // sums are small next to the operand)
   const int ks64 = skinny_step(SORSVD_F64);
@@ -141,12 +168,13 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->gram_m = choose_split(LP, m, rpbg, ks64, (int)LP, 8, 8, 0, 4, 2);
   p->gram_n = choose_split(LP, n, rpbg, ks64, (int)LP, 8, 8, 0, 4, 2);
   p->proj = p->gram_m;
-  p->nn_blocks = (int)(ceil_div(m, skinny_rows_per_block(a_type, m)) * p->nn.nsplit);
+  p->nn_blocks = (int)(ceil_div(m, rpb_m) * p->nn.nsplit);
+  if (a_type == SORSVD_BF16 && p->rt_nn != 1 && p->rt_nn != 2 && p->rt_nn != 4) return SORSVD_EINVAL;
 
   Layout L;
   p->off_info = L.take(256);
   const int64_t rows = std::max(m, n);
-  p->off_xc = L.take((size_t)rows * LP * p->es);
+  p->off_xc = a_type == SORSVD_BF16 ? L.take((size_t)2 * LP * p->ldt * 2) : L.take((size_t)rows * LP * p->es);
   p->off_t1 = L.take((size_t)m * LP * 8);
   p->off_t2 = L.take((size_t)n * LP * 8);
   p->off_w = L.take((size_t)m * LP * 8);
@@ -154,6 +182,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->off_v64 = L.take((size_t)n * KP * 8);
   size_t pb = 0;
   pb = std::max(pb, partial_bytes(m, LP, p->nn, acc));
+  pb = std::max(pb, partial_bytes(m, (p->refine ? 2 : 1) * LP, p->projb, acc));
   pb = std::max(pb, partial_bytes(n, LP, p->tn, acc));
   pb = std::max(pb, partial_bytes(LP, LP, p->gram_m, 8));
   pb = std::max(pb, partial_bytes(LP, LP, p->gram_n, 8));
@@ -219,7 +248,7 @@ PassTimer& timer() {
 // T (OUT x LP, FP64) = A X   (trans = false, X in compute type, K = n)
 //                    = A^T Y (trans = true,  Y in compute type, K = m)
 int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, double* T,
-         double* normp, void* ws, hipStream_t st) {
+         double* normp, void* ws, hipStream_t st, bool fold = false, bool proj = false) {
   const int LP = (int)p.LP;
   const int64_t OUT = trans ? p.n : p.m;
   const int64_t K = trans ? p.m : p.n;
@@ -240,23 +269,48 @@ int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, 
   if (p.a_type == SORSVD_F64) {
     double* P = at<double>(ws, p.off_p);
     SORSVD_TRY(launch_skinny_f64(trans, (const double*)A, lda, OUT, K, (const double*)Xc, LP, LP,
-                                     sp.kchunk, sp.nsplit, P, normp, nullptr, st));
+                                 sp.kchunk, sp.nsplit, P, normp, nullptr, st, T));
     if (e1) SORSVD_TRY(hipEventRecord(e1, st));
-    SORSVD_TRY(launch_reduce_f64(P, OUT, LP, sp.nsplit, T, LP, LP, st));
-  } else {
+    if (sp.nsplit > 1) SORSVD_TRY(launch_reduce_f64(P, OUT, LP, sp.nsplit, T, LP, LP, st));
+  } else if (p.a_type == SORSVD_F32) {
     float* P = at<float>(ws, p.off_p);
     SORSVD_TRY(launch_skinny_f32(trans, (const float*)A, lda, OUT, K, (const float*)Xc, LP, LP,
-                                    sp.kchunk, sp.nsplit, P, normp, nullptr, st));
+                                 sp.kchunk, sp.nsplit, P, normp, nullptr, st, T));
     if (e1) SORSVD_TRY(hipEventRecord(e1, st));
-    SORSVD_TRY(launch_reduce_f32(P, OUT, LP, sp.nsplit, T, LP, LP, st));
+    if (sp.nsplit > 1) SORSVD_TRY(launch_reduce_f32(P, OUT, LP, sp.nsplit, T, LP, LP, st));
+  } else {
+    // BF16: Xc is the transposed operand; `fold` = the refinement pass with
+    // [Q2 hi | Q2 lo] (2 LP columns) whose two halves are summed.
+    float* P = at<float>(ws, p.off_p);
+    const int LPw = fold ? 2 * LP : LP;
+    const Split& spb = proj ? p.projb : sp;
+    const int rt = proj ? p.rt_proj : (trans ? p.rt_tn : p.rt_nn);
+    SORSVD_TRY(launch_bf16_pass(trans, (const bf16_t*)A, lda, OUT, K, (const bf16_t*)Xc, p.ldt, LPw,
+                                spb.kchunk, spb.nsplit, P, normp, T, fold ? 1 : 0, rt, st));
+    if (e1) SORSVD_TRY(hipEventRecord(e1, st));
+    if (spb.nsplit > 1) {  // with one split the kernel wrote T itself
+      if (fold)
+        SORSVD_TRY(launch_reduce_fold(P, OUT, LPw, spb.nsplit, T, LP, LP, st));
+      else
+        SORSVD_TRY(launch_reduce_f32(P, OUT, LP, spb.nsplit, T, LP, LP, st));
+    }
   }
   return SORSVD_OK;
 }
 
 // Skinny operand of the next pass: Q (rows x LP, FP64) in A's compute type.
-const void* as_operand(const Plan& p, const double* Q, int64_t rows, void* ws, hipStream_t st, int* rc) {
+// BF16: transposed, with the contraction permutation for the orbit (TN)
+// pass, and with the low part appended for the refinement pass.
+const void* as_operand(const Plan& p, const double* Q, int64_t rows, void* ws, hipStream_t st, int* rc,
+                       bool for_tn = false, bool with_lo = false) {
   *rc = SORSVD_OK;
   if (p.a_type == SORSVD_F64) return Q;
+  if (p.a_type == SORSVD_BF16) {
+    bf16_t* XT = at<bf16_t>(ws, p.off_xc);
+    if (launch_cast_bf16_t(Q, rows, (int)p.LP, p.ldt, for_tn ? 1 : 0, with_lo ? 1 : 0, XT, st) != hipSuccess)
+      *rc = SORSVD_EHIP;
+    return XT;
+  }
   float* Xc = at<float>(ws, p.off_xc);
   if (launch_cast_f32(Q, rows * p.LP, Xc, st) != hipSuccess) *rc = SORSVD_EHIP;
   return Xc;
@@ -275,17 +329,22 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
 
   // Omega, n x l (Alg. 3 / Alg. 4 step 1), straight into the compute-type operand.
   void* Xc = at<void>(ws, p.off_xc);
-  SORSVD_TRY(launch_fill((double*)Xc, (p.n * LP * p.es + 7) / 8, 0.0, st));
-  if (p.a_type == SORSVD_F64)
+  if (p.a_type == SORSVD_F64) {
+    SORSVD_TRY(launch_fill((double*)Xc, p.n * LP, 0.0, st));
     SORSVD_TRY(launch_omega_rowmajor_f64(seed, p.n, p.l, (double*)Xc, LP, st));
-  else
+  } else if (p.a_type == SORSVD_F32) {
+    SORSVD_TRY(launch_fill((double*)Xc, (p.n * LP * 4 + 7) / 8, 0.0, st));
     SORSVD_TRY(launch_omega_rowmajor_f32(seed, p.n, p.l, (float*)Xc, LP, st));
+  } else {
+    SORSVD_TRY(launch_fill((double*)Xc, LP * p.ldt * 2 / 8, 0.0, st));
+    SORSVD_TRY(launch_omega_bf16_t(seed, p.n, p.l, (bf16_t*)Xc, p.ldt, st));
+  }
 
   // T1 = A Omega (eq. T1), with ||A||_F^2 accumulated on the way; Q1 = qr(T1).
   if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
   if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
   // T2 = A^T Q1 (eq. AT1; the span of A^T T1 by Lemma 1); Q2 = qr(T2).
-  const void* Y = as_operand(p, T1, p.m, ws, st, &rc);
+  const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true);
   if (rc) return rc;
   if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
   if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st))) return rc;
@@ -295,15 +354,15 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
     if (rc) return rc;
     if ((rc = pass(p, false, A, lda, X, T1, nullptr, ws, st))) return rc;
     if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
-    Y = as_operand(p, T1, p.m, ws, st, &rc);
+    Y = as_operand(p, T1, p.m, ws, st, &rc, true);
     if (rc) return rc;
     if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
     if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st))) return rc;
   }
   // M = Q1^T (A Q2) (eq. M): W = A Q2 in the pass kernel, then the FP64 Q1^T W.
-  const void* X = as_operand(p, T2, p.n, ws, st, &rc);
+  const void* X = as_operand(p, T2, p.n, ws, st, &rc, false, p.refine != 0);
   if (rc) return rc;
-  if ((rc = pass(p, false, A, lda, X, W, nullptr, ws, st))) return rc;
+  if ((rc = pass(p, false, A, lda, X, W, nullptr, ws, st, p.refine != 0, true))) return rc;
   double* P = at<double>(ws, p.off_p);
   double* M = at<double>(ws, p.off_m);
   SORSVD_TRY(launch_skinny_f64(true, T1, LP, LP, p.m, W, LP, LP, p.proj.kchunk, p.proj.nsplit, P,
@@ -378,6 +437,7 @@ size_t sorsvd_step_workspace_bytes(int64_t m, int64_t n, int64_t l, int32_t a_ty
   sorsvd_opts o;
   std::memset(&o, 0, sizeof(o));
   o.l = l;
+  o.refine = a_type == SORSVD_BF16 ? 1 : 0;
   Plan p;
   if (make_plan(m, n, l, 0, a_type, &o, &p) != SORSVD_OK) return 0;
   // room for packed FP64 copies of two skinny operands (QR input copy, projection)
@@ -388,6 +448,7 @@ static int step_plan(int64_t m, int64_t n, int64_t l, int32_t a_type, size_t ws_
   sorsvd_opts o;
   std::memset(&o, 0, sizeof(o));
   o.l = l;
+  o.refine = a_type == SORSVD_BF16 ? 1 : 0;  // the BF16 projection step uses the hi + lo split
   const int rc = make_plan(m, n, l, 0, a_type, &o, p);
   if (rc != SORSVD_OK) return rc;
   if (ws_bytes < sorsvd_step_workspace_bytes(m, n, l, a_type)) return SORSVD_EWORKSPACE;
@@ -395,7 +456,14 @@ static int step_plan(int64_t m, int64_t n, int64_t l, int32_t a_type, size_t ws_
 }
 
 static int pack_operand(const Plan& p, const double* src, int64_t rows, int64_t l, void* ws,
-                        hipStream_t st, const void** out) {
+                        hipStream_t st, const void** out, bool for_tn = false, bool with_lo = false) {
+  if (p.a_type == SORSVD_BF16) {
+    double* tmp = at<double>(ws, p.total + round_up(std::max(p.m, p.n) * p.LP * 8, kAlign));
+    SORSVD_TRY(launch_pack_f64(src, rows, (int)l, l, tmp, (int)p.LP, st));
+    int rc;
+    *out = as_operand(p, tmp, rows, ws, st, &rc, for_tn, with_lo);
+    return rc;
+  }
   if (p.a_type == SORSVD_F64) {
     double* d = at<double>(ws, p.off_xc);
     SORSVD_TRY(launch_pack_f64(src, rows, (int)l, l, d, (int)p.LP, st));
@@ -431,7 +499,7 @@ int sorsvd_step_orbit(const void* A, int64_t lda, int32_t a_type, int64_t m, int
   if (!A || !Y || !T || lda < n) return SORSVD_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const void* Yc;
-  if ((rc = pack_operand(p, Y, m, l, ws, st, &Yc))) return rc;
+  if ((rc = pack_operand(p, Y, m, l, ws, st, &Yc, true))) return rc;
   double* Tp = at<double>(ws, p.off_t2);
   if ((rc = pass(p, true, A, lda, Yc, Tp, nullptr, ws, st))) return rc;
   SORSVD_TRY(launch_pack_f64(Tp, n, (int)l, p.LP, T, (int)l, st));
@@ -474,9 +542,10 @@ int sorsvd_step_project(const void* A, int64_t lda, int32_t a_type, int64_t m, i
   hipStream_t st = (hipStream_t)stream;
   const int LP = (int)p.LP;
   const void* Xc;
-  if ((rc = pack_operand(p, Q2, n, l, ws, st, &Xc))) return rc;
+  const bool fold = p.a_type == SORSVD_BF16;
+  if ((rc = pack_operand(p, Q2, n, l, ws, st, &Xc, false, fold))) return rc;
   double* W = at<double>(ws, p.off_w);
-  if ((rc = pass(p, false, A, lda, Xc, W, nullptr, ws, st))) return rc;
+  if ((rc = pass(p, false, A, lda, Xc, W, nullptr, ws, st, fold, true))) return rc;
   double* Q1p = at<double>(ws, p.total);
   SORSVD_TRY(launch_pack_f64(Q1, m, (int)l, l, Q1p, LP, st));
   double* P = at<double>(ws, p.off_p);
