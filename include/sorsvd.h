@@ -68,7 +68,10 @@ typedef struct sorsvd_info {
   double err_fro;          /* sqrt(||A||_F^2 - sum_j s_j^2) / ||A||_F (Th. 2 split) */
   double err_fro_explicit; /* ||A - U S V^T||_F / ||A||_F if opts.residual, else -1 */
   int32_t sweeps;          /* Jacobi sweeps taken by the core SVD */
-  int32_t flags;           /* bit 0: sweep cap reached; bit 1: non-finite entry in A */
+  int32_t flags;           /* bit 0: sweep cap reached; bit 1: non-finite entry in A;
+                              bit 2: a Cholesky-QR pivot stayed <= 0 after the shift, so its
+                              column was dropped from Q (sketch columns dependent to
+                              rounding: a sketch condition number near 1/u) */
 } sorsvd_info;
 
 /* Workspace size in bytes for sorsvd() with the same arguments. Returns 0 for
@@ -155,6 +158,88 @@ int sorsvd_step_core_svd(const double* M, int64_t l, int64_t k, double* Ut, doub
  */
 int sorsvd_pass_timing(int32_t enable, int32_t capacity);
 int sorsvd_pass_timing_read(double* total_ms, int64_t* launches, double* bytes, double* flops);
+
+/*
+ * Batched SOR-SVD: many independent problems of uneven sizes (each one is
+ * Alg. 3 for q = 0, Alg. 4 for q > 0, exactly as sorsvd() computes it), run
+ * together so that every step of the method is one launch over the whole batch.
+ *
+ * One problem. A (m x n, row-major, lda >= n, batch dtype) is read only; U
+ * (m x k, ldu >= k), S (k) and V (n x k, ldv >= k) are FP64 outputs with the
+ * same meaning, sign convention and Omega draw (key (seed, 0)) as sorsvd().
+ * l = sketch width (0 means k; k <= l <= min(m, n), l rounded up to a multiple
+ * of 16 must be <= 128). q >= 0 power steps, per problem.
+ */
+typedef struct sorsvd_problem {
+  const void* A;
+  int64_t lda, m, n;
+  int32_t k, l, q, reserved;
+  uint64_t seed;
+  double* U;
+  int64_t ldu;
+  double* S;
+  double* V;
+  int64_t ldv;
+} sorsvd_problem;
+
+/* Host-side plan of a batch (opaque; created and freed by the library). */
+typedef struct sorsvd_batch sorsvd_batch;
+
+/*
+ * sorsvd_batch_create - validate `count` problems (1..65535) and build the
+ * plan: per-step work lists ordered largest item first, the workspace layout
+ * and the default launch configuration (or the one stored for this batch
+ * shape in the tuning cache file named by the environment variable
+ * SORSVD_TUNE_CACHE). a_type: SORSVD_F32 or SORSVD_F64 (BF16 ->
+ * SORSVD_EUNSUPPORTED). opts: NULL, or only max_sweeps set (other fields
+ * non-zero -> SORSVD_EUNSUPPORTED). On success *out holds the plan and
+ * *ws_bytes the device workspace it needs. The problem array is copied; the
+ * device buffers it points to must stay valid while the plan is used.
+ */
+int sorsvd_batch_create(int32_t count, const sorsvd_problem* problems, int32_t a_type,
+                        const sorsvd_opts* opts, sorsvd_batch** out, size_t* ws_bytes);
+
+/* Bind the plan to a device workspace (256-byte aligned, >= *ws_bytes) and
+ * copy the problem table and work lists into it; waits for `stream`. Must be
+ * called once before run, autotune or graph; again after a new workspace. */
+int sorsvd_batch_upload(sorsvd_batch* b, void* workspace, size_t ws_bytes, void* stream);
+
+/* Enqueue the whole batch on `stream`: Omega, 2q + 3 passes over each A with
+ * their Cholesky QRs, projection, core SVDs, lifts, sign convention and the
+ * result records. Problems with smaller q sit out the later power steps. */
+int sorsvd_batch_run(const sorsvd_batch* b, void* workspace, void* stream);
+
+/* Launch configuration of the three pass kinds (sketch, orbit, projection):
+ * config[2i] = tile height in units of 64 rows (1 or 2), config[2i + 1] =
+ * persistent workgroups. Results are bitwise the same for every configuration. */
+int sorsvd_batch_get_config(const sorsvd_batch* b, int32_t* config /* host, 6 */);
+int sorsvd_batch_set_config(sorsvd_batch* b, const int32_t* config /* host, 6 */);
+
+/* Time each pass kind over tile heights {1, 2} x grids {256 .. 4096} with HIP
+ * events on `stream` (synchronous), keep the fastest, append it to the tuning
+ * cache file if SORSVD_TUNE_CACHE is set, write it to config_out (host, 6
+ * entries, may be NULL), and leave the results of a complete run behind. */
+int sorsvd_batch_autotune(sorsvd_batch* b, void* workspace, void* stream, int32_t* config_out);
+
+/* Copy the `count` result records (same fields as sorsvd_info) into host
+ * memory `out`, after waiting for `stream`. */
+int sorsvd_batch_read_info(const sorsvd_batch* b, sorsvd_info* out, void* stream);
+
+/* Capture the launch sequence of sorsvd_batch_run (no memsets, no allocations)
+ * in a HIP graph on a library-created stream and instantiate it: *graph_exec
+ * receives a hipGraphExec_t. Replays with sorsvd_graph_launch recompute the
+ * batch from the current contents of the A buffers; free with
+ * sorsvd_graph_destroy. The plan's configuration at capture time is frozen
+ * into the graph. Pass timing (sorsvd_pass_timing) does not see graph replays. */
+int sorsvd_batch_graph(const sorsvd_batch* b, void* workspace, void** graph_exec);
+int sorsvd_graph_launch(void* graph_exec, void* stream);
+int sorsvd_graph_destroy(void* graph_exec);
+
+/* Number of problems of a plan (0 for NULL). */
+int32_t sorsvd_batch_count(const sorsvd_batch* b);
+
+/* Free a plan (NULL is allowed). Does not touch device memory. */
+void sorsvd_batch_destroy(sorsvd_batch* b);
 
 /* Human-readable text of a status code (static storage). */
 const char* sorsvd_status_string(int status);

@@ -31,6 +31,12 @@ class Opts(ctypes.Structure):
                 ("split", c_i32), ("tile", c_i32), ("reserved1", c_i32)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("A", c_vp), ("lda", c_i64), ("m", c_i64), ("n", c_i64), ("k", c_i32), ("l", c_i32),
+                ("q", c_i32), ("reserved", c_i32), ("seed", c_u64), ("U", c_vp), ("ldu", c_i64),
+                ("S", c_vp), ("V", c_vp), ("ldv", c_i64)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("a_fro", c_dbl), ("err_fro", c_dbl), ("err_fro_explicit", c_dbl),
                 ("sweeps", c_i32), ("flags", c_i32)]
@@ -50,6 +56,18 @@ _SIGS = {
     "sorsvd_step_core_svd": (c_i32, [c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_i32, c_vp, c_sz, c_vp]),
     "sorsvd_pass_timing": (c_i32, [c_i32, c_i32]),
     "sorsvd_pass_timing_read": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "sorsvd_batch_create": (c_i32, [c_i32, c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "sorsvd_batch_upload": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
+    "sorsvd_batch_run": (c_i32, [c_vp, c_vp, c_vp]),
+    "sorsvd_batch_get_config": (c_i32, [c_vp, c_vp]),
+    "sorsvd_batch_set_config": (c_i32, [c_vp, c_vp]),
+    "sorsvd_batch_autotune": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "sorsvd_batch_read_info": (c_i32, [c_vp, c_vp, c_vp]),
+    "sorsvd_batch_graph": (c_i32, [c_vp, c_vp, c_vp]),
+    "sorsvd_graph_launch": (c_i32, [c_vp, c_vp]),
+    "sorsvd_graph_destroy": (c_i32, [c_vp]),
+    "sorsvd_batch_count": (c_i32, [c_vp]),
+    "sorsvd_batch_destroy": (None, [c_vp]),
     "sorsvd_status_string": (ctypes.c_char_p, [c_i32]),
     "sorsvd_version": (ctypes.c_char_p, []),
 }

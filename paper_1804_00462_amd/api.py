@@ -6,7 +6,7 @@ computation runs in the library's kernels. Names follow the C entry points.
 import ctypes
 
 from . import _lib
-from ._lib import SORSVD_BF16, SORSVD_F32, SORSVD_F64, Info, Opts, check
+from ._lib import SORSVD_BF16, SORSVD_F32, SORSVD_F64, Info, Opts, Problem, check
 
 
 def _torch():
@@ -198,3 +198,110 @@ def pass_timing_read():
     check(_lib.load().sorsvd_pass_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
                                               ctypes.byref(f)), "sorsvd_pass_timing_read")
     return ms.value, n.value, b.value, f.value
+
+
+class Batch:
+    """A batch of independent SOR-SVDs of uneven sizes, run as one launch per step.
+
+    mats: list of 2-D row-major device tensors of one dtype (float32 or float64);
+    ks, qs, seeds, ls: per-problem rank, power steps, Omega seed and sketch width
+    (l = 0 means l = k). Allocates the FP64 outputs U_i (m_i x k_i), S_i, V_i
+    (n_i x k_i) and the workspace once; run() recomputes them from the current
+    contents of mats.
+    """
+
+    def __init__(self, mats, ks, qs, seeds, ls=None, max_sweeps=0):
+        torch = _torch()
+        if not mats:
+            raise ValueError("empty batch")
+        code = dtype_code(mats[0].dtype)
+        count = len(mats)
+        ls = ls if ls is not None else [0] * count
+        if not (len(ks) == len(qs) == len(seeds) == len(ls) == count):
+            raise ValueError("per-problem lists must match the number of matrices")
+        self.mats = list(mats)
+        self.U, self.S, self.V = [], [], []
+        probs = (Problem * count)()
+        for i, A in enumerate(mats):
+            _check_matrix(A)
+            if dtype_code(A.dtype) != code:
+                raise ValueError("all matrices of a batch share one dtype")
+            m, n = A.shape
+            k = int(ks[i])
+            U = torch.empty(m, k, dtype=torch.float64, device=A.device)
+            S = torch.empty(k, dtype=torch.float64, device=A.device)
+            V = torch.empty(n, k, dtype=torch.float64, device=A.device)
+            self.U.append(U)
+            self.S.append(S)
+            self.V.append(V)
+            probs[i] = Problem(A=A.data_ptr(), lda=A.stride(0), m=m, n=n, k=k, l=int(ls[i]), q=int(qs[i]),
+                               reserved=0, seed=int(seeds[i]), U=U.data_ptr(), ldu=k, S=S.data_ptr(),
+                               V=V.data_ptr(), ldv=k)
+        self._probs = probs
+        lib = _lib.load()
+        handle = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t()
+        opts = make_opts(max_sweeps=max_sweeps)
+        check(lib.sorsvd_batch_create(count, probs, code, ctypes.byref(opts), ctypes.byref(handle),
+                                      ctypes.byref(nbytes)), "sorsvd_batch_create")
+        self._h = handle
+        self.ws_bytes = nbytes.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=mats[0].device)
+        check(lib.sorsvd_batch_upload(self._h, _ptr(self.ws), self.ws_bytes, _stream()), "sorsvd_batch_upload")
+        self._graph = None
+
+    def __len__(self):
+        return len(self.mats)
+
+    def run(self, stream=None):
+        check(_lib.load().sorsvd_batch_run(self._h, _ptr(self.ws), _stream(stream)), "sorsvd_batch_run")
+
+    def config(self):
+        c = (ctypes.c_int32 * 6)()
+        check(_lib.load().sorsvd_batch_get_config(self._h, c), "sorsvd_batch_get_config")
+        return list(c)
+
+    def set_config(self, cfg):
+        c = (ctypes.c_int32 * 6)(*[int(x) for x in cfg])
+        check(_lib.load().sorsvd_batch_set_config(self._h, c), "sorsvd_batch_set_config")
+
+    def autotune(self, stream=None):
+        c = (ctypes.c_int32 * 6)()
+        check(_lib.load().sorsvd_batch_autotune(self._h, _ptr(self.ws), _stream(stream), c),
+              "sorsvd_batch_autotune")
+        return list(c)
+
+    def info(self, stream=None):
+        out = (Info * len(self.mats))()
+        check(_lib.load().sorsvd_batch_read_info(self._h, out, _stream(stream)), "sorsvd_batch_read_info")
+        return [{"a_fro": o.a_fro, "err_fro": o.err_fro, "err_fro_explicit": o.err_fro_explicit,
+                 "sweeps": o.sweeps, "flags": o.flags} for o in out]
+
+    def capture(self):
+        """Capture the run's launch sequence in a HIP graph (replaces an earlier one)."""
+        self.release_graph()
+        g = ctypes.c_void_p()
+        check(_lib.load().sorsvd_batch_graph(self._h, _ptr(self.ws), ctypes.byref(g)), "sorsvd_batch_graph")
+        self._graph = g
+
+    def replay(self, stream=None):
+        if self._graph is None:
+            raise RuntimeError("no graph captured")
+        check(_lib.load().sorsvd_graph_launch(self._graph, _stream(stream)), "sorsvd_graph_launch")
+
+    def release_graph(self):
+        if self._graph is not None:
+            _lib.load().sorsvd_graph_destroy(self._graph)
+            self._graph = None
+
+    def close(self):
+        self.release_graph()
+        if self._h:
+            _lib.load().sorsvd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -24,6 +24,7 @@ SOURCES = {
     "gemm_bf16.hip": [],
     "small.hip": [],
     "sorsvd.hip": [],
+    "batched.hip": [],
 }
 
 COMMON = [

@@ -11,6 +11,15 @@ typedef uint16_t bf16_t;  // storage type of BF16 data (raw bits)
 
 namespace sor {
 
+// One Gaussian draw of a batch (Omega of one problem): rows x cols draws of
+// key (seed, 0) written row-major into `out` (leading dimension ldx) in the
+// compute type of that batch.
+struct OmegaJob {
+  uint64_t seed;
+  int64_t rows, cols, ldx;
+  void* out;
+};
+
 constexpr int kWave = 64;
 constexpr int kTile = 16;  // MFMA output tile edge
 

@@ -137,6 +137,26 @@ __global__ void __launch_bounds__(256) k_omega(uint64_t seed, uint64_t stream, u
   }
 }
 
+// Batched Omega: blockIdx.y selects the job; one thread per Philox block,
+// element (i, j) of job y is draw i + j * rows of key (seed_y, 0), exactly as
+// in the single-problem kernel (mode 1).
+template <typename T>
+__global__ void __launch_bounds__(256) k_omega_batch(const OmegaJob* __restrict__ jobs) {
+  const OmegaJob J = jobs[blockIdx.y];
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t count = J.rows * J.cols;
+  if (4 * b >= count) return;
+  double z[4];
+  normals4((uint64_t)b, 0, J.seed, 0, z);
+  T* out = reinterpret_cast<T*>(J.out);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t e = 4 * b + t;
+    if (e >= count) break;
+    out[(e % J.rows) * J.ldx + e / J.rows] = (T)z[t];
+  }
+}
+
 }  // namespace
 
 // Host launchers ------------------------------------------------------------
@@ -171,6 +191,18 @@ hipError_t launch_omega_bf16_t(uint64_t seed, int64_t rows, int64_t cols, bf16_t
   int64_t blocks = ceil_div(ceil_div(rows * cols, 4), 256);
   hipLaunchKernelGGL((k_omega<2, bf16_t>), dim3((unsigned)blocks), dim3(256), 0, st,
                      seed, (uint64_t)0, (uint64_t)0, rows, cols, out, ldx);
+  return hipGetLastError();
+}
+
+// jobs: device array of njobs descriptors; max_count = the largest rows * cols.
+hipError_t launch_omega_batch(const OmegaJob* jobs, int njobs, int64_t max_count, int f32,
+                              hipStream_t st) {
+  const int64_t blocks = ceil_div(ceil_div(max_count, 4), 256);
+  if (blocks == 0 || njobs == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_omega_batch<float>, dim3((unsigned)blocks, (unsigned)njobs), dim3(256), 0, st, jobs);
+  else
+    hipLaunchKernelGGL(k_omega_batch<double>, dim3((unsigned)blocks, (unsigned)njobs), dim3(256), 0, st, jobs);
   return hipGetLastError();
 }
 

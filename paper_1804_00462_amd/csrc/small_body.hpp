@@ -1,0 +1,274 @@
+// Device bodies of the small dense FP64 steps of the SOR-SVD path, each run
+// by one workgroup of kSmallThreads threads (shared by the single-problem
+// kernels and the batched kernels, which run one workgroup per problem):
+//   * Cholesky factor and inverse of the l x l Gram matrix (the QR step of
+//     Alg. 3 / Alg. 4 as Cholesky QR: T = Q R with R^T R = T^T T),
+//   * the core SVD of M = Q1^T A Q2 by one-sided (Hestenes) Jacobi rotations
+//     with a round-robin pair order (rank-k truncation of Alg. 3 step 6).
+#pragma once
+#include "common.hpp"
+
+namespace sor {
+
+constexpr int kSmallThreads = 1024;
+
+// Flags stored in the int32 `flags` word of the result record.
+constexpr int kFlagNoConv = 1;
+constexpr int kFlagNonFinite = 2;
+constexpr int kFlagQrBreakdown = 4;
+
+struct DevInfo {  // mirrors sorsvd_info
+  double a_fro;
+  double err_fro;
+  double err_fro_explicit;
+  int32_t sweeps;
+  int32_t flags;
+};
+
+// ---------------------------------------------------------------------------
+// Cholesky QR step. G (ld LP) holds T^T T for the current T (rows x l).
+// Computes R with R^T R = G (+ shift I) and writes Rinv = R^{-1} into an
+// LP x LP zero-padded buffer; the caller then forms T <- T Rinv.
+// Every step first factors G unshifted; if a pivot shows column j nearly in
+// the span of the earlier ones (Schur pivot < 1e-13 G_jj, i.e. a condition
+// number beyond ~3e6, or a breakdown), it factors again with the shift
+// c u tr(G), c = 11 (rows l + l (l + 1)), u = 2^-53 (shifted Cholesky QR,
+// Fukaya et al.), and asks for the third step through *skip3 = 0.
+//   mode 0 (first step): sets *skip3 = 1 when no shift was needed;
+//   mode 1 (second step): leaves *skip3 alone unless it shifted;
+//   mode 2 (third step): does nothing when *skip3 is set.
+// Two unshifted steps leave T orthonormal to rounding when its condition
+// number is below ~1e7; the shifted step brings any T with condition number
+// up to ~1/u into that range. A pivot that is still not positive after the
+// shift (a column dependent to rounding, or NaN) drops its column: it
+// eliminates nothing and its column of R^{-1} is zero (flag bit 2).
+constexpr int kCholRetry = 1;
+
+// LDL^T elimination of the l x l SPD matrix held in the upper triangle of S,
+// carrying W = L^{-1} (unit lower triangular) in the strict lower triangle:
+// step j subtracts f_a = S[j][a] / S[j][j] times row j from every row a > j,
+// on the trailing upper triangle of S and on W's columns 0..j. The pivots
+// d_j stay on the diagonal. One barrier per step. Then R = D^{1/2} L^T and
+// R^{-1} = L^{-T} D^{-1/2} = W^T D^{-1/2}.
+__device__ inline int ldl_inverse(double* S, int l, double shift, const double* d0, bool check,
+                                  DevInfo* info) {
+  const int tid = threadIdx.x;
+  const int tx = tid % 32, ty = tid / 32;
+  if (shift != 0.0)
+    for (int i = tid; i < l; i += kSmallThreads) S[i * l + i] += shift;
+  __syncthreads();
+  for (int j = 0; j < l; ++j) {
+    const double d = S[j * l + j];
+    if (check && !(d > 1e-13 * d0[j])) return kCholRetry;  // every thread sees the same d
+    double dinv = 1.0 / d;
+    if (!(d > 0.0)) {  // not positive after the shift (or NaN): drop column j
+      if (tid == 0) atomicOr(&info->flags, kFlagQrBreakdown);
+      dinv = 0.0;
+    }
+    const double* rowj = S + j * l;
+    for (int a = j + 1 + ty; a < l; a += kSmallThreads / 32) {
+      const double f = rowj[a] * dinv;
+      double* rowa = S + a * l;
+#pragma unroll 4
+      for (int c = a + tx; c < l; c += 32) rowa[c] -= f * rowj[c];
+#pragma unroll 4
+      for (int c = tx; c <= j; c += 32) rowa[c] -= f * (c == j ? 1.0 : rowj[c]);
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// G is given as nparts partial sums (stride pstride elements), added here in
+// order; sm: LDS of (l * l + l) doubles.
+__device__ inline void chol_inv_body(const double* __restrict__ G, int nparts, int64_t pstride, int LP,
+                                     int l, int64_t rows, int mode, double* __restrict__ Rinv,
+                                     int* __restrict__ skip3, DevInfo* __restrict__ info, double* sm) {
+  if (mode == 2 && *skip3) return;
+  double* S = sm;               // l x l: upper = S, strict lower = W
+  double* d0 = sm + l * l;      // l: diagonal of G
+  const int tid = threadIdx.x;
+  auto gval = [&](int r, int c) {
+    double v = 0.0;
+    for (int p = 0; p < nparts; ++p) v += G[p * pstride + r * LP + c];
+    return v;
+  };
+
+  auto load = [&]() {
+    for (int i = tid; i < l * l; i += kSmallThreads) {
+      const int r = i / l, c = i % l;
+      S[i] = (c >= r) ? gval(r, c) : 0.0;
+    }
+  };
+  load();
+  for (int i = tid; i < l; i += kSmallThreads) d0[i] = gval(i, i);
+  __syncthreads();
+  bool shifted = false;
+  if (ldl_inverse(S, l, 0.0, d0, true, info) == kCholRetry) {
+    __syncthreads();
+    double tr = 0.0;
+    for (int i = 0; i < l; ++i) tr += d0[i];
+    const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 0x1p-53 * tr;
+    load();
+    __syncthreads();
+    ldl_inverse(S, l, shift, d0, false, info);
+    shifted = true;
+  }
+  if (tid == 0) {
+    if (shifted) *skip3 = 0;
+    else if (mode == 0) *skip3 = 1;
+  }
+  __syncthreads();
+  // R^{-1}[r][c] = W[c][r] / sqrt(d_c) for r < c, 1 / sqrt(d_c) on the diagonal;
+  // a dropped column (d_c not positive) is zero.
+  for (int i = tid; i < LP * LP; i += kSmallThreads) {
+    const int r = i / LP, c = i % LP;
+    double v = 0.0;
+    if (r < l && c < l && c >= r) {
+      const double d = S[c * l + c];
+      if (d > 0.0) {
+        const double isd = 1.0 / sqrt(d);
+        v = (r == c) ? isd : S[c * l + r] * isd;
+      }
+    }
+    Rinv[i] = v;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi SVD of an l x l matrix M (ld LP), FP64, l <= 128.
+// Columns are rotated in pairs (p, q): with alpha = |m_p|^2, beta = |m_q|^2,
+// gamma = m_p . m_q, zeta = (beta - alpha) / (2 gamma),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = c t,
+// m_p <- c m_p - s m_q, m_q <- s m_p + c m_q (and the same on V), which makes
+// the pair orthogonal. A sweep visits every pair once in round-robin order
+// (l' - 1 steps of l'/2 disjoint pairs, l' = l rounded up to even); sweeps
+// stop when no pair had |gamma| > tol sqrt(alpha beta), tol = sqrt(l) 2^-52,
+// or after max_sweeps. Then sigma_j = |m_j|, U~_j = m_j / sigma_j, V~_j = v_j,
+// sorted descending; the first k are written (Ut, Vt: l x k, ld ldk; s: k).
+// Each pair is handled by a group of 16 lanes (one DPP row); each lane keeps
+// its (at most 8) rows of the two columns in registers for the step, and the
+// dot products are reduced with DPP. M lives in LDS; V lives in LDS when both
+// fit, else in the global scratch `Vg` (l x l).
+constexpr int kJacRows = 8;  // rows per lane: l <= 16 * kJacRows
+
+// Min is given as nparts partial sums (stride pstride elements), added in order.
+template <bool V_LDS>
+__device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, int64_t pstride, int LP,
+                                   int l, int k, int max_sweeps, double* __restrict__ Ut,
+                                   double* __restrict__ sv, double* __restrict__ Vt, int ldk,
+                                   double* __restrict__ Vg, DevInfo* __restrict__ info, double* sm) {
+  double* Mc = sm;                             // column-major: Mc[c * l + r]
+  double* Vc;                                  // column-major
+  if constexpr (V_LDS) Vc = sm + l * l; else Vc = Vg;
+  double* sig = sm + (V_LDS ? 2 * l * l : l * l);  // l
+  __shared__ int s_rot;
+  const int tid = threadIdx.x;
+  const int grp = tid / 16, gl = tid % 16;
+  constexpr int ngroups = kSmallThreads / 16;
+
+  for (int i = tid; i < l * l; i += kSmallThreads) {
+    const int c = i / l, r = i % l;
+    double mv = 0.0;
+    for (int p = 0; p < nparts; ++p) mv += Min[p * pstride + r * LP + c];
+    Mc[i] = mv;
+    Vc[i] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  const int lp = (l + 1) & ~1;
+  const int npairs = lp / 2;
+  const double tol2 = (double)l * 0x1p-104;  // (sqrt(l) 2^-52)^2
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int step = 0; step < lp - 1; ++step) {
+      for (int pr = grp; pr < npairs; pr += ngroups) {
+        // round-robin: position 0 fixed, positions 1..lp-1 rotate
+        auto player = [&](int pos) {
+          if (pos == 0) return 0;
+          int x = pos - 1 + step;
+          if (x >= lp - 1) x -= lp - 1;
+          return 1 + x;
+        };
+        int p = player(pr), q = player(lp - 1 - pr);
+        if (p >= l || q >= l) continue;
+        if (p > q) { int t = p; p = q; q = t; }
+        double* mp = Mc + p * l;
+        double* mq = Mc + q * l;
+        double* vp = Vc + p * l;
+        double* vq = Vc + q * l;
+        double x[kJacRows], y[kJacRows], vx[kJacRows], vy[kJacRows];
+#pragma unroll
+        for (int i = 0; i < kJacRows; ++i) {
+          // clamped, unconditional loads (all issued before the first use)
+          const int r = gl + 16 * i;
+          const int rc = r < l ? r : l - 1;
+          const double a = mp[rc], b = mq[rc], va = vp[rc], vb = vq[rc];
+          const bool in = r < l;
+          x[i] = in ? a : 0.0;
+          y[i] = in ? b : 0.0;
+          vx[i] = in ? va : 0.0;
+          vy[i] = in ? vb : 0.0;
+        }
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int i = 0; i < kJacRows; ++i) {
+          al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i];
+        }
+        al = sum16(al); be = sum16(be); ga = sum16(ga);
+        if (!(ga * ga > tol2 * (al * be))) continue;  // orthogonal enough (or zero column)
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double s = c * t;
+#pragma unroll
+        for (int i = 0; i < kJacRows; ++i) {
+          const int r = gl + 16 * i;
+          if (r < l) {
+            mp[r] = c * x[i] - s * y[i];
+            mq[r] = s * x[i] + c * y[i];
+            vp[r] = c * vx[i] - s * vy[i];
+            vq[r] = s * vx[i] + c * vy[i];
+          }
+        }
+        if (gl == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (!rot) break;
+  }
+  if (tid == 0) {
+    info->sweeps = sweep + (sweep < max_sweeps ? 1 : 0);
+    if (sweep >= max_sweeps) atomicOr(&info->flags, kFlagNoConv);
+  }
+  // column norms -> singular values
+  for (int c = grp; c < l; c += ngroups) {
+    double a = 0.0;
+    for (int r = gl; r < l; r += 16) a += Mc[c * l + r] * Mc[c * l + r];
+    a = sum16(a);
+    if (gl == 0) sig[c] = sqrt(a);
+  }
+  __syncthreads();
+  // rank of each column in descending order (ties: lower index first)
+  for (int c = grp; c < l; c += ngroups) {
+    const double sc = sig[c];
+    int rank = 0;
+    for (int i = gl; i < l; i += 16) rank += (sig[i] > sc || (sig[i] == sc && i < c)) ? 1 : 0;
+    for (int off = 8; off >= 1; off >>= 1) rank += __shfl_xor(rank, off, kWave);
+    if (rank < k) {
+      const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+      for (int r = gl; r < l; r += 16) {
+        Ut[r * ldk + rank] = Mc[c * l + r] * inv;
+        Vt[r * ldk + rank] = Vc[c * l + r];
+      }
+      if (gl == 0) sv[rank] = sc;
+    }
+  }
+}
+
+}  // namespace sor

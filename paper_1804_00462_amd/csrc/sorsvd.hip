@@ -390,6 +390,22 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
 }
 
 }  // namespace
+
+// Timing hook for launches of pass kernels outside this file (the batched
+// engine): records the start event and returns the end event to record after
+// the launch, or null when timing is off or its capacity is used up.
+hipEvent_t pass_timer_begin(hipStream_t st, double bytes, double flops) {
+  PassTimer& tm = timer();
+  std::lock_guard<std::mutex> g(tm.mu);
+  if (!tm.on || tm.used + 2 > tm.ev.size()) return nullptr;
+  hipEvent_t e0 = tm.ev[tm.used], e1 = tm.ev[tm.used + 1];
+  tm.used += 2;
+  tm.bytes += bytes;
+  tm.flops += flops;
+  if (hipEventRecord(e0, st) != hipSuccess) return nullptr;
+  return e1;
+}
+
 }  // namespace sor
 
 using namespace sor;

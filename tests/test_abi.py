@@ -76,3 +76,85 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError):
         _lib.load()
+
+
+def _problems(specs):
+    """sorsvd_problem array with placeholder (never dereferenced) device pointers."""
+    arr = (_lib.Problem * len(specs))()
+    for i, (m, n, k, l, q) in enumerate(specs):
+        arr[i] = _lib.Problem(A=256, lda=n, m=m, n=n, k=k, l=l, q=q, reserved=0, seed=i, U=512, ldu=k,
+                              S=768, V=1024, ldv=k)
+    return arr
+
+
+def _create(clib, specs, dtype=1, opts=None, count=None):
+    h, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    arr = _problems(specs)
+    st = clib.sorsvd_batch_create(len(specs) if count is None else count, arr, dtype,
+                                  ctypes.byref(opts) if opts is not None else None, ctypes.byref(h),
+                                  ctypes.byref(nb))
+    return st, h, nb.value
+
+
+def test_batch_plan_is_host_only_and_sized(clib):
+    st, h, nb = _create(clib, [(300, 200, 10, 0, 1), (129, 517, 20, 40, 0)])
+    assert st == 0 and h.value and nb > 0
+    assert clib.sorsvd_batch_count(h) == 2
+    cfg = (ctypes.c_int32 * 6)()
+    assert clib.sorsvd_batch_get_config(h, cfg) == 0
+    assert list(cfg[0::2]) == [1, 1, 1] and min(cfg[1::2]) >= 1
+    # run / read_info before a workspace is bound, a too small or misaligned workspace
+    assert clib.sorsvd_batch_run(h, ctypes.c_void_p(256), None) == EINVAL
+    assert clib.sorsvd_batch_upload(h, ctypes.c_void_p(256), nb - 1, None) == EWORKSPACE
+    assert clib.sorsvd_batch_upload(h, ctypes.c_void_p(264), nb, None) == EINVAL
+    bad = (ctypes.c_int32 * 6)(3, 256, 1, 256, 1, 256)
+    assert clib.sorsvd_batch_set_config(h, bad) == EINVAL
+    good = (ctypes.c_int32 * 6)(2, 512, 1, 128, 2, 64)
+    assert clib.sorsvd_batch_set_config(h, good) == 0
+    assert clib.sorsvd_batch_get_config(h, cfg) == 0 and list(cfg) == [2, 512, 1, 128, 2, 64]
+    clib.sorsvd_batch_destroy(h)
+    # the workspace grows with the problems
+    _, h2, nb2 = _create(clib, [(300, 200, 10, 0, 1), (129, 517, 20, 40, 0), (4000, 2000, 72, 0, 1)])
+    assert nb2 > nb
+    clib.sorsvd_batch_destroy(h2)
+    # FP64 batches run 64-row tiles only
+    _, h3, _ = _create(clib, [(300, 200, 10, 0, 1)], dtype=0)
+    assert clib.sorsvd_batch_set_config(h3, good) == EINVAL
+    clib.sorsvd_batch_destroy(h3)
+    clib.sorsvd_batch_destroy(None)
+
+
+def test_batch_create_rejects_bad_problems(clib):
+    ok = (300, 200, 10, 0, 1)
+    assert _create(clib, [ok], count=0)[0] == EINVAL
+    assert _create(clib, [ok, (300, 200, 0, 0, 1)])[0] == EINVAL      # k < 1
+    assert _create(clib, [ok, (300, 200, 201, 0, 1)])[0] == EINVAL    # k > min(m, n)
+    assert _create(clib, [ok, (300, 200, 10, 9, 1)])[0] == EINVAL     # 0 < l < k
+    assert _create(clib, [ok, (300, 200, 10, 201, 1)])[0] == EINVAL   # l > min(m, n)
+    assert _create(clib, [ok, (300, 200, 10, 0, -1)])[0] == EINVAL    # q < 0
+    assert _create(clib, [(300, 200, 10, 129, 0)])[0] == EUNSUPPORTED # padded l > 128
+    assert _create(clib, [ok], dtype=2)[0] == EUNSUPPORTED            # BF16 batches
+    assert _create(clib, [ok], opts=_lib.Opts(refine=1))[0] == EUNSUPPORTED
+    arr = _problems([ok])
+    arr[0].lda = 199
+    h, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    assert clib.sorsvd_batch_create(1, arr, 1, None, ctypes.byref(h), ctypes.byref(nb)) == EINVAL
+    arr = _problems([ok])
+    arr[0].A = None
+    assert clib.sorsvd_batch_create(1, arr, 1, None, ctypes.byref(h), ctypes.byref(nb)) == EINVAL
+
+
+def test_batch_tuning_cache_is_read_at_create(clib, tmp_path, monkeypatch):
+    specs = [(300, 200, 10, 0, 1), (129, 517, 20, 40, 0)]
+    _, h, _ = _create(clib, specs)
+    clib.sorsvd_batch_destroy(h)
+    # key: dtype, count and the summed m n LP of the batch
+    work = 300 * 200 * 16 + 129 * 517 * 48
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"t1_c2_w{work:.6e} 2 640 1 96 2 3200\nt1_c2_w1.000000e+00 1 1 1 1 1 1\n")
+    monkeypatch.setenv("SORSVD_TUNE_CACHE", str(cache))
+    _, h, _ = _create(clib, specs)
+    cfg = (ctypes.c_int32 * 6)()
+    clib.sorsvd_batch_get_config(h, cfg)
+    assert list(cfg) == [2, 640, 1, 96, 2, 3200]
+    clib.sorsvd_batch_destroy(h)

@@ -159,6 +159,23 @@ def rpca_problem_torch(m, n, r, seed, device="cuda", frac=0.05, amp=10.0, dtype=
     return A.to(dtype or torch.float32).contiguous()
 
 
+def c4_problem_seed(i, seed=3):
+    """Generator seed of problem i of the batched workload."""
+    return (seed << 20) + i
+
+
+def c4_torch(device="cuda", count=512, seed=3):
+    """The batched workload: FP32 RPCA-style matrices of uneven sizes.
+
+    Returns (mats, ks, qs, omega_seeds, ranks): k = r + 8, q = 1, Omega seed
+    of problem i is i + 1.
+    """
+    sizes = c4_sizes(count, seed)
+    mats = [rpca_problem_torch(m, n, r, c4_problem_seed(i, seed), device) for i, (m, n, r) in enumerate(sizes)]
+    ks = [r + 8 for (_, _, r) in sizes]
+    return mats, ks, [1] * count, [i + 1 for i in range(count)], [r for (_, _, r) in sizes]
+
+
 def c5_torch(device="cuda", n=32768, seed=5):
     torch = _torch()
     return spectral_torch(n, n, sigma_power(n, 1.5), seed, device, torch.bfloat16)
