@@ -13,6 +13,9 @@ the BF16-stored configuration (200000 x 4000, sigma_j = 0.9^j plus noise of
 s.d. 1e-6, k = 64, q = 1, refinement pass) and the small FP64 configuration
 (1000 x 800, k = 20, q = 0).
 
+The batched configuration (512 FP32 problems of uneven sizes, k = r + 8,
+q = 1) runs as HIP graph replays, one batch per step (extra "c4").
+
 Printed: ONE JSON line with throughput (SOR-SVDs/s), the algorithmic HBM rate
 of the passes, the roofline of the dominant kernel (the pass kernel over A,
 timed per launch with HIP events that the library records on the same stream
@@ -35,6 +38,10 @@ WORKLOADS = {
            "plain SOR-SVD FP64: A = X Y^T + 1e-3 E (1000 x 800, seed 0), k = 20, q = 0, Omega seed 1"),
 }
 
+C4_DESC = ("batched SOR-SVD FP32: 512 RPCA-style problems L + S (L = X Y^T, N(0,1) factors of rank r, "
+           "S = 5% outliers U[-10, 10]), m ~ U[256, 4096], n ~ U[128, 2048], r ~ U[4, 64] (seed 3), "
+           "k = r + 8, q = 1; one launch per step kind, autotuned tiles, HIP graph replay")
+
 # dominant-kernel roofline: (bound, peak, unit)
 PEAK = {"float32": ("mfma", 157.3, "TFLOP/s"), "float64": ("mfma", 78.6, "TFLOP/s"),
         "bfloat16": ("hbm", 8000.0, "GB/s")}
@@ -45,8 +52,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_input(name, torch):
+def make_input(name, torch, quick=False):
     import workloads as W
+    if quick:  # same shape and dtype, N(0, 1) entries: for counter runs where the spectrum does not matter
+        m, n, _, _, dname, _, _ = WORKLOADS[name]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        return torch.randn(m, n, generator=g, device="cuda", dtype=torch.float32).to(getattr(torch, dname))
     if name == "c2":
         return W.c2_torch("cuda")
     if name == "c3":
@@ -80,12 +92,12 @@ def cpu_baseline(A_host, k, q, seed, budget_s=20.0, max_reps=5):
                       f"(median {med:.3f} s; includes the oracle's explicit residual)"}
 
 
-def run_workload(name, steps, warmup, torch, P):
+def run_workload(name, steps, warmup, torch, P, quick=False):
     m, n, k, q, dname, refine, desc = WORKLOADS[name]
     seed = 1
     log(f"[bench] building input {name}: {desc}")
     t0 = time.perf_counter()
-    A = make_input(name, torch)
+    A = make_input(name, torch, quick)
     torch.cuda.synchronize()
     log(f"[bench] input ready in {time.perf_counter() - t0:.1f} s; dtype {A.dtype}")
     plan = P.Plan(m, n, k, q, A.dtype, refine=refine)
@@ -136,14 +148,69 @@ def run_workload(name, steps, warmup, torch, P):
     return res, A
 
 
+def run_batched(steps, warmup, torch, P):
+    """C4: the whole batch is one step; timed as HIP graph replays."""
+    import workloads as W
+    log(f"[bench] building input c4: {C4_DESC}")
+    mats, ks, qs, seeds, _ = W.c4_torch("cuda")
+    torch.cuda.synchronize()
+    b = P.Batch(mats, ks, qs, seeds)
+    cfg = b.autotune()
+    log(f"[bench] c4 tuned (rt, grid) per pass kind: {cfg}")
+    b.capture()
+    for _ in range(warmup):
+        b.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        b.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    # pass kernels, timed per launch group on one eager run (graph replays carry no timing events)
+    passes = [2 * q + 3 for q in qs]
+    P.pass_timing(True, capacity=64)
+    b.run()
+    torch.cuda.synchronize()
+    kern_ms, launches, kbytes, kflops = P.pass_timing_read()
+    P.pass_timing(False)
+    infos = b.info()
+    b.release_graph()
+    shapes = [tuple(A.shape) for A in mats]
+    bytes_a = sum(p * m * n * 4 for p, (m, n) in zip(passes, shapes))
+    flops_a = sum(p * 2.0 * m * n * k for p, (m, n), k in zip(passes, shapes, ks))
+    # per-problem roofline: each problem's passes at max(bytes / HBM, flops / FP32 peak)
+    t_roof = sum(max(p * m * n * 4 / 8e12, p * 2.0 * m * n * k / 157.3e12)
+                 for p, (m, n), k in zip(passes, shapes, ks))
+    log(f"[bench] c4: {ms:.3f} ms per batch of {len(mats)}; passes {kern_ms:.3f} ms in {launches} launch groups")
+    return {"workload": C4_DESC, "problems": len(mats), "dtype": "f32", "ms_per_step": round(ms, 4),
+            "value": round(len(mats) * 1000.0 / ms, 1), "unit": "SOR-SVD/s",
+            "tuned_config": cfg,
+            "hbm_gbps_algorithmic": round(bytes_a / (ms / 1e3) / 1e9, 1),
+            "roofline": {"bound": "mixed (per problem max of HBM and FP32 MFMA time)",
+                         "roofline_ms": round(t_roof * 1e3, 4), "frac": round(t_roof * 1e3 / ms, 4),
+                         "pass_kernels_ms": round(kern_ms, 4), "pass_launch_groups": launches,
+                         "pass_kernels_gbps": round(kbytes / (kern_ms / 1e3) / 1e9, 1),
+                         "pass_kernels_tflops": round(kflops / (kern_ms / 1e3) / 1e12, 2),
+                         "pass_bytes": kbytes, "pass_flops": kflops, "total_flops_of_passes": flops_a},
+            "max_jacobi_sweeps": max(i["sweeps"] for i in infos),
+            "flags": sum(i["flags"] for i in infos),
+            "err_fro_median": float(sorted(i["err_fro"] for i in infos)[len(infos) // 2])}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--extra", default="c3,c1", help="comma-separated extra workloads ('' for none)")
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
+    ap.add_argument("--extra", default="c3,c1,c4", help="comma-separated extra workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick-input", action="store_true",
+                    help="N(0, 1) entries of the workload's shape instead of its spectrum (counter runs only)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 3 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).",
@@ -153,7 +220,25 @@ def main():
     import torch
     import paper_1804_00462_amd as P
 
-    head, A = run_workload(args.workload, args.steps, args.warmup, torch, P)
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy calibration: 3 copies of 1 GiB done")
+    if args.workload == "c4":
+        head = run_batched(args.steps, args.warmup, torch, P)
+        out = {"metric": "rank-k SOR-SVDs/sec + HBM GB/s; BF16+learned vs FP32 plain at ≤1e-3 rel err",
+               "value": head["value"], "unit": "SOR-SVD/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": head["workload"], "problems": head["problems"]},
+               "roofline": head["roofline"], "cpu_baseline": None, "extra": {}}
+        print(json.dumps(out), flush=True)
+        return 0
+    head, A = run_workload(args.workload, args.steps, args.warmup, torch, P, args.quick_input)
     m, n, k, q = head["m"], head["n"], head["k"], head["q"]
     cpu = None
     if not args.no_cpu_baseline:
@@ -168,10 +253,13 @@ def main():
 
     extra = {}
     for name in [x for x in args.extra.split(",") if x and x != args.workload]:
-        res, A = run_workload(name, args.steps, args.warmup, torch, P)
-        del A
+        if name == "c4":
+            extra[name] = run_batched(args.steps, args.warmup, torch, P)
+        else:
+            res, A = run_workload(name, args.steps, args.warmup, torch, P)
+            del A
+            extra[name] = res
         torch.cuda.empty_cache()
-        extra[name] = res
 
     out = {
         "metric": "rank-k SOR-SVDs/sec + HBM GB/s; BF16+learned vs FP32 plain at ≤1e-3 rel err",
