@@ -39,6 +39,7 @@ typedef enum sorsvd_status {
   SORSVD_EHIP = -3,          /* a HIP launch or runtime call failed */
   SORSVD_ENOCONV = -4,       /* (info flag) Jacobi reached its sweep cap */
   SORSVD_ENONFINITE = -5,    /* (info flag) A holds Inf or NaN */
+  SORSVD_ETOL = -6,          /* sorsvd_auto: the tolerance was not met, fallback included */
   SORSVD_EUNSUPPORTED = -7   /* valid request outside what this build implements */
 } sorsvd_status;
 
@@ -49,14 +50,21 @@ typedef enum sorsvd_status {
  *           BF16 (with opts.refine the projection pass splits Q2 into a BF16
  *           high and low part).
  * QR, the core SVD and the lift always run in FP64. */
-typedef enum sorsvd_dtype { SORSVD_F64 = 0, SORSVD_F32 = 1, SORSVD_BF16 = 2 } sorsvd_dtype;
+typedef enum sorsvd_dtype { SORSVD_F64 = 0, SORSVD_F32 = 1, SORSVD_BF16 = 2, SORSVD_DIAG = 3 } sorsvd_dtype;
+/* SORSVD_DIAG: A = diag(sigma), m = n, given by its diagonal: A points to n FP64
+ * values on the device (lda is not used). Every pass is diag(sigma) X in FP64;
+ * everything else is the FP64 path. The Gaussian Omega is rotation-invariant,
+ * so a SOR-SVD of diag(sigma) is distributed exactly as one of U diag(sigma) V^T
+ * with Haar U, V: this form labels the training spectra of the (k, q)
+ * predictor at O(n l) per pass. No explicit residual (opts.residual) for it. */
 
 /* Optional settings; pass NULL for the defaults (all fields 0). */
 typedef struct sorsvd_opts {
   int64_t l;          /* sketch width l, k <= l <= min(m, n); 0 means l = k */
   int32_t max_sweeps; /* Jacobi sweep cap of the core SVD; 0 means 40 */
   int32_t refine;     /* BF16 A only: 1 = projection pass with Q2 split hi+lo */
-  int32_t residual;   /* 1 = also compute ||A - U S V^T||_F explicitly (one more pass) */
+  int32_t residual;   /* 1 = also compute ||A - U S V^T||_F explicitly (one more pass over A,
+                         FP32 MFMA for FP32 / BF16 A, FP64 for FP64 A, FP64 accumulation) */
   int32_t split;      /* split of the contraction in the passes; 0 = automatic */
   int32_t tile;       /* BF16 passes: 64*tile rows (columns) of A per workgroup, tile in {1,2,4}; 0 = automatic */
   int32_t reserved1;
@@ -72,6 +80,12 @@ typedef struct sorsvd_info {
                               bit 2: a Cholesky-QR pivot stayed <= 0 after the shift, so its
                               column was dropped from Q (sketch columns dependent to
                               rounding: a sketch condition number near 1/u) */
+  double a_noise_rel;      /* opts.residual with BF16 A: sqrt(sum ulp(a_ij)^2 / 12) / ||A||_F, the
+                              expected relative size of the rounding of A to BF16; the error
+                              against A before rounding lies between
+                              sqrt(err_fro_explicit^2 - a_noise_rel^2) and
+                              sqrt(err_fro_explicit^2 - (1 - 2 rho) a_noise_rel^2),
+                              rho = min(1, k (m^-1/2 + n^-1/2)^2). 0 otherwise */
 } sorsvd_info;
 
 /* Workspace size in bytes for sorsvd() with the same arguments. Returns 0 for
@@ -190,7 +204,7 @@ typedef struct sorsvd_batch sorsvd_batch;
  * plan: per-step work lists ordered largest item first, the workspace layout
  * and the default launch configuration (or the one stored for this batch
  * shape in the tuning cache file named by the environment variable
- * SORSVD_TUNE_CACHE). a_type: SORSVD_F32 or SORSVD_F64 (BF16 ->
+ * SORSVD_TUNE_CACHE). a_type: SORSVD_F32, SORSVD_F64 or SORSVD_DIAG (BF16 ->
  * SORSVD_EUNSUPPORTED). opts: NULL, or only max_sweeps set (other fields
  * non-zero -> SORSVD_EUNSUPPORTED). On success *out holds the plan and
  * *ws_bytes the device workspace it needs. The problem array is copied; the
@@ -240,6 +254,72 @@ int32_t sorsvd_batch_count(const sorsvd_batch* b);
 
 /* Free a plan (NULL is allowed). Does not touch device memory. */
 void sorsvd_batch_destroy(sorsvd_batch* b);
+
+/*
+ * Learned choice of (k, q) for a target tolerance (extension of the method:
+ * the error check of the method is the judge, fixed (k, q) the fallback).
+ *
+ * sorsvd_probe_features: the probe sketch Y0 = A Omega[:, :l], l = min(128, m, n),
+ *   Omega of key (seed, 0) as in sorsvd(); s_j = singular values of Y0 (Cholesky
+ *   QR of Y0, then the core SVD of R); features (device, 128 FP32):
+ *   f_j = clamp(log10(s_j / s_1) / 8, -1, 0) for j < l, -1 beyond.
+ *   Workspace: sorsvd_probe_workspace_bytes(m, n, a_type).
+ *
+ * The network: 128 -> 64 (tanh) -> 64 (tanh) -> 4, FP32, parameters one flat
+ * device vector of sorsvd_mlp_param_count() = 12676 values: W1 (64 x 128,
+ * row-major), b1 (64), W2 (64 x 64), b2, W3 (4 x 64), b3 (4). Output y_q
+ * predicts log2 of the smallest k (= l) whose SOR-SVD with q power steps meets
+ * the tolerance, q = 0..3.
+ *   sorsvd_mlp_forward:  Y (batch x 4) from X (batch x 128), row-major.
+ *   sorsvd_mlp_backward: forward, then grad (12676) of the loss
+ *       mean over batch x 4 of (y - T)^2, and the loss itself (device, 1 float).
+ *   sorsvd_mlp_adam: one Adam step (step >= 1) on params with moments m, v.
+ *   sorsvd_mlp_train_step: backward + Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ *   work: device scratch of sorsvd_mlp_work_floats(batch) floats (activations;
+ *   backward and train_step keep them there between their kernels).
+ *
+ * sorsvd_auto: probe -> network -> (k, q) -> SOR-SVD -> judge -> fallback.
+ *   For each q the network's width is taken with 25% head-room, rounded up to
+ *   a multiple of 8, and kept if it fits min(128, m, n); among those the (k, q)
+ *   with the least modelled pass time (2q + 3) max(1, k / k_ridge) wins
+ *   (k_ridge 312 for BF16, 39 otherwise). Judge: the error identity
+ *   (FP32/FP64), or for BF16 the explicit residual corrected for the rounding
+ *   of A to BF16: sqrt(err_fro_explicit^2 - (1 - 2 rho) a_noise_rel^2) with
+ *   rho = min(1, k (m^-1/2 + n^-1/2)^2), the largest share of the rounding noise
+ *   a rank-k fit can absorb (so the judge errs on the safe side). If the judge
+ *   rejects, or no predicted width fits, the fallback k = min(128, m, n),
+ *   q = 2 runs and is judged. params = NULL skips the network (fallback only).
+ *   U, V need ldu, ldv >= min(128, m, n) (the first k_used columns are the
+ *   result), S as many entries. Synchronous: waits for `stream`. Returns
+ *   SORSVD_OK, or SORSVD_ETOL with the fallback's result left in U, S, V.
+ *   Workspace: sorsvd_auto_workspace_bytes(m, n, a_type).
+ */
+typedef struct sorsvd_auto_info {
+  int32_t k_used, q_used;  /* the (k, q) of the returned result */
+  int32_t used_fallback;   /* 1 if the result is the fallback's */
+  int32_t runs;            /* SOR-SVDs run (1 or 2) */
+  double err;              /* the judge's error of the returned result */
+  double k_pred[4];        /* network widths 2^y_q before head-room (0 without params) */
+  int32_t flags;           /* sorsvd_info.flags of the returned result */
+  int32_t reserved;
+} sorsvd_auto_info;
+
+size_t sorsvd_probe_workspace_bytes(int64_t m, int64_t n, int32_t a_type);
+int sorsvd_probe_features(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed,
+                          float* features, void* workspace, size_t ws_bytes, void* stream);
+int32_t sorsvd_mlp_param_count(void);
+size_t sorsvd_mlp_work_floats(int32_t batch);
+int sorsvd_mlp_forward(const float* params, const float* X, int32_t batch, float* Y, float* work, void* stream);
+int sorsvd_mlp_backward(const float* params, const float* X, const float* T, int32_t batch, float* grad,
+                        float* loss, float* work, void* stream);
+int sorsvd_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
+                    float beta2, float eps, void* stream);
+int sorsvd_mlp_train_step(float* params, float* m, float* v, const float* X, const float* T, int32_t batch,
+                          int64_t step, float lr, float* grad, float* loss, float* work, void* stream);
+size_t sorsvd_auto_workspace_bytes(int64_t m, int64_t n, int32_t a_type);
+int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed, double tol,
+                const float* params, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                void* workspace, size_t ws_bytes, void* stream, sorsvd_auto_info* out);
 
 /* Human-readable text of a status code (static storage). */
 const char* sorsvd_status_string(int status);

@@ -5,10 +5,10 @@ The computation lives in ``libsorsvd.so`` (HIP kernels behind the C ABI of
 not load the library; the first call does, and fails loudly if it is missing.
 """
 from . import _lib
-from ._lib import SORSVD_BF16, SORSVD_F32, SORSVD_F64, SorsvdError, load
-from .api import (Batch, Plan, dtype_code, pass_timing, pass_timing_read, philox_normal, sorsvd, step_core_svd, step_orbit, step_project,
+from ._lib import SORSVD_BF16, SORSVD_DIAG, SORSVD_F32, SORSVD_F64, SorsvdError, load
+from .api import (MLP, Batch, Plan, auto, dtype_code, mlp_param_count, probe_features, sorsvd_diag, pass_timing, pass_timing_read, philox_normal, sorsvd, step_core_svd, step_orbit, step_project,
                   step_qr, step_sketch, workspace_bytes)
 
-__all__ = ["Batch", "Plan", "SorsvdError", "SORSVD_BF16", "SORSVD_F32", "SORSVD_F64", "dtype_code", "load",
+__all__ = ["MLP", "SORSVD_DIAG", "auto", "mlp_param_count", "probe_features", "sorsvd_diag", "Batch", "Plan", "SorsvdError", "SORSVD_BF16", "SORSVD_F32", "SORSVD_F64", "dtype_code", "load",
            "pass_timing", "pass_timing_read", "philox_normal", "sorsvd", "step_core_svd", "step_orbit", "step_project", "step_qr",
            "step_sketch", "workspace_bytes"]

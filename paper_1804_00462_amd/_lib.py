@@ -14,10 +14,11 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "sorsvd.h")
 c_i32, c_i64, c_u64, c_sz, c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
 c_vp = ctypes.c_void_p
 
-SORSVD_F64, SORSVD_F32, SORSVD_BF16 = 0, 1, 2
+SORSVD_F64, SORSVD_F32, SORSVD_BF16, SORSVD_DIAG = 0, 1, 2, 3
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error",
-          -4: "Jacobi sweep cap reached", -5: "non-finite input", -7: "unsupported in this build"}
+          -4: "Jacobi sweep cap reached", -5: "non-finite input", -6: "tolerance not met",
+          -7: "unsupported in this build"}
 
 
 class SorsvdError(RuntimeError):
@@ -37,9 +38,14 @@ class Problem(ctypes.Structure):
                 ("S", c_vp), ("V", c_vp), ("ldv", c_i64)]
 
 
+class AutoInfo(ctypes.Structure):
+    _fields_ = [("k_used", c_i32), ("q_used", c_i32), ("used_fallback", c_i32), ("runs", c_i32),
+                ("err", c_dbl), ("k_pred", c_dbl * 4), ("flags", c_i32), ("reserved", c_i32)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("a_fro", c_dbl), ("err_fro", c_dbl), ("err_fro_explicit", c_dbl),
-                ("sweeps", c_i32), ("flags", c_i32)]
+                ("sweeps", c_i32), ("flags", c_i32), ("a_noise_rel", c_dbl)]
 
 
 _SIGS = {
@@ -68,6 +74,19 @@ _SIGS = {
     "sorsvd_graph_destroy": (c_i32, [c_vp]),
     "sorsvd_batch_count": (c_i32, [c_vp]),
     "sorsvd_batch_destroy": (None, [c_vp]),
+    "sorsvd_probe_workspace_bytes": (c_sz, [c_i64, c_i64, c_i32]),
+    "sorsvd_probe_features": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_vp, c_sz, c_vp]),
+    "sorsvd_mlp_param_count": (c_i32, []),
+    "sorsvd_mlp_work_floats": (c_sz, [c_i32]),
+    "sorsvd_mlp_forward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "sorsvd_mlp_backward": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "sorsvd_mlp_adam": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, c_vp]),
+    "sorsvd_mlp_train_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, ctypes.c_float, c_vp, c_vp,
+                                      c_vp, c_vp]),
+    "sorsvd_auto_workspace_bytes": (c_sz, [c_i64, c_i64, c_i32]),
+    "sorsvd_auto": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_u64, c_dbl, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64,
+                            c_vp, c_sz, c_vp, c_vp]),
     "sorsvd_status_string": (ctypes.c_char_p, [c_i32]),
     "sorsvd_version": (ctypes.c_char_p, []),
 }

@@ -6,7 +6,7 @@ computation runs in the library's kernels. Names follow the C entry points.
 import ctypes
 
 from . import _lib
-from ._lib import SORSVD_BF16, SORSVD_F32, SORSVD_F64, Info, Opts, Problem, check
+from ._lib import SORSVD_BF16, SORSVD_DIAG, SORSVD_F32, SORSVD_F64, AutoInfo, Info, Opts, Problem, check
 
 
 def _torch():
@@ -42,6 +42,11 @@ def _check_matrix(A):
         raise ValueError("A must be row-major (unit column stride)")
 
 
+def _info_dict(o):
+    return {"a_fro": o.a_fro, "err_fro": o.err_fro, "err_fro_explicit": o.err_fro_explicit,
+            "sweeps": o.sweeps, "flags": o.flags, "a_noise_rel": o.a_noise_rel}
+
+
 def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0):
     return Opts(l=l, max_sweeps=max_sweeps, refine=refine, residual=residual, split=split, tile=tile)
 
@@ -58,7 +63,7 @@ class Plan:
     def __init__(self, m, n, k, q, dtype, device="cuda", **opts):
         torch = _torch()
         self.m, self.n, self.k, self.q = m, n, k, q
-        self.code = dtype_code(dtype)
+        self.code = dtype if isinstance(dtype, int) else dtype_code(dtype)
         self.opts = make_opts(**opts)
         lib = _lib.load()
         nbytes = int(lib.sorsvd_workspace_bytes(m, n, k, q, self.code, ctypes.byref(self.opts)))
@@ -71,11 +76,17 @@ class Plan:
         self.V = torch.empty(n, k, dtype=torch.float64, device=device)
 
     def run(self, A, seed=0, stream=None):
-        _check_matrix(A)
-        if tuple(A.shape) != (self.m, self.n) or dtype_code(A.dtype) != self.code:
-            raise ValueError("A does not match the plan")
+        if self.code == SORSVD_DIAG:
+            if A.dim() != 1 or A.shape[0] != self.n or A.dtype != _torch().float64 or not A.is_cuda:
+                raise ValueError("diagonal A must be a 1-D FP64 device tensor of length n")
+            lda = self.n
+        else:
+            _check_matrix(A)
+            if tuple(A.shape) != (self.m, self.n) or dtype_code(A.dtype) != self.code:
+                raise ValueError("A does not match the plan")
+            lda = A.stride(0)
         lib = _lib.load()
-        st = lib.sorsvd(_ptr(A), A.stride(0), self.code, self.m, self.n, self.k, self.q, seed,
+        st = lib.sorsvd(_ptr(A), lda, self.code, self.m, self.n, self.k, self.q, seed,
                         _ptr(self.U), self.k, _ptr(self.S), _ptr(self.V), self.k,
                         _ptr(self.ws), self.ws_bytes, _stream(stream), ctypes.byref(self.opts))
         check(st, "sorsvd")
@@ -84,14 +95,21 @@ class Plan:
     def info(self, stream=None):
         out = Info()
         check(_lib.load().sorsvd_read_info(_ptr(self.ws), ctypes.byref(out), _stream(stream)), "sorsvd_read_info")
-        return {"a_fro": out.a_fro, "err_fro": out.err_fro, "err_fro_explicit": out.err_fro_explicit,
-                "sweeps": out.sweeps, "flags": out.flags}
+        return _info_dict(out)
 
 
 def sorsvd(A, k, q=0, seed=0, **opts):
     """Rank-k SOR-SVD of the device matrix A. Returns (U, S, V, info) as FP64 tensors."""
     plan = Plan(A.shape[0], A.shape[1], k, q, A.dtype, device=A.device, **opts)
     U, S, V = plan.run(A, seed)
+    return U, S, V, plan.info()
+
+
+def sorsvd_diag(sigma, k, q=0, seed=0, **opts):
+    """SOR-SVD of A = diag(sigma) (1-D FP64 device tensor); (U, S, V, info)."""
+    n = sigma.shape[0]
+    plan = Plan(n, n, k, q, SORSVD_DIAG, device=sigma.device, **opts)
+    U, S, V = plan.run(sigma, seed)
     return U, S, V, plan.info()
 
 
@@ -214,7 +232,8 @@ class Batch:
         torch = _torch()
         if not mats:
             raise ValueError("empty batch")
-        code = dtype_code(mats[0].dtype)
+        diag = mats[0].dim() == 1
+        code = SORSVD_DIAG if diag else dtype_code(mats[0].dtype)
         count = len(mats)
         ls = ls if ls is not None else [0] * count
         if not (len(ks) == len(qs) == len(seeds) == len(ls) == count):
@@ -223,10 +242,15 @@ class Batch:
         self.U, self.S, self.V = [], [], []
         probs = (Problem * count)()
         for i, A in enumerate(mats):
-            _check_matrix(A)
-            if dtype_code(A.dtype) != code:
-                raise ValueError("all matrices of a batch share one dtype")
-            m, n = A.shape
+            if diag:
+                if A.dim() != 1 or A.dtype != torch.float64 or not A.is_cuda:
+                    raise ValueError("diagonal problems are 1-D FP64 device tensors")
+                m = n = A.shape[0]
+            else:
+                _check_matrix(A)
+                if dtype_code(A.dtype) != code:
+                    raise ValueError("all matrices of a batch share one dtype")
+                m, n = A.shape
             k = int(ks[i])
             U = torch.empty(m, k, dtype=torch.float64, device=A.device)
             S = torch.empty(k, dtype=torch.float64, device=A.device)
@@ -234,7 +258,7 @@ class Batch:
             self.U.append(U)
             self.S.append(S)
             self.V.append(V)
-            probs[i] = Problem(A=A.data_ptr(), lda=A.stride(0), m=m, n=n, k=k, l=int(ls[i]), q=int(qs[i]),
+            probs[i] = Problem(A=A.data_ptr(), lda=n if diag else A.stride(0), m=m, n=n, k=k, l=int(ls[i]), q=int(qs[i]),
                                reserved=0, seed=int(seeds[i]), U=U.data_ptr(), ldu=k, S=S.data_ptr(),
                                V=V.data_ptr(), ldv=k)
         self._probs = probs
@@ -274,8 +298,7 @@ class Batch:
     def info(self, stream=None):
         out = (Info * len(self.mats))()
         check(_lib.load().sorsvd_batch_read_info(self._h, out, _stream(stream)), "sorsvd_batch_read_info")
-        return [{"a_fro": o.a_fro, "err_fro": o.err_fro, "err_fro_explicit": o.err_fro_explicit,
-                 "sweeps": o.sweeps, "flags": o.flags} for o in out]
+        return [_info_dict(o) for o in out]
 
     def capture(self):
         """Capture the run's launch sequence in a HIP graph (replaces an earlier one)."""
@@ -305,3 +328,98 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ learned (k, q)
+
+def probe_features(A, seed=0):
+    """128 FP32 features of A (2-D device matrix, or 1-D FP64 diagonal) from the probe sketch."""
+    torch = _torch()
+    lib = _lib.load()
+    if A.dim() == 1:
+        code, m, n, lda = SORSVD_DIAG, A.shape[0], A.shape[0], A.shape[0]
+    else:
+        _check_matrix(A)
+        code, (m, n), lda = dtype_code(A.dtype), A.shape, A.stride(0)
+    nbytes = int(lib.sorsvd_probe_workspace_bytes(m, n, code))
+    if nbytes == 0:
+        raise _lib.SorsvdError(-1, "sorsvd_probe_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    feat = torch.empty(128, dtype=torch.float32, device=A.device)
+    check(lib.sorsvd_probe_features(_ptr(A), lda, code, m, n, seed, _ptr(feat), _ptr(ws), nbytes, _stream()),
+          "sorsvd_probe_features")
+    return feat
+
+
+def mlp_param_count():
+    return int(_lib.load().sorsvd_mlp_param_count())
+
+
+class MLP:
+    """Device parameters, Adam moments and scratch of the (k, q) network."""
+
+    def __init__(self, params, max_batch=256):
+        torch = _torch()
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.grad = torch.zeros_like(params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        self.max_batch = max_batch
+        self.work = torch.empty(int(_lib.load().sorsvd_mlp_work_floats(max_batch)), dtype=torch.float32,
+                                device=params.device)
+        self.step = 0
+
+    def _check(self, X):
+        if X.dtype != _torch().float32 or X.dim() != 2 or X.shape[1] != 128 or X.shape[0] > self.max_batch:
+            raise ValueError("X must be B x 128 FP32 with B <= max_batch")
+        return X.contiguous()
+
+    def forward(self, X):
+        X = self._check(X)
+        Y = _torch().empty(X.shape[0], 4, dtype=_torch().float32, device=X.device)
+        check(_lib.load().sorsvd_mlp_forward(_ptr(self.params), _ptr(X), X.shape[0], _ptr(Y), _ptr(self.work),
+                                             _stream()), "sorsvd_mlp_forward")
+        return Y
+
+    def backward(self, X, T):
+        X = self._check(X)
+        T = T.contiguous()
+        check(_lib.load().sorsvd_mlp_backward(_ptr(self.params), _ptr(X), _ptr(T), X.shape[0], _ptr(self.grad),
+                                              _ptr(self.loss), _ptr(self.work), _stream()), "sorsvd_mlp_backward")
+        return self.grad, self.loss
+
+    def train_step(self, X, T, lr=1e-3):
+        X = self._check(X)
+        T = T.contiguous()
+        self.step += 1
+        check(_lib.load().sorsvd_mlp_train_step(_ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(X), _ptr(T),
+                                                X.shape[0], self.step, lr, _ptr(self.grad), _ptr(self.loss),
+                                                _ptr(self.work), _stream()), "sorsvd_mlp_train_step")
+        return self.loss
+
+
+def auto(A, tol, params=None, seed=0):
+    """Learned (k, q) + judge + fallback (params None: fallback only). Returns (U, S, V, info dict, status)."""
+    torch = _torch()
+    lib = _lib.load()
+    _check_matrix(A)
+    code, (m, n) = dtype_code(A.dtype), A.shape
+    kcap = min(128, m, n)
+    nbytes = int(lib.sorsvd_auto_workspace_bytes(m, n, code))
+    if nbytes == 0:
+        raise _lib.SorsvdError(-1, "sorsvd_auto_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    U = torch.empty(m, kcap, dtype=torch.float64, device=A.device)
+    S = torch.empty(kcap, dtype=torch.float64, device=A.device)
+    V = torch.empty(n, kcap, dtype=torch.float64, device=A.device)
+    out = AutoInfo()
+    st = lib.sorsvd_auto(_ptr(A), A.stride(0), code, m, n, seed, float(tol),
+                         _ptr(params) if params is not None else None, _ptr(U), kcap, _ptr(S), _ptr(V), kcap,
+                         _ptr(ws), nbytes, _stream(), ctypes.byref(out))
+    if st not in (0, -6):
+        check(st, "sorsvd_auto")
+    k = out.k_used
+    info = {"k_used": k, "q_used": out.q_used, "used_fallback": out.used_fallback, "runs": out.runs,
+            "err": out.err, "k_pred": list(out.k_pred), "flags": out.flags, "met": st == 0}
+    return U[:, :k], S[:k], V[:, :k], info

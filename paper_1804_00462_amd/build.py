@@ -25,6 +25,8 @@ SOURCES = {
     "small.hip": [],
     "sorsvd.hip": [],
     "batched.hip": [],
+    "residual.hip": [],
+    "mlp.hip": [],
 }
 
 COMMON = [

@@ -115,6 +115,37 @@ k_bpass(const BProb* __restrict__ probs, const BItem* __restrict__ items, int ni
   }
 }
 
+// Passes over A = diag(sigma) (given by its diagonal, m = n): out = diag(sigma) X
+// for one 64-row tile, the same product for A and A^T; the first sketch also
+// records the sum of sigma_r^2 over the tile.
+__global__ void __launch_bounds__(256)
+k_bdiag(const BProb* __restrict__ probs, const BItem* __restrict__ items, int nitems, int mode, int qiter,
+        int want_norm) {
+  __shared__ double red[4];
+  for (int it = xcd_remap(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
+    const BItem I = items[it];
+    const BProb& P = probs[I.prob];
+    if (qiter >= 0 && qiter >= P.q) continue;
+    const double* sig = reinterpret_cast<const double*>(P.A);
+    const double* X = reinterpret_cast<const double*>(P.Xc);
+    double* out = mode == M_SKETCH ? P.T1 : (mode == M_ORBIT ? P.T2 : P.W);
+    const int64_t r0 = I.base, r1 = min(P.n, r0 + 64);
+    for (int64_t e = threadIdx.x; e < (r1 - r0) * P.LP; e += 256) {
+      const int64_t r = r0 + e / P.LP;
+      out[r * P.LP + e % P.LP] = sig[r] * X[r * P.LP + e % P.LP];
+    }
+    if (want_norm) {
+      double a = 0.0;
+      for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) a += sig[r] * sig[r];
+      a = wave_sum(a);
+      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
+      __syncthreads();
+      if (threadIdx.x == 0) P.normp[I.chunk] = (red[0] + red[1]) + (red[2] + red[3]);
+      __syncthreads();
+    }
+  }
+}
+
 // FP64 products on the tall sketches, 64-row tiles, problems with LP = 16 CT
 // (lifts: KP = 16 CT).
 // Gram: T^T T (or Q1^T W) over one 512-row chunk, output rows [base, base + 64)
@@ -191,6 +222,7 @@ __global__ void __launch_bounds__(256) k_bclear(const BProb* __restrict__ probs)
     P.info->err_fro_explicit = -1.0;
     P.info->sweeps = 0;
     P.info->flags = 0;
+    P.info->a_noise_rel = 0.0;
     *P.skip3 = 1;
   }
   TA* Xc = reinterpret_cast<TA*>(P.Xc);
@@ -430,6 +462,16 @@ const BItem* dev_items(const sorsvd_batch* b, void* ws, int mode, int r, int c) 
 // the launches with the library's pass-timing events (when timing is on).
 template <typename TA>
 int launch_pass(const sorsvd_batch* b, void* ws, int mode, int qiter, const Cfg& c, bool timed, hipStream_t st) {
+  if (b->a_type == SORSVD_DIAG) {  // A = diag(sigma): one element-wise launch per LP group
+    for (int ci = 0; ci < 8; ++ci) {
+      const int n = (int)b->items[mode][0][ci].size();
+      if (n == 0) continue;
+      hipLaunchKernelGGL(k_bdiag, dim3((unsigned)std::min(2048, n)), dim3(256), 0, st, dev_table(b, ws),
+                         dev_items(b, ws, mode, 0, ci), n, mode, qiter, (mode == M_SKETCH && qiter < 0) ? 1 : 0);
+      SORSVD_TRY(hipGetLastError());
+    }
+    return SORSVD_OK;
+  }
   // FP64 tiles are 64 rows only (128-row FP64 tiles do not fit the registers)
   const int rt = sizeof(TA) == 8 ? 1 : c.rt;
   const int r = rt - 1;
@@ -599,7 +641,7 @@ int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
 }
 
 int run_any(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
-  return b->a_type == SORSVD_F64 ? run_batch<double>(b, ws, timed, st) : run_batch<float>(b, ws, timed, st);
+  return b->a_type == SORSVD_F32 ? run_batch<float>(b, ws, timed, st) : run_batch<double>(b, ws, timed, st);
 }
 
 std::string tune_key(const sorsvd_batch* b) {
@@ -624,7 +666,7 @@ bool tune_cache_load(sorsvd_batch* b) {
   while (std::fscanf(f, "%127s %d %d %d %d %d %d", key, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 7) {
     if (want != key) continue;
     bool ok = true;
-    for (int i = 0; i < 3; ++i) ok = ok && (v[2 * i] == 1 || (v[2 * i] == 2 && b->a_type != SORSVD_F64)) && v[2 * i + 1] >= 1;
+    for (int i = 0; i < 3; ++i) ok = ok && (v[2 * i] == 1 || (v[2 * i] == 2 && b->a_type == SORSVD_F32)) && v[2 * i + 1] >= 1;
     if (!ok) continue;
     for (int i = 0; i < 3; ++i) {
       b->cfg[i].rt = v[2 * i];
@@ -655,12 +697,12 @@ int sorsvd_batch_create(int32_t count, const sorsvd_problem* probs, int32_t a_ty
   if (!out || !ws_bytes || !probs || count < 1 || count > kMaxBatch) return SORSVD_EINVAL;
   *out = nullptr;
   *ws_bytes = 0;
-  if (a_type != SORSVD_F32 && a_type != SORSVD_F64) return SORSVD_EUNSUPPORTED;
+  if (a_type != SORSVD_F32 && a_type != SORSVD_F64 && a_type != SORSVD_DIAG) return SORSVD_EUNSUPPORTED;
   if (opts && (opts->refine || opts->residual || opts->split || opts->tile || opts->l)) return SORSVD_EUNSUPPORTED;
   sorsvd_batch* b = new sorsvd_batch();
   b->count = count;
   b->a_type = a_type;
-  b->es = a_type == SORSVD_F64 ? 8 : 4;
+  b->es = a_type == SORSVD_F32 ? 4 : 8;
   b->max_sweeps = (opts && opts->max_sweeps > 0) ? opts->max_sweeps : 40;
   b->probs.resize(count);
   b->omega.resize(count);
@@ -668,8 +710,10 @@ int sorsvd_batch_create(int32_t count, const sorsvd_problem* probs, int32_t a_ty
   for (int i = 0; i < count; ++i) {
     const sorsvd_problem& u = probs[i];
     const int64_t l = u.l > 0 ? u.l : u.k;
+    const bool diag = a_type == SORSVD_DIAG;
     const bool bad = !u.A || !u.U || !u.S || !u.V || u.m < 1 || u.n < 1 || u.k < 1 || u.q < 0 || l < u.k ||
-                     l > std::min(u.m, u.n) || u.lda < u.n || u.ldu < u.k || u.ldv < u.k;
+                     l > std::min(u.m, u.n) || (!diag && u.lda < u.n) || (diag && u.m != u.n) ||
+                     u.ldu < u.k || u.ldv < u.k;
     if (bad || round_up(l, kTile) > kMaxBatchLP || u.m > INT32_MAX || u.n > INT32_MAX) {
       delete b;
       return bad ? SORSVD_EINVAL : SORSVD_EUNSUPPORTED;
@@ -802,7 +846,7 @@ int sorsvd_batch_get_config(const sorsvd_batch* b, int32_t* config) {
 
 int sorsvd_batch_set_config(sorsvd_batch* b, const int32_t* config) {
   if (!b || !config) return SORSVD_EINVAL;
-  const int max_rt = b->a_type == SORSVD_F64 ? 1 : 2;
+  const int max_rt = b->a_type == SORSVD_F32 ? 2 : 1;
   for (int i = 0; i < 3; ++i)
     if (config[2 * i] < 1 || config[2 * i] > max_rt || config[2 * i + 1] < 1) return SORSVD_EINVAL;
   for (int i = 0; i < 3; ++i) {
@@ -826,14 +870,14 @@ int sorsvd_batch_autotune(sorsvd_batch* b, void* ws, void* stream, int32_t* conf
   for (int mi = 0; mi < 3 && rc == SORSVD_OK; ++mi) {
     float best = 1e30f;
     Cfg bestc = b->cfg[mi];
-    for (int rt = 1; rt <= (b->a_type == SORSVD_F64 ? 1 : 2); ++rt)
+    for (int rt = 1; rt <= (b->a_type == SORSVD_F32 ? 2 : 1); ++rt)
       for (int grid : {256, 512, 1024, 2048, 4096}) {
         const Cfg c{rt, grid};
         float tot = 0.f;
         for (int rep = 0; rep < 4 && rc == SORSVD_OK; ++rep) {
           if (hipEventRecord(e0, st) != hipSuccess) { rc = SORSVD_EHIP; break; }
-          rc = b->a_type == SORSVD_F64 ? launch_pass<double>(b, ws, modes[mi], -1, c, false, st)
-                                       : launch_pass<float>(b, ws, modes[mi], -1, c, false, st);
+          rc = b->a_type == SORSVD_F32 ? launch_pass<float>(b, ws, modes[mi], -1, c, false, st)
+                                       : launch_pass<double>(b, ws, modes[mi], -1, c, false, st);
           if (rc) break;
           float ms = 0.f;
           if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

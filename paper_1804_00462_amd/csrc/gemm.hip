@@ -10,6 +10,8 @@
 // are renumbered so that each of the 8 XCDs receives a contiguous run of
 // (split, tile) pairs: workgroups on one XCD mostly share one split, i.e. one
 // slab of the skinny operand, which then stays in that XCD's L2.
+#include <algorithm>
+
 #include "skinny_body.hpp"
 
 namespace sor {
@@ -203,6 +205,40 @@ hipError_t launch_pack_f32(const double* src, int64_t rows, int cols, int64_t ld
 hipError_t launch_cast_f32(const double* Q, int64_t n_elem, float* Xc, hipStream_t st) {
   if (n_elem == 0) return hipSuccess;
   hipLaunchKernelGGL(k_cast_f32, dim3((unsigned)ceil_div(n_elem, 256)), dim3(256), 0, st, Q, n_elem, Xc);
+  return hipGetLastError();
+}
+
+// A = diag(sigma) (n x n, given by its diagonal): T = diag(sigma) X, which is
+// also A^T X. X and T are n x LP row-major.
+__global__ void __launch_bounds__(256) k_diag_pass(const double* __restrict__ sigma, int64_t n, int LP,
+                                                   const double* __restrict__ X, double* __restrict__ T) {
+  const int64_t tot = n * LP;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += (int64_t)gridDim.x * 256)
+    T[i] = sigma[i / LP] * X[i];
+}
+
+// normp[b] = sum of sigma_r^2 over rows [b rpb, (b + 1) rpb) (the ||A||_F^2 slots of the first pass).
+__global__ void __launch_bounds__(256) k_diag_norm(const double* __restrict__ sigma, int64_t n, int64_t rpb,
+                                                   double* __restrict__ normp) {
+  __shared__ double part[256];
+  const int64_t r0 = (int64_t)blockIdx.x * rpb, r1 = min(n, r0 + rpb);
+  double a = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) a += sigma[r] * sigma[r];
+  part[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) normp[blockIdx.x] = part[0];
+}
+
+hipError_t launch_diag_pass(const double* sigma, int64_t n, int LP, const double* X, double* T, double* normp,
+                            int nparts, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>(8192, ceil_div(n * LP, 256));
+  hipLaunchKernelGGL(k_diag_pass, dim3((unsigned)blocks), dim3(256), 0, st, sigma, n, LP, X, T);
+  if (normp)
+    hipLaunchKernelGGL(k_diag_norm, dim3((unsigned)nparts), dim3(256), 0, st, sigma, n, ceil_div(n, nparts), normp);
   return hipGetLastError();
 }
 

@@ -143,6 +143,7 @@ __global__ void __launch_bounds__(64) k_info_init(DevInfo* info) {
     info->err_fro_explicit = -1.0;
     info->sweeps = 0;
     info->flags = 0;
+    info->a_noise_rel = 0.0;
   }
 }
 

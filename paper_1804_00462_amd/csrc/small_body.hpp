@@ -23,6 +23,7 @@ struct DevInfo {  // mirrors sorsvd_info
   double err_fro_explicit;
   int32_t sweeps;
   int32_t flags;
+  double a_noise_rel;
 };
 
 // ---------------------------------------------------------------------------

@@ -37,6 +37,8 @@ hipError_t launch_pack_f32(const double* src, int64_t rows, int cols, int64_t ld
                            int LP, hipStream_t st);
 hipError_t launch_cast_f32(const double* Q, int64_t n_elem, float* Xc, hipStream_t st);
 hipError_t launch_zero_lower(double* R, int l, hipStream_t st);
+hipError_t launch_diag_pass(const double* sigma, int64_t n, int LP, const double* X, double* T, double* normp,
+                            int nparts, hipStream_t st);
 int skinny_rows_per_block(int a_type, int64_t OUT);
 int skinny_step(int a_type);
 // gemm_bf16.hip
@@ -68,6 +70,20 @@ hipError_t launch_signfix(const double* U64, int64_t m, const double* V64, int64
 hipError_t launch_finalize(const double* normp, int nparts, const double* sv, int k, void* info,
                            hipStream_t st);
 hipError_t launch_info_init(void* info, hipStream_t st);
+// mlp.hip
+int mlp_param_count();
+size_t mlp_work_floats(int B);
+hipError_t launch_mlp_forward(const float* P, const float* X, int B, float* Y, float* work, hipStream_t st);
+hipError_t launch_mlp_backward(const float* P, const float* X, const float* T, int B, float* G, float* loss,
+                               float* work, hipStream_t st);
+hipError_t launch_mlp_adam(float* P, const float* G, float* M, float* V, int64_t step, float lr, float beta1,
+                           float beta2, float eps, hipStream_t st);
+hipError_t launch_features(const double* sv, int l, float* feat, hipStream_t st);
+// residual.hip
+int64_t residual_parts(int64_t m, int64_t n);
+hipError_t launch_residual(int a_type, const void* A, int64_t lda, int64_t m, int64_t n, const double* U,
+                           int64_t ldu, const double* S, const double* V, int64_t ldv, int k, int KP, double* part,
+                           void* info, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 
 namespace {
@@ -115,17 +131,18 @@ struct Plan {
   int es;
   int max_sweeps;
   int refine;     // BF16: projection pass with Q2 = hi + lo
+  int residual;   // explicit residual pass after the lift
   int64_t ldt;    // BF16: leading dimension of the transposed skinny operands
   int rt_nn, rt_tn, rt_proj;  // BF16: rows (NN) / columns (TN) of A per workgroup = 64 rt
   Split projb;    // BF16: split of the refinement projection pass
   Split nn, tn, gram_m, gram_n, proj;
   int nn_blocks;
   size_t off_info, off_xc, off_t1, off_t2, off_w, off_u64, off_v64, off_p, off_normp;
-  size_t off_g, off_rinv, off_m, off_ut, off_vt, off_vg, off_pval, off_pidx, off_sgn, off_skip;
+  size_t off_g, off_rinv, off_m, off_ut, off_vt, off_vg, off_pval, off_pidx, off_sgn, off_skip, off_res;
   size_t total;
 };
 
-int elem_size(int t) { return t == SORSVD_F64 ? 8 : (t == SORSVD_F32 ? 4 : 2); }
+int elem_size(int t) { return (t == SORSVD_F64 || t == SORSVD_DIAG) ? 8 : (t == SORSVD_F32 ? 4 : 2); }
 
 size_t partial_bytes(int64_t OUT, int64_t LP, const Split& s, int acc) {
   return (size_t)s.nsplit * OUT * LP * acc;
@@ -133,29 +150,33 @@ size_t partial_bytes(int64_t OUT, int64_t LP, const Split& s, int acc) {
 
 int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const sorsvd_opts* o,
               Plan* p) {
-  if (a_type != SORSVD_F64 && a_type != SORSVD_F32 && a_type != SORSVD_BF16) return SORSVD_EINVAL;
+  if (a_type != SORSVD_F64 && a_type != SORSVD_F32 && a_type != SORSVD_BF16 && a_type != SORSVD_DIAG)
+    return SORSVD_EINVAL;
   if (m < 1 || n < 1 || k < 1 || q < 0) return SORSVD_EINVAL;
+  if (a_type == SORSVD_DIAG && m != n) return SORSVD_EINVAL;
+  if (a_type == SORSVD_DIAG && o && o->residual) return SORSVD_EUNSUPPORTED;
   const int64_t l = (o && o->l > 0) ? o->l : k;
   if (k > l || l > std::min(m, n)) return SORSVD_EINVAL;
   const int64_t LP = round_up(l, kTile), KP = round_up(k, kTile);
   if (LP > kMaxLP) return SORSVD_EUNSUPPORTED;
-  if (o && o->residual) return SORSVD_EUNSUPPORTED;
   p->a_type = a_type; p->m = m; p->n = n; p->k = k; p->l = l; p->LP = LP; p->KP = KP; p->q = q;
   p->es = elem_size(a_type);
   p->max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
   p->refine = (a_type == SORSVD_BF16 && o && o->refine) ? 1 : 0;
+  p->residual = (o && o->residual) ? 1 : 0;
   p->ldt = round_up(std::max(m, n), 128) + 128;  // room for the last step's over-read
   const int forced = o ? o->split : 0;
-  const int ks = skinny_step(a_type);
-  const int acc = a_type == SORSVD_F64 ? 8 : 4;
+  const int ks = skinny_step(a_type == SORSVD_DIAG ? SORSVD_F64 : a_type);
+  const int acc = (a_type == SORSVD_F64 || a_type == SORSVD_DIAG) ? 8 : 4;
   // BF16 tiles: wide workgroups amortise the re-read of the skinny operand
   // (an opts override serves tuning sweeps)
   const int tile_opt = o ? o->tile : 0;
   p->rt_nn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
   p->rt_tn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
   p->rt_proj = tile_opt ? std::min(tile_opt, p->refine && LP > 32 ? 2 : 4) : (p->refine ? (LP <= 32 ? 4 : 2) : p->rt_nn);
-  const int rpb_m = a_type == SORSVD_BF16 ? 64 * p->rt_nn : skinny_rows_per_block(a_type, m);
-  const int rpb_n = a_type == SORSVD_BF16 ? 64 * p->rt_tn : skinny_rows_per_block(a_type, n);
+  const int t64 = a_type == SORSVD_DIAG ? SORSVD_F64 : a_type;
+  const int rpb_m = a_type == SORSVD_BF16 ? 64 * p->rt_nn : skinny_rows_per_block(t64, m);
+  const int rpb_n = a_type == SORSVD_BF16 ? 64 * p->rt_tn : skinny_rows_per_block(t64, n);
   const int ks_nn = a_type == SORSVD_BF16 ? bf16_step(false, p->rt_nn) : ks;
   const int ks_tn = a_type == SORSVD_BF16 ? bf16_step(true, p->rt_tn) : ks;
   p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced);
@@ -198,6 +219,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->off_pidx = L.take((size_t)kSignBlocks * KP * 8);
   p->off_sgn = L.take((size_t)KP * 8);
   p->off_skip = L.take(64);
+  p->off_res = p->residual ? L.take((size_t)2 * residual_parts(m, n) * 8) : 0;
   p->total = L.total;
   return SORSVD_OK;
 }
@@ -266,7 +288,10 @@ int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, 
     }
   }
   if (e0) SORSVD_TRY(hipEventRecord(e0, st));
-  if (p.a_type == SORSVD_F64) {
+  if (p.a_type == SORSVD_DIAG) {
+    SORSVD_TRY(launch_diag_pass((const double*)A, p.n, LP, (const double*)Xc, T, normp, p.nn_blocks, st));
+    if (e1) SORSVD_TRY(hipEventRecord(e1, st));
+  } else if (p.a_type == SORSVD_F64) {
     double* P = at<double>(ws, p.off_p);
     SORSVD_TRY(launch_skinny_f64(trans, (const double*)A, lda, OUT, K, (const double*)Xc, LP, LP,
                                  sp.kchunk, sp.nsplit, P, normp, nullptr, st, T));
@@ -304,7 +329,7 @@ int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, 
 const void* as_operand(const Plan& p, const double* Q, int64_t rows, void* ws, hipStream_t st, int* rc,
                        bool for_tn = false, bool with_lo = false) {
   *rc = SORSVD_OK;
-  if (p.a_type == SORSVD_F64) return Q;
+  if (p.a_type == SORSVD_F64 || p.a_type == SORSVD_DIAG) return Q;
   if (p.a_type == SORSVD_BF16) {
     bf16_t* XT = at<bf16_t>(ws, p.off_xc);
     if (launch_cast_bf16_t(Q, rows, (int)p.LP, p.ldt, for_tn ? 1 : 0, with_lo ? 1 : 0, XT, st) != hipSuccess)
@@ -329,7 +354,7 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
 
   // Omega, n x l (Alg. 3 / Alg. 4 step 1), straight into the compute-type operand.
   void* Xc = at<void>(ws, p.off_xc);
-  if (p.a_type == SORSVD_F64) {
+  if (p.a_type == SORSVD_F64 || p.a_type == SORSVD_DIAG) {
     SORSVD_TRY(launch_fill((double*)Xc, p.n * LP, 0.0, st));
     SORSVD_TRY(launch_omega_rowmajor_f64(seed, p.n, p.l, (double*)Xc, LP, st));
   } else if (p.a_type == SORSVD_F32) {
@@ -386,6 +411,54 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
                             at<int64_t>(ws, p.off_pidx), kSignBlocks, at<double>(ws, p.off_sgn), U, ldu,
                             V, ldv, st));
   SORSVD_TRY(launch_finalize(normp, p.nn_blocks, S, (int)p.k, info, st));
+  // Error check as one more pass (the identity above is free; this one is
+  // exact up to the pass arithmetic, and for BF16 A also measures the
+  // rounding of A to BF16).
+  if (p.residual)
+    SORSVD_TRY(launch_residual(p.a_type, A, lda, p.m, p.n, U, ldu, S, V, ldv, (int)p.k, (int)KP,
+                               at<double>(ws, p.off_res), info, st));
+  return SORSVD_OK;
+}
+
+// Probe of the (k, q) predictor: Y0 = A Omega[:, :l], l = min(128, m, n), the
+// same draw as a SOR-SVD with that seed (Omega is nested in its width); the
+// singular values of Y0 are those of R in Y0 = Q R; features as in
+// launch_features. p: plan with k = l, q = 0.
+int probe(const Plan& p, const void* A, int64_t lda, uint64_t seed, float* feat, void* ws, hipStream_t st) {
+  const int LP = (int)p.LP, KP = (int)p.KP;
+  void* info = at<void>(ws, p.off_info);
+  double* T1 = at<double>(ws, p.off_t1);
+  double* Wc = at<double>(ws, p.off_w);
+  double* normp = at<double>(ws, p.off_normp);
+  int rc;
+  SORSVD_TRY(launch_info_init(info, st));
+  void* Xc = at<void>(ws, p.off_xc);
+  if (p.a_type == SORSVD_F64 || p.a_type == SORSVD_DIAG) {
+    SORSVD_TRY(launch_fill((double*)Xc, p.n * LP, 0.0, st));
+    SORSVD_TRY(launch_omega_rowmajor_f64(seed, p.n, p.l, (double*)Xc, LP, st));
+  } else if (p.a_type == SORSVD_F32) {
+    SORSVD_TRY(launch_fill((double*)Xc, (p.n * LP * 4 + 7) / 8, 0.0, st));
+    SORSVD_TRY(launch_omega_rowmajor_f32(seed, p.n, p.l, (float*)Xc, LP, st));
+  } else {
+    SORSVD_TRY(launch_fill((double*)Xc, LP * p.ldt * 2 / 8, 0.0, st));
+    SORSVD_TRY(launch_omega_bf16_t(seed, p.n, p.l, (bf16_t*)Xc, p.ldt, st));
+  }
+  if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
+  SORSVD_TRY(launch_pack_f64(T1, p.m, LP, LP, Wc, LP, st));
+  if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+  double* P = at<double>(ws, p.off_p);
+  double* G = at<double>(ws, p.off_g);
+  SORSVD_TRY(launch_skinny_f64(true, T1, LP, LP, p.m, Wc, LP, LP, p.gram_m.kchunk, p.gram_m.nsplit, P, nullptr,
+                               nullptr, st));
+  SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.gram_m.nsplit, G, LP, LP, st));
+  double* Ut = at<double>(ws, p.off_ut);
+  double* Vt = at<double>(ws, p.off_vt);
+  double* sv = at<double>(ws, p.off_sgn);
+  SORSVD_TRY(launch_fill(Ut, (int64_t)LP * KP, 0.0, st));
+  SORSVD_TRY(launch_fill(Vt, (int64_t)LP * KP, 0.0, st));
+  SORSVD_TRY(launch_jacobi(G, LP, (int)p.l, (int)p.l, p.max_sweeps, Ut, sv, Vt, KP, at<double>(ws, p.off_vg),
+                           info, st));
+  SORSVD_TRY(launch_features(sv, (int)p.l, feat, st));
   return SORSVD_OK;
 }
 
@@ -426,7 +499,7 @@ int sorsvd(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, int
   const int rc = make_plan(m, n, k, q, a_type, opts, &p);
   if (rc != SORSVD_OK) return rc;
   if (!A || !U || !S || !V || !workspace) return SORSVD_EINVAL;
-  if (lda < n || ldu < k || ldv < k) return SORSVD_EINVAL;
+  if ((lda < n && a_type != SORSVD_DIAG) || ldu < k || ldv < k) return SORSVD_EINVAL;
   if (ws_bytes < p.total) return SORSVD_EWORKSPACE;
   if (((uintptr_t)workspace) % kAlign) return SORSVD_EINVAL;
   return run(p, A, lda, seed, U, ldu, S, V, ldv, workspace, (hipStream_t)stream);
@@ -480,7 +553,7 @@ static int pack_operand(const Plan& p, const double* src, int64_t rows, int64_t 
     *out = as_operand(p, tmp, rows, ws, st, &rc, for_tn, with_lo);
     return rc;
   }
-  if (p.a_type == SORSVD_F64) {
+  if (p.a_type == SORSVD_F64 || p.a_type == SORSVD_DIAG) {
     double* d = at<double>(ws, p.off_xc);
     SORSVD_TRY(launch_pack_f64(src, rows, (int)l, l, d, (int)p.LP, st));
     *out = d;
@@ -625,6 +698,185 @@ int sorsvd_pass_timing_read(double* total_ms, int64_t* launches, double* bytes, 
   return SORSVD_OK;
 }
 
+// ------------------------------------------------------------------ learned (k, q)
+
+static int probe_plan(int64_t m, int64_t n, int32_t a_type, Plan* p) {
+  const int64_t l = std::min<int64_t>(kMaxLP, std::min(m, n));
+  sorsvd_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.l = l;
+  return make_plan(m, n, l, 0, a_type, &o, p);
+}
+
+size_t sorsvd_probe_workspace_bytes(int64_t m, int64_t n, int32_t a_type) {
+  Plan p;
+  return probe_plan(m, n, a_type, &p) == SORSVD_OK ? p.total : 0;
+}
+
+int sorsvd_probe_features(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed,
+                          float* features, void* workspace, size_t ws_bytes, void* stream) {
+  Plan p;
+  const int rc = probe_plan(m, n, a_type, &p);
+  if (rc) return rc;
+  if (!A || !features || !workspace || (lda < n && a_type != SORSVD_DIAG)) return SORSVD_EINVAL;
+  if (ws_bytes < p.total) return SORSVD_EWORKSPACE;
+  if (((uintptr_t)workspace) % kAlign) return SORSVD_EINVAL;
+  return probe(p, A, lda, seed, features, workspace, (hipStream_t)stream);
+}
+
+int32_t sorsvd_mlp_param_count(void) { return mlp_param_count(); }
+
+size_t sorsvd_mlp_work_floats(int32_t batch) { return batch < 1 ? 0 : mlp_work_floats(batch); }
+
+int sorsvd_mlp_forward(const float* params, const float* X, int32_t batch, float* Y, float* work, void* stream) {
+  if (!params || !X || !Y || !work || batch < 1) return SORSVD_EINVAL;
+  SORSVD_TRY(launch_mlp_forward(params, X, batch, Y, work, (hipStream_t)stream));
+  return SORSVD_OK;
+}
+
+int sorsvd_mlp_backward(const float* params, const float* X, const float* T, int32_t batch, float* grad,
+                        float* loss, float* work, void* stream) {
+  if (!params || !X || !T || !grad || !loss || !work || batch < 1) return SORSVD_EINVAL;
+  SORSVD_TRY(launch_mlp_backward(params, X, T, batch, grad, loss, work, (hipStream_t)stream));
+  return SORSVD_OK;
+}
+
+int sorsvd_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
+                    float beta2, float eps, void* stream) {
+  if (!params || !grad || !m || !v || step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return SORSVD_EINVAL;
+  SORSVD_TRY(launch_mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream));
+  return SORSVD_OK;
+}
+
+int sorsvd_mlp_train_step(float* params, float* m, float* v, const float* X, const float* T, int32_t batch,
+                          int64_t step, float lr, float* grad, float* loss, float* work, void* stream) {
+  int rc = sorsvd_mlp_backward(params, X, T, batch, grad, loss, work, stream);
+  if (rc) return rc;
+  return sorsvd_mlp_adam(params, grad, m, v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+static constexpr double kAutoMargin = 1.25;  // head-room on the predicted width
+static constexpr int kAutoFallbackQ = 2;
+
+static int auto_plan(int64_t m, int64_t n, int32_t a_type, Plan* p) {
+  const int64_t kcap = std::min<int64_t>(kMaxLP, std::min(m, n));
+  sorsvd_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.refine = a_type == SORSVD_BF16 ? 1 : 0;
+  o.residual = 1;
+  return make_plan(m, n, kcap, 3, a_type, &o, p);
+}
+
+static size_t auto_tail_bytes() { return 256 + 4096 + round_up((int64_t)mlp_work_floats(1) * 4, 256); }
+
+// Largest workspace of any run sorsvd_auto may start (k a multiple of 8 or the
+// cap, any q <= 3) and of the probe; the tail (features, outputs, network
+// scratch) follows it.
+static size_t auto_main_bytes(int64_t m, int64_t n, int32_t a_type) {
+  Plan p;
+  if (auto_plan(m, n, a_type, &p) != SORSVD_OK) return 0;
+  size_t mx = p.total;
+  const int64_t kcap = p.k;
+  sorsvd_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.refine = a_type == SORSVD_BF16 ? 1 : 0;
+  o.residual = 1;
+  for (int64_t k = 8; k < kcap; k += 8) {
+    Plan pk;
+    if (make_plan(m, n, k, 3, a_type, &o, &pk) == SORSVD_OK) mx = std::max(mx, pk.total);
+  }
+  Plan pp;
+  if (probe_plan(m, n, a_type, &pp) == SORSVD_OK) mx = std::max(mx, pp.total);
+  return round_up((int64_t)mx, kAlign);
+}
+
+size_t sorsvd_auto_workspace_bytes(int64_t m, int64_t n, int32_t a_type) {
+  const size_t mb = auto_main_bytes(m, n, a_type);
+  return mb ? mb + auto_tail_bytes() : 0;
+}
+
+int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed, double tol,
+                const float* params, double* U, int64_t ldu, double* S, double* V, int64_t ldv, void* workspace,
+                size_t ws_bytes, void* stream, sorsvd_auto_info* out) {
+  Plan big;
+  int rc = auto_plan(m, n, a_type, &big);
+  if (rc) return rc;
+  const int64_t kcap = big.k;
+  if (!A || !U || !S || !V || !workspace || !out || lda < n || ldu < kcap || ldv < kcap || !(tol > 0.0))
+    return SORSVD_EINVAL;
+  const size_t main_bytes = auto_main_bytes(m, n, a_type);
+  if (ws_bytes < main_bytes + auto_tail_bytes()) return SORSVD_EWORKSPACE;
+  if (((uintptr_t)workspace) % kAlign) return SORSVD_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  std::memset(out, 0, sizeof(*out));
+  char* tail = (char*)workspace + main_bytes;
+  float* feat = (float*)(tail + 256);
+  float* y = feat + 128;
+  float* work = (float*)(tail + 256 + 4096);
+  const double ridge = a_type == SORSVD_BF16 ? 312.0 : 39.0;  // width where a pass turns MFMA-bound
+  int64_t k = kcap;
+  int q = kAutoFallbackQ;
+  bool predicted = false;
+  if (params) {
+    Plan pp;
+    if ((rc = probe_plan(m, n, a_type, &pp))) return rc;
+    if ((rc = probe(pp, A, lda, seed, feat, workspace, st))) return rc;
+    SORSVD_TRY(launch_mlp_forward(params, feat, 1, y, work, st));
+    float yh[4];
+    SORSVD_TRY(hipMemcpyAsync(yh, y, sizeof(yh), hipMemcpyDeviceToHost, st));
+    SORSVD_TRY(hipStreamSynchronize(st));
+    double best = 1e300;
+    for (int qq = 0; qq < 4; ++qq) {
+      out->k_pred[qq] = yh[qq] == yh[qq] ? std::exp2((double)yh[qq]) : 1e30;
+      const double kk = std::ceil(kAutoMargin * out->k_pred[qq] / 8.0) * 8.0;
+      if (!(kk <= (double)kcap)) continue;
+      const int64_t ki = std::max<int64_t>(1, (int64_t)kk);
+      const double cost = (2.0 * qq + 3.0) * std::max(1.0, (double)ki / ridge);
+      if (cost < best) {
+        best = cost;
+        k = ki;
+        q = qq;
+        predicted = true;
+      }
+    }
+  }
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    sorsvd_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.refine = a_type == SORSVD_BF16 ? 1 : 0;
+    o.residual = a_type == SORSVD_BF16 ? 1 : 0;  // BF16: the identity cannot resolve 1e-3
+    Plan p;
+    if ((rc = make_plan(m, n, k, q, a_type, &o, &p))) return rc;
+    if ((rc = run(p, A, lda, seed, U, ldu, S, V, ldv, workspace, st))) return rc;
+    sorsvd_info info;
+    SORSVD_TRY(hipMemcpyAsync(&info, workspace, sizeof(info), hipMemcpyDeviceToHost, st));
+    SORSVD_TRY(hipStreamSynchronize(st));
+    double e = info.err_fro;
+    if (o.residual) {
+      // error against A before rounding: the rounding noise E (expected size
+      // a_noise_rel) adds to the stored residual except for the part the rank-k
+      // subspaces capture, at most rho = k (m^-1/2 + n^-1/2)^2 of it (the top-k
+      // singular values of an m x n noise matrix); judge with that worst case
+      const double es = info.err_fro_explicit, nz = info.a_noise_rel;
+      const double rho = std::min(1.0, (double)k * std::pow(1.0 / std::sqrt((double)m) + 1.0 / std::sqrt((double)n), 2.0));
+      e = std::sqrt(std::max(es * es - (1.0 - 2.0 * rho) * nz * nz, 0.0));
+    }
+    out->runs += 1;
+    out->k_used = (int32_t)k;
+    out->q_used = q;
+    out->err = e;
+    out->used_fallback = (attempt > 0 || !predicted) ? 1 : 0;
+    out->flags = info.flags;
+    if (e <= tol) return SORSVD_OK;
+    if (!predicted || (k == kcap && q >= kAutoFallbackQ)) break;
+    k = kcap;  // fallback
+    q = kAutoFallbackQ;
+  }
+  return SORSVD_ETOL;
+}
+
 const char* sorsvd_status_string(int status) {
   switch (status) {
     case SORSVD_OK: return "ok";
@@ -633,6 +885,7 @@ const char* sorsvd_status_string(int status) {
     case SORSVD_EHIP: return "HIP runtime error";
     case SORSVD_ENOCONV: return "Jacobi sweep cap reached";
     case SORSVD_ENONFINITE: return "non-finite input";
+    case SORSVD_ETOL: return "tolerance not met";
     case SORSVD_EUNSUPPORTED: return "unsupported in this build";
     default: return "unknown status";
   }

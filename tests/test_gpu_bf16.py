@@ -124,3 +124,29 @@ def test_bf16_whole_method(lib, m, n, k, q):
     # ||A||_F of a BF16 matrix is accumulated from FP32 sums of 8 exact squares
     # (relative rounding 2^-24 each), then in FP64
     assert abs(info["a_fro"] - io["a_fro"]) <= 1e-7 * io["a_fro"]
+
+
+def test_bf16_explicit_residual_and_rounding_noise(lib):
+    """The residual pass measures the error against the stored BF16 matrix and
+    the rounding noise of storing it; their difference of squares estimates the
+    error against the matrix before rounding."""
+    m, n, k = 3000, 1000, 64
+    sigma = 1.0 / np.arange(1, n + 1) ** 2.0
+    A, _, _ = W.spectral(m, n, sigma, 23)
+    As = to_bf16(A)
+    U, S, V, info = lib.sorsvd(dev_bf16(A), k, q=1, seed=3, refine=1, residual=1)
+    U, S, V = host(U), host(S), host(V)
+    Ahat = (U * S) @ V.T
+    e_stored = np.linalg.norm(As - Ahat) / np.linalg.norm(As)
+    assert abs(info["err_fro_explicit"] - e_stored) <= 1e-4 * e_stored
+    noise = np.linalg.norm(As - A) / np.linalg.norm(As)
+    assert abs(info["a_noise_rel"] - noise) <= 0.02 * noise, (info["a_noise_rel"], noise)
+    e_true = np.linalg.norm(A - Ahat) / np.linalg.norm(A)
+    # the rounding noise adds to the stored residual except for the share a
+    # rank-k fit absorbs, at most rho = k (m^-1/2 + n^-1/2)^2 of it
+    es2, nz2 = info["err_fro_explicit"] ** 2, info["a_noise_rel"] ** 2
+    rho = k * (m ** -0.5 + n ** -0.5) ** 2
+    low = np.sqrt(max(es2 - nz2, 0.0))
+    high = np.sqrt(max(es2 - (1 - 2 * rho) * nz2, 0.0))
+    print(f"stored {e_stored:.4e} noise {noise:.4e} true {e_true:.4e} bounds [{low:.4e}, {high:.4e}]")
+    assert low <= 1.01 * e_true and e_true <= 1.01 * high

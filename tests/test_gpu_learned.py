@@ -1,0 +1,124 @@
+"""The learned (k, q) part on the GPU: network kernels against the FP64 oracle
+(forward <= 1e-5, gradients <= 1e-4 normwise per tensor, the loss over 10
+Adam steps on one minibatch stream <= 1e-4 relative), probe features against
+the oracle's definition, the diagonal form of the method against the oracle on
+the dense diagonal matrix, and the judge / fallback logic of sorsvd_auto."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp as omlp
+from oracle import sorsvd as osvd
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev32(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _params(seed):
+    return (omlp.init_params(seed) + 0.05 * np.random.default_rng(seed + 1).standard_normal(omlp.N_PARAMS)).astype(
+        np.float32)
+
+
+def _batch(seed, B):
+    gen = np.random.default_rng(seed)
+    return (gen.uniform(-1, 0, size=(B, 128)).astype(np.float32), gen.uniform(2, 8, size=(B, 4)).astype(np.float32))
+
+
+@pytest.mark.parametrize("B", [1, 37, 256])
+def test_mlp_forward_matches_oracle(lib, B):
+    p = _params(3)
+    X, _ = _batch(4, B)
+    net = lib.MLP(dev32(p), max_batch=256)
+    Y = host(net.forward(dev32(X)))
+    Yo, _, _ = omlp.forward(p.astype(np.float64), X.astype(np.float64))
+    assert np.abs(Y - Yo).max() <= 1e-5 * max(1.0, np.abs(Yo).max())
+
+
+def test_mlp_gradient_matches_oracle(lib):
+    p = _params(5)
+    X, T = _batch(6, 200)
+    net = lib.MLP(dev32(p), max_batch=256)
+    g, loss = net.backward(dev32(X), dev32(T))
+    g = host(g)
+    Lo, go = omlp.backward(p.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    assert abs(float(loss) - Lo) <= 1e-5 * Lo
+    off = 0
+    for name, shape in omlp.SIZES:
+        size = int(np.prod(shape))
+        a, b = g[off:off + size], go[off:off + size]
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b), name
+        off += size
+
+
+def test_training_curve_matches_oracle(lib):
+    p = _params(7)
+    net = lib.MLP(dev32(p), max_batch=256)
+    th = p.astype(np.float64)
+    m, v = np.zeros_like(th), np.zeros_like(th)
+    for step in range(1, 11):
+        X, T = _batch(100 + step, 128)
+        loss = float(net.train_step(dev32(X), dev32(T), lr=1e-3))
+        Lo, go = omlp.backward(th, X.astype(np.float64), T.astype(np.float64))
+        th, m, v = omlp.adam_step(th, go, m, v, step, lr=1e-3)
+        assert abs(loss - Lo) <= 1e-4 * Lo, (step, loss, Lo)
+    assert np.abs(host(net.params) - th).max() <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(600, 400), (300, 900), (2000, 128)])
+def test_probe_features_match_oracle(lib, shape):
+    m, n = shape
+    A, _, _ = W.spectral(m, n, 0.9 ** np.arange(min(m, n)), 3 + m)
+    f = host(lib.probe_features(torch.as_tensor(A).cuda(), seed=11))
+    fo = omlp.probe_features(A, 11)
+    assert np.abs(f - fo).max() <= 2e-6
+
+
+def test_probe_features_of_diagonal(lib):
+    sigma = np.arange(1, 1501, dtype=np.float64) ** -1.2
+    f = host(lib.probe_features(torch.as_tensor(sigma).cuda(), seed=4))
+    fo = omlp.probe_features(np.diag(sigma), 4)
+    assert np.abs(f - fo).max() <= 2e-6
+
+
+@pytest.mark.parametrize("k,q", [(10, 0), (24, 2), (64, 1)])
+def test_diagonal_form_matches_oracle(lib, k, q):
+    sigma = 0.95 ** np.arange(300)
+    U, S, V, info = lib.sorsvd_diag(torch.as_tensor(sigma).cuda(), k, q=q, seed=8)
+    Uo, So, Vo, io = osvd.sorsvd(np.diag(sigma), k, q=q, seed=8)
+    assert np.max(np.abs(host(S) - So)) <= 1e-10 * So[0]
+    assert abs(info["err_fro"] - io["err_fro_identity"]) <= 1e-9
+    d = So >= 1e-4 * So[0]
+    assert np.abs(host(U)[:, d] - Uo[:, d]).max() <= 1e-7
+
+
+def test_batched_diagonal_equals_single(lib):
+    sig = [torch.as_tensor(0.9 ** np.arange(n)).cuda() for n in (500, 777, 2048)]
+    specs = [(8, 0), (40, 1), (128, 3)]
+    b = lib.Batch(sig, [k for k, _ in specs], [q for _, q in specs], [5, 6, 7])
+    b.run()
+    infos = b.info()
+    for i, (s, (k, q)) in enumerate(zip(sig, specs)):
+        _, S, _, info = lib.sorsvd_diag(s, k, q=q, seed=5 + i)
+        assert torch.allclose(b.S[i], S, rtol=0, atol=1e-12)
+        assert abs(infos[i]["err_fro"] - info["err_fro"]) <= 1e-10
+
+
+def test_auto_fallback_and_judge(lib):
+    # fast decay: the fallback (k = 128, q = 2) meets 1e-3; the identity is the FP32 judge
+    n = 1500
+    A, _, _ = W.spectral(n, n, np.arange(1, n + 1) ** -2.5, 9)
+    U, S, V, info = lib.auto(torch.as_tensor(A, dtype=torch.float32).cuda(), 1e-3, None, seed=1)
+    assert info["met"] and info["used_fallback"] == 1 and info["k_used"] == 128 and info["q_used"] == 2
+    assert info["err"] <= 1e-3
+    # slow decay: nothing of width <= 128 meets 1e-3 -> ETOL with the fallback's result
+    B, _, _ = W.spectral(n, n, np.arange(1, n + 1) ** -0.8, 10)
+    _, _, _, info2 = lib.auto(torch.as_tensor(B, dtype=torch.float32).cuda(), 1e-3, None, seed=1)
+    assert not info2["met"] and info2["err"] > 1e-3

@@ -245,3 +245,33 @@ def test_seed_changes_draw_not_leading_values(lib):
     assert not np.array_equal(S1, S2)
     assert np.all(S1 <= sigma[:10] * (1 + 1e-12)) and np.all(S2 <= sigma[:10] * (1 + 1e-12))
     assert normwise(S1[:5], S2[:5]) < 1e-4
+
+
+# ------------------------------------------------------------------ explicit residual (error check)
+
+@pytest.mark.parametrize("m,n,k,q", [(1000, 800, 20, 0), (333, 1200, 48, 1), (2500, 700, 128, 1)])
+def test_explicit_residual_fp64(lib, m, n, k, q):
+    A = W.low_rank_plus_noise(m, n, 30, 1e-3, m + n + k)
+    U, S, V, info = lib.sorsvd(dev(A), k, q=q, seed=5, residual=1)
+    _, _, _, io = osvd.sorsvd(A, k, q=q, seed=5)
+    e = info["err_fro_explicit"]
+    assert abs(e - io["err_fro"]) <= 1e-10 * max(io["err_fro"], 1e-6), (e, io["err_fro"])
+    assert info["a_noise_rel"] == 0.0
+    # the explicit value and the identity agree where the error is not tiny
+    assert abs(e - info["err_fro"]) <= 1e-6
+
+
+def test_explicit_residual_fp32_on_stored_values(lib):
+    sigma = 1.0 / np.arange(1, 1301) ** 1.5
+    A, _, _ = W.spectral(1500, 1300, sigma, 17)
+    A32 = A.astype(np.float32)
+    _, _, _, info = lib.sorsvd(dev(A32, torch.float32), 40, q=1, seed=6, residual=1)
+    _, _, _, io = osvd.sorsvd(A32.astype(np.float64), 40, q=1, seed=6)
+    assert abs(info["err_fro_explicit"] - io["err_fro"]) <= 1e-3 * io["err_fro"]
+
+
+def test_residual_of_exact_low_rank_is_tiny(lib):
+    gen = W.rng(44)
+    A = gen.standard_normal((700, 12)) @ gen.standard_normal((12, 530))
+    _, _, _, info = lib.sorsvd(dev(A), 12, q=0, seed=2, residual=1)
+    assert info["err_fro_explicit"] < 1e-13

@@ -180,3 +180,46 @@ def c5_torch(device="cuda", n=32768, seed=5):
     torch = _torch()
     return spectral_torch(n, n, sigma_power(n, 1.5), seed, device, torch.bfloat16)
 
+
+
+# ----------------------------------------------------------------- (k, q) predictor spectra
+
+C5_SIZES = (4096, 8192, 16384, 32768)
+
+
+def c5_training_spectra(count=10000, seed=55, sizes=C5_SIZES):
+    """Training spectra of the (k, q) predictor: a third each of
+      j^-alpha, alpha ~ U[0.5, 3];  beta^j, beta ~ U[0.8, 0.99];
+      rank r ~ U[4, 256] signal (values U[0.2, 1], sorted) plus a noise floor of
+      relative Frobenius size 10^U[-6, -2] (quarter-circle profile);
+    size n drawn from `sizes`. Returns a list of (kind, n, sigma) with sigma
+    descending, FP64."""
+    gen = rng(seed)
+    out = []
+    for i in range(count):
+        kind = i % 3
+        n = int(gen.choice(sizes))
+        j = np.arange(1, n + 1, dtype=np.float64)
+        if kind == 0:
+            s = j ** (-gen.uniform(0.5, 3.0))
+        elif kind == 1:
+            s = gen.uniform(0.8, 0.99) ** j
+        else:
+            r = int(gen.integers(4, 257))
+            sig = np.sort(gen.uniform(0.2, 1.0, size=r))[::-1]
+            nu = 10.0 ** gen.uniform(-6.0, -2.0)
+            x = (np.arange(n - r, dtype=np.float64) + 0.5) / (n - r)
+            floor = np.sqrt(np.maximum(1.0 - x * x, 0.0))           # quarter-circle quantile profile
+            floor *= nu * np.linalg.norm(sig) / np.linalg.norm(floor)
+            s = np.sort(np.concatenate([sig, floor]))[::-1]
+        out.append((kind, n, s / s[0]))
+    return out
+
+
+def ey_relative(sigma, kmax):
+    """Eckart-Young relative Frobenius floor e_k for k = 0..kmax (Th. 1)."""
+    s2 = np.asarray(sigma, dtype=np.float64) ** 2
+    tail = np.cumsum(s2[::-1])[::-1]                                # tail[k] = sum_{j >= k} s_j^2
+    tot = tail[0]
+    ks = np.arange(kmax + 1)
+    return np.sqrt(np.where(ks < s2.size, tail[np.minimum(ks, s2.size - 1)], 0.0) / tot)
