@@ -82,10 +82,10 @@ typedef struct sorsvd_info {
                               rounding: a sketch condition number near 1/u) */
   double a_noise_rel;      /* opts.residual with BF16 A: sqrt(sum ulp(a_ij)^2 / 12) / ||A||_F, the
                               expected relative size of the rounding of A to BF16; the error
-                              against A before rounding lies between
-                              sqrt(err_fro_explicit^2 - a_noise_rel^2) and
-                              sqrt(err_fro_explicit^2 - (1 - 2 rho) a_noise_rel^2),
-                              rho = min(1, k (m^-1/2 + n^-1/2)^2). 0 otherwise */
+                              against A before rounding is about
+                              sqrt(err_fro_explicit^2 - a_noise_rel^2) plus twice the
+                              share of the noise the rank-k fit absorbs (see
+                              sorsvd_auto). 0 otherwise */
 } sorsvd_info;
 
 /* Workspace size in bytes for sorsvd() with the same arguments. Returns 0 for
@@ -285,8 +285,11 @@ void sorsvd_batch_destroy(sorsvd_batch* b);
  *   (k_ridge 312 for BF16, 39 otherwise). Judge: the error identity
  *   (FP32/FP64), or for BF16 the explicit residual corrected for the rounding
  *   of A to BF16: sqrt(err_fro_explicit^2 - (1 - 2 rho) a_noise_rel^2) with
- *   rho = min(1, k (m^-1/2 + n^-1/2)^2), the largest share of the rounding noise
- *   a rank-k fit can absorb (so the judge errs on the safe side). If the judge
+ *   rho = min(1, 4 k (m^-1/2 + n^-1/2)^2), an allowance for the share of the
+ *   rounding noise a rank-k fit absorbs (four times the i.i.d. bound, since
+ *   BF16 rounding follows |a_ij|), so that the judge errs on the safe side.
+ *   BF16 runs take q >= 1 (with q = 0 the BF16 rounding of the skinny operand
+ *   leaves a subspace error near 1e-3). If the judge
  *   rejects, or no predicted width fits, the fallback k = min(128, m, n),
  *   q = 2 runs and is judged. params = NULL skips the network (fallback only).
  *   U, V need ldu, ldv >= min(128, m, n) (the first k_used columns are the

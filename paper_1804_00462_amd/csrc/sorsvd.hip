@@ -759,6 +759,7 @@ int sorsvd_mlp_train_step(float* params, float* m, float* v, const float* X, con
 
 static constexpr double kAutoMargin = 1.25;  // head-room on the predicted width
 static constexpr int kAutoFallbackQ = 2;
+static constexpr double kNoiseShare = 4.0;   // BF16 judge: captured rounding-noise allowance / i.i.d. bound
 
 static int auto_plan(int64_t m, int64_t n, int32_t a_type, Plan* p) {
   const int64_t kcap = std::min<int64_t>(kMaxLP, std::min(m, n));
@@ -828,8 +829,12 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     SORSVD_TRY(hipMemcpyAsync(yh, y, sizeof(yh), hipMemcpyDeviceToHost, st));
     SORSVD_TRY(hipStreamSynchronize(st));
     double best = 1e300;
+    // BF16 passes round the skinny operand: without a power step the subspace
+    // error of that rounding stays near 1e-3, so BF16 runs take q >= 1
+    const int qmin = a_type == SORSVD_BF16 ? 1 : 0;
     for (int qq = 0; qq < 4; ++qq) {
       out->k_pred[qq] = yh[qq] == yh[qq] ? std::exp2((double)yh[qq]) : 1e30;
+      if (qq < qmin) continue;
       const double kk = std::ceil(kAutoMargin * out->k_pred[qq] / 8.0) * 8.0;
       if (!(kk <= (double)kcap)) continue;
       const int64_t ki = std::max<int64_t>(1, (int64_t)kk);
@@ -857,10 +862,13 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     if (o.residual) {
       // error against A before rounding: the rounding noise E (expected size
       // a_noise_rel) adds to the stored residual except for the part the rank-k
-      // subspaces capture, at most rho = k (m^-1/2 + n^-1/2)^2 of it (the top-k
-      // singular values of an m x n noise matrix); judge with that worst case
+      // subspaces capture. For i.i.d. noise that part is at most
+      // k (m^-1/2 + n^-1/2)^2 of it (the top-k singular values of an m x n noise
+      // matrix); BF16 rounding noise follows |a_ij| and so the leading singular
+      // directions of A, and the allowance is four times the i.i.d. share
       const double es = info.err_fro_explicit, nz = info.a_noise_rel;
-      const double rho = std::min(1.0, (double)k * std::pow(1.0 / std::sqrt((double)m) + 1.0 / std::sqrt((double)n), 2.0));
+      const double rho = std::min(1.0, kNoiseShare * (double)k *
+                                           std::pow(1.0 / std::sqrt((double)m) + 1.0 / std::sqrt((double)n), 2.0));
       e = std::sqrt(std::max(es * es - (1.0 - 2.0 * rho) * nz * nz, 0.0));
     }
     out->runs += 1;

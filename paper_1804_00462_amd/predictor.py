@@ -37,6 +37,10 @@ N_LAB = 2048
 CENSORED = 8.0  # log2(256): "needs more than 128"
 WIDTH_FACTORS = (1.0, 1.1, 1.25, 1.5, 2.0, 3.0)
 PARAMS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "predictor_params.f32")
+PARAMS_FILE_BF16 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "predictor_params_bf16.f32")
+# relative Frobenius size of the rounding of a dense matrix with Gaussian-like
+# entries to BF16 (as measured by the residual pass on the evaluation matrices)
+BF16_NOISE = 1.66e-3
 
 
 def _torch():
@@ -132,12 +136,18 @@ def label_spectra(spectra, tol=TOL, batch_bytes=24e9, log=print):
     return labels
 
 
-def spectrum_features(spectra, seed0=1000, log=print):
-    """Probe features of the diagonal stand-ins at their nominal size (device, count x 128)."""
+def spectrum_features(spectra, seed0=1000, noise_rel=0.0, log=print):
+    """Probe features of the diagonal stand-ins at their nominal size (device, count x 128).
+
+    noise_rel > 0: features of the matrix as stored in a reduced precision
+    whose rounding adds isotropic noise of that relative Frobenius size: the
+    stand-in's spectrum becomes sqrt(sigma_j^2 + noise_rel^2 ||sigma||^2 / n)."""
     torch = _torch()
     feats = torch.empty(len(spectra), 128, dtype=torch.float32, device="cuda")
     t0 = time.perf_counter()
     for i, (_, n, s) in enumerate(spectra):
+        if noise_rel > 0.0:
+            s = np.sqrt(s * s + (noise_rel ** 2) * float(np.sum(s * s)) / n)
         feats[i] = api.probe_features(torch.as_tensor(s).cuda(), seed0 + i)
         if (i + 1) % 2000 == 0:
             log(f"[features] {i + 1}/{len(spectra)}, {time.perf_counter() - t0:.1f} s")
@@ -199,11 +209,76 @@ def save_params(params, path=PARAMS_FILE):
 
 
 def load_params(path=PARAMS_FILE, device="cuda"):
+    """Network weights (device FP32); path "bf16" selects the weights trained on
+    BF16-stored inputs."""
     torch = _torch()
+    if path == "bf16":
+        path = PARAMS_FILE_BF16
     p = np.fromfile(path, dtype="<f4")
     if p.size != api.mlp_param_count():
         raise ValueError(f"{path}: {p.size} values, expected {api.mlp_param_count()}")
     return torch.as_tensor(p).to(device)
+
+
+def eval_matrix(n, sigma, seed, rank=2048, device="cuda"):
+    """FP64 device matrix U diag(sigma) V^T (n x n) with Haar U, V restricted to the
+    leading `rank` singular values (the rest is dropped; for spectra that a width
+    <= 128 can resolve to 1e-3 their energy is below 1e-15 relative)."""
+    torch = _torch()
+    r = min(n, rank)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def haar(rows):
+        G = torch.randn(rows, r, generator=g, device=device, dtype=torch.float64)
+        Q, R = torch.linalg.qr(G, mode="reduced")
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1.0
+        return Q * d[None, :]
+    U, V = haar(n), haar(n)
+    s = torch.as_tensor(np.asarray(sigma[:r], dtype=np.float64), device=device)
+    return (U * s[None, :]) @ V.T
+
+
+def time_to_tolerance(A, tol, params, seed=1, reps=3):
+    """Median wall time (ms) of sorsvd_auto (probe, network, SOR-SVD, judge,
+    fallback) on a device matrix, after one warm-up call, and the last call's
+    result."""
+    torch = _torch()
+    api.auto(A, tol, params, seed)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, S, V, info = api.auto(A, tol, params, seed)
+        times.append((time.perf_counter() - t0) * 1e3)
+    info["ms"] = sorted(times)[len(times) // 2]
+    return U, S, V, info
+
+
+def true_error(A64, U, S, V):
+    torch = _torch()
+    return float(torch.linalg.norm(A64 - (U * S) @ V.T) / torch.linalg.norm(A64))
+
+
+def compare(A64, tol, params, seed=1, log=print, label=""):
+    """BF16 + learned against FP32 plain (fixed (128, 2) + judge), and the other
+    two combinations, on one FP64 matrix: time-to-tolerance and true error."""
+    torch = _torch()
+    out = {}
+    p16 = load_params("bf16") if os.path.exists(PARAMS_FILE_BF16) else params
+    for name, dt, p in (("bf16_learned", torch.bfloat16, p16), ("fp32_plain", torch.float32, None),
+                        ("fp32_learned", torch.float32, params), ("bf16_plain", torch.bfloat16, None)):
+        A = A64.to(dt)
+        U, S, V, info = time_to_tolerance(A, tol, p, seed)
+        info["true_err"] = true_error(A64, U, S, V)
+        info["met_true"] = info["true_err"] <= tol
+        out[name] = info
+        del A
+        log(f"[{label}] {name}: {info['ms']:.2f} ms, k {info['k_used']} q {info['q_used']}, "
+            f"fallback {info['used_fallback']}, judge {info['err']:.3e} ({'met' if info['met'] else 'not met'}), "
+            f"true {info['true_err']:.3e}")
+    return out
 
 
 def main(argv=None):
@@ -215,17 +290,19 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--seed", type=int, default=55)
     ap.add_argument("--out", default=PARAMS_FILE)
+    ap.add_argument("--out-bf16", default=PARAMS_FILE_BF16)
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     spectra = W.c5_training_spectra(args.count, args.seed)
     t0 = time.perf_counter()
     T = label_spectra(spectra, log=log)
     log(f"[labels] done in {time.perf_counter() - t0:.1f} s; censored {np.mean(T[:, 0] >= CENSORED):.2%}")
-    X = spectrum_features(spectra, log=log)
-    params, hist = train(X, T, epochs=args.epochs, log=log)
-    save_params(params, args.out)
     np.save(os.path.splitext(args.out)[0] + "_labels.npy", T)
-    log(f"[train] saved {args.out}")
+    for out, noise in ((args.out, 0.0), (args.out_bf16, BF16_NOISE)):
+        X = spectrum_features(spectra, noise_rel=noise, log=log)
+        params, hist = train(X, T, epochs=args.epochs, log=log)
+        save_params(params, out)
+        log(f"[train] saved {out} (input noise {noise:g})")
 
 
 if __name__ == "__main__":

@@ -122,3 +122,42 @@ def test_auto_fallback_and_judge(lib):
     B, _, _ = W.spectral(n, n, np.arange(1, n + 1) ** -0.8, 10)
     _, _, _, info2 = lib.auto(torch.as_tensor(B, dtype=torch.float32).cuda(), 1e-3, None, seed=1)
     assert not info2["met"] and info2["err"] > 1e-3
+
+
+@pytest.mark.slow
+def test_learned_choice_gains_over_fixed_fallback(lib):
+    """The trained network (committed weights) against the method without it
+    (fixed k = 128, q = 2 plus the judge), on held-out 32768 x 32768 matrices
+    with spectra a width <= 128 can resolve: every accepted result meets the
+    tolerance against the FP64 matrix, and the learned choice takes less time
+    to tolerance in total (FP32); BF16 results accepted by the judge meet the
+    tolerance too."""
+    from paper_1804_00462_amd import predictor as PR
+    params = PR.load_params()
+    n, tol = 32768, 1e-3
+    j = np.arange(1, n + 1, dtype=np.float64)
+    cases = [("j^-2.5", j ** -2.5), ("j^-2.2", j ** -2.2), ("0.9^j", 0.9 ** (j - 1))]
+    t_learned = t_plain = 0.0
+    for name, sigma in cases:
+        A64 = PR.eval_matrix(n, sigma, 300 + len(name))
+        A = A64.float()
+        Ul, Sl, Vl, il = PR.time_to_tolerance(A, tol, params, seed=2)
+        Up, Sp, Vp, ip = PR.time_to_tolerance(A, tol, None, seed=2)
+        el, ep = PR.true_error(A64, Ul, Sl, Vl), PR.true_error(A64, Up, Sp, Vp)
+        print(f"{name}: learned k {il['k_used']} q {il['q_used']} fb {il['used_fallback']} {il['ms']:.2f} ms "
+              f"err {el:.3e} | plain {ip['ms']:.2f} ms err {ep:.3e}", flush=True)
+        assert il["met"] and ip["met"]
+        assert el <= tol and ep <= tol
+        t_learned += il["ms"]
+        t_plain += ip["ms"]
+        Ab = A64.to(torch.bfloat16)
+        Ub, Sb, Vb, ib = PR.time_to_tolerance(Ab, tol, PR.load_params("bf16"), seed=2, reps=1)
+        eb = PR.true_error(A64, Ub, Sb, Vb)
+        print(f"{name}: bf16 learned k {ib['k_used']} q {ib['q_used']} fb {ib['used_fallback']} "
+              f"{ib['ms']:.2f} ms err {eb:.3e} judge {ib['err']:.3e}", flush=True)
+        if ib["met"]:
+            assert eb <= tol
+        del A64, A, Ab
+        torch.cuda.empty_cache()
+    print(f"total time to tolerance: learned {t_learned:.1f} ms, fixed {t_plain:.1f} ms", flush=True)
+    assert t_learned < 0.9 * t_plain
