@@ -36,7 +36,8 @@ constexpr int kGramRows = 512;  // rows of T per Gram work item
 constexpr int kMaxBatchLP = 128;
 constexpr int kMaxBatch = 65535;
 constexpr int kElemsPerBlock = 4096;  // element-wise kernels: elements per workgroup
-constexpr size_t kTileLds = 32 * (kMaxBatchLP + 1) * 8 + 64;
+constexpr size_t kXsBytes = (size_t)xs_elems<double, kMaxBatchLP / kTile>() * 8;  // largest staged operand
+constexpr size_t kTileLds = kXsBytes + 64;
 
 struct BProb {
   int64_t m, n;
@@ -88,7 +89,7 @@ enum Mode : int {
 template <typename TA, bool TRANS, int RT, int CT>
 __device__ void pass_item(const BProb& P, const BItem& I, int mode, bool want_norm, char* lds) {
   TA* Xs = reinterpret_cast<TA*>(lds);
-  double* red = reinterpret_cast<double*>(lds + 32 * (kMaxBatchLP + 1) * 8);
+  double* red = reinterpret_cast<double*>(lds + kXsBytes);
   const int64_t OUT = TRANS ? P.n : P.m;
   const int64_t K = TRANS ? P.m : P.n;
   double* out = mode == M_SKETCH ? P.T1 : (mode == M_ORBIT ? P.T2 : P.W);
@@ -157,7 +158,7 @@ k_bgram(const BProb* __restrict__ probs, const BItem* __restrict__ items, int ni
         int skip3) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   double* Xs = reinterpret_cast<double*>(lds);
-  double* red = reinterpret_cast<double*>(lds + 32 * (kMaxBatchLP + 1) * 8);
+  double* red = reinterpret_cast<double*>(lds + kXsBytes);
   for (int it = xcd_remap(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const BItem I = items[it];
     const BProb& P = probs[I.prob];
@@ -181,7 +182,7 @@ k_bapply(const BProb* __restrict__ probs, const BItem* __restrict__ items, int n
          int skip3) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   double* Xs = reinterpret_cast<double*>(lds);
-  double* red = reinterpret_cast<double*>(lds + 32 * (kMaxBatchLP + 1) * 8);
+  double* red = reinterpret_cast<double*>(lds + kXsBytes);
   for (int it = xcd_remap(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const BItem I = items[it];
     const BProb& P = probs[I.prob];
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(256, 2)
 k_blift(const BProb* __restrict__ probs, const BItem* __restrict__ items, int nitems, int which) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   double* Xs = reinterpret_cast<double*>(lds);
-  double* red = reinterpret_cast<double*>(lds + 32 * (kMaxBatchLP + 1) * 8);
+  double* red = reinterpret_cast<double*>(lds + kXsBytes);
   for (int it = xcd_remap(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const BItem I = items[it];
     const BProb& P = probs[I.prob];

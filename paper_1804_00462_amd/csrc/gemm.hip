@@ -25,7 +25,7 @@ k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
   if (skipflag && *skipflag) return;  // product not needed (see the Cholesky QR step)
   constexpr int LP = CT * kTile;
   constexpr int KS = 4 * Traits<T>::VK;
-  __shared__ T Xs[KS * (LP + 1)];
+  __shared__ T Xs[xs_elems<T, CT>()];
   __shared__ double red[4];
   const int nb = tiles * nsplit;
   const int v = xcd_remap((int)blockIdx.x, nb);
@@ -121,7 +121,8 @@ static hipError_t launch_ct(int CT, const T* A, int64_t lda, int64_t OUT, int64_
 template <typename T> constexpr bool has_rt1() { return true; }
 template <> constexpr bool has_rt1<float>() { return false; }
 
-int skinny_rt(int a_type, int64_t OUT) { return (a_type == 1 || OUT <= 128) ? 2 : 1; }
+// FP64 tiles are 64 rows: 128-row FP64 tiles of the widest operands do not fit the registers
+int skinny_rt(int a_type, int64_t OUT) { return a_type == 1 ? 2 : 1; }
 
 template <typename T, int RT>
 static hipError_t launch_rt(bool trans, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
@@ -141,11 +142,11 @@ hipError_t launch_skinny(bool trans, const T* A, int64_t lda, int64_t OUT, int64
                          int64_t ldx, int LP, int64_t kchunk, int nsplit,
                          typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
                          double* Tout, hipStream_t st) {
-  if constexpr (has_rt1<T>()) {
-    if (OUT > 128)
-      return launch_rt<T, 1>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st);
-  }
-  return launch_rt<T, 2>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st);
+  // must agree with skinny_rt: FP64 64-row tiles, FP32 128-row tiles
+  if constexpr (has_rt1<T>())
+    return launch_rt<T, 1>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st);
+  else
+    return launch_rt<T, 2>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st);
 }
 
 // With Tout != null and nsplit == 1 the kernel writes the FP64 result itself.

@@ -12,7 +12,7 @@
 // indices starting at VK * (l / 16)); the skinny operand is staged in LDS and
 // read as the MFMA B operand. Both operands use the same lane -> contraction
 // map, so any permutation of the contraction inside a step is harmless.
-// Loads for the next step are issued before the MFMAs of the current one.
+// Loads for later steps are issued before the MFMAs of the current one.
 #pragma once
 #include "common.hpp"
 
@@ -68,12 +68,20 @@ __device__ inline int xcd_remap(int b, int nb) {
 }
 
 
+// LDS of the staged skinny operand: two buffers (the next step's rows are
+// stored while the current ones feed the MFMAs) of KS rows, row stride LP + 2.
+// With that stride the four 16-lane groups of a B-operand read, whose rows lie
+// VK apart, start 16 banks apart, so each 32-lane half of the wave hits 32
+// distinct banks.
+template <typename T, int CT>
+constexpr int xs_elems() { return 2 * 4 * Traits<T>::VK * (CT * kTile + 2); }
+
 // Output: if Tout != null, out[r][c] -> Tout[r * ldo + c] in FP64 (c < LP);
 // else -> P[r * LP + c] in the accumulator type (a partial sum). Tout may
 // alias A (the in-place T <- T R^{-1}): the workgroup writes only its own
 // output rows, after it has read all of its input rows. If nrm != null the
 // FP64 sum of squares of the A elements this workgroup read is stored there.
-// Xs: LDS of at least 4 VK (16 CT + 1) elements; red: LDS of 4 doubles.
+// Xs: LDS of xs_elems<T, CT>() elements; red: LDS of 4 doubles.
 template <typename T, bool TRANS, int RT, int CT>
 __device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t k0, int64_t k1,
                                    const T* __restrict__ X, int64_t ldx, int64_t base, int vec_ok,
@@ -84,7 +92,7 @@ __device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t
   constexpr int LP = CT * kTile;
   constexpr int VK = Tr::VK;
   constexpr int KS = 4 * VK;          // contraction indices per step
-  constexpr int LPS = LP + 1;         // LDS row stride (odd: spreads the 4 lane groups over banks)
+  constexpr int LPS = LP + 2;         // LDS row stride (see xs_elems)
   constexpr int XPT = KS * LP / 256;  // skinny-operand elements staged per thread per step
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
   const int g = l / kTile, li = l % kTile;
@@ -126,41 +134,84 @@ __device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t
     }
   };
 
-  T a[RT][VK];
-  T xr[XPT];
-  if (k0 < k1) { load_a(a, k0); load_x(xr, k0); }
-  for (int64_t kb = k0; kb < k1; kb += KS) {
-    __syncthreads();
+  auto store_x = [&](const T (&xr)[XPT], T* buf) {
 #pragma unroll
     for (int i = 0; i < XPT; ++i) {
       const int idx = threadIdx.x + 256 * i;
-      Xs[(idx / LP) * LPS + idx % LP] = xr[i];
+      buf[(idx / LP) * LPS + idx % LP] = xr[i];
     }
-    __syncthreads();
-    T an[RT][VK];
+  };
+
+  // A fragments are loaded PD steps ahead (FP32: two, to cover the HBM
+  // latency under load with the MFMA time of one step; FP64: one, registers)
+  constexpr int PD = sizeof(T) == 4 ? 2 : 1;
+  T a[RT][VK];
+  T an[RT][VK];
+  T xr[XPT];
+  T* xb = Xs;                  // rows of the current step
+  T* xn = Xs + KS * LPS;       // rows of the next step
+  __syncthreads();             // LDS may still be read by the previous tile of a persistent loop
+  if (k0 < k1) {
+    load_a(a, k0);
+    load_x(xr, k0);
+    store_x(xr, xb);
+    if (PD == 2 && k0 + KS < k1) load_a(an, k0 + KS);
+  }
+  __syncthreads();
+  for (int64_t kb = k0; kb < k1; kb += KS) {
+    T an2[RT][VK];
     const bool more = kb + KS < k1;
-    if (more) { load_a(an, kb + KS); load_x(xr, kb + KS); }
+    if (PD == 2) {
+      // the X rows of the next step first: waiting for them below does not
+      // wait for the A fragments two steps ahead
+      if (more) load_x(xr, kb + KS);
+      if (kb + 2 * KS < k1) load_a(an2, kb + 2 * KS);
+    } else if (more) {
+      load_a(an, kb + KS);
+      load_x(xr, kb + KS);
+    }
     if (nrm_out) {
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int j = 0; j < VK; ++j) nrm += (double)a[rt][j] * (double)a[rt][j];
     }
+    // B fragments of contraction index j + 1 are read from LDS while the
+    // MFMAs of index j run (the scheduling barriers keep the reads ahead of
+    // the MFMAs instead of next to their uses, where the LDS latency would
+    // stall the matrix pipe between every few MFMAs)
+    T bq[2][CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) bq[0][ct] = xb[(VK * g) * LPS + ct * kTile + li];
 #pragma unroll
     for (int j = 0; j < VK; ++j) {
+      if (j + 1 < VK) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const T b = Xs[(VK * g + j) * LPS + ct * kTile + li];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Tr::mfma(a[rt][j], b, acc[rt][ct]);
+        for (int ct = 0; ct < CT; ++ct) bq[(j + 1) & 1][ct] = xb[(VK * g + j + 1) * LPS + ct * kTile + li];
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Tr::mfma(a[rt][j], bq[j & 1][ct], acc[rt][ct]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (more) {
+      // the other buffer was last read in the previous step, which every wave
+      // finished before the barrier that ended it
+      store_x(xr, xn);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int j = 0; j < VK; ++j) a[rt][j] = an[rt][j];
+        for (int j = 0; j < VK; ++j) {
+          a[rt][j] = an[rt][j];
+          if (PD == 2) an[rt][j] = an2[rt][j];
+        }
     }
+    __syncthreads();  // the next step's rows are in LDS; the current ones may be overwritten
+    T* t = xb;
+    xb = xn;
+    xn = t;
   }
 
 #pragma unroll
