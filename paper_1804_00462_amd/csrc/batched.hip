@@ -36,8 +36,11 @@ constexpr int kGramRows = 512;  // rows of T per Gram work item
 constexpr int kMaxBatchLP = 128;
 constexpr int kMaxBatch = 65535;
 constexpr int kElemsPerBlock = 4096;  // element-wise kernels: elements per workgroup
-constexpr size_t kXsBytes = (size_t)xs_elems<double, kMaxBatchLP / kTile>() * 8;  // largest staged operand
-constexpr size_t kTileLds = kXsBytes + 64;
+// dynamic LDS of a tile kernel: its staged operand, then 4 doubles of reductions
+template <typename T, int CT>
+constexpr size_t xs_bytes() { return (size_t)xs_elems<T, CT>() * sizeof(T); }
+template <typename T, int CT>
+constexpr size_t tile_lds() { return xs_bytes<T, CT>() + 64; }
 
 struct BProb {
   int64_t m, n;
@@ -89,12 +92,15 @@ enum Mode : int {
 template <typename TA, bool TRANS, int RT, int CT>
 __device__ void pass_item(const BProb& P, const BItem& I, int mode, bool want_norm, char* lds) {
   TA* Xs = reinterpret_cast<TA*>(lds);
-  double* red = reinterpret_cast<double*>(lds + kXsBytes);
+  double* red = reinterpret_cast<double*>(lds + xs_bytes<TA, CT>());
   const int64_t OUT = TRANS ? P.n : P.m;
   const int64_t K = TRANS ? P.m : P.n;
   double* out = mode == M_SKETCH ? P.T1 : (mode == M_ORBIT ? P.T2 : P.W);
   double* nrm = want_norm ? P.normp + I.chunk : nullptr;
-  skinny_tile<TA, TRANS, RT, CT>(reinterpret_cast<const TA*>(P.A), P.lda, OUT, 0, K,
+  // one step of prefetch for the widest 128-row tiles: two do not fit the
+  // registers next to the persistent loop's state
+  constexpr int PD = (sizeof(TA) == 4 && (CT <= 4 || (RT == 1 && CT == 5))) ? 2 : 1;
+  skinny_tile<TA, TRANS, RT, CT, PD>(reinterpret_cast<const TA*>(P.A), P.lda, OUT, 0, K,
                                  reinterpret_cast<const TA*>(P.Xc), P.LP, I.base, P.vec_ok, nullptr, out, P.LP,
                                  nrm, Xs, red);
 }
@@ -158,7 +164,7 @@ k_bgram(const BProb* __restrict__ probs, const BItem* __restrict__ items, int ni
         int skip3) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   double* Xs = reinterpret_cast<double*>(lds);
-  double* red = reinterpret_cast<double*>(lds + kXsBytes);
+  double* red = reinterpret_cast<double*>(lds + xs_bytes<double, CT>());
   for (int it = xcd_remap(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const BItem I = items[it];
     const BProb& P = probs[I.prob];
@@ -182,7 +188,7 @@ k_bapply(const BProb* __restrict__ probs, const BItem* __restrict__ items, int n
          int skip3) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   double* Xs = reinterpret_cast<double*>(lds);
-  double* red = reinterpret_cast<double*>(lds + kXsBytes);
+  double* red = reinterpret_cast<double*>(lds + xs_bytes<double, CT>());
   for (int it = xcd_remap(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const BItem I = items[it];
     const BProb& P = probs[I.prob];
@@ -200,7 +206,7 @@ __global__ void __launch_bounds__(256, 2)
 k_blift(const BProb* __restrict__ probs, const BItem* __restrict__ items, int nitems, int which) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   double* Xs = reinterpret_cast<double*>(lds);
-  double* red = reinterpret_cast<double*>(lds + kXsBytes);
+  double* red = reinterpret_cast<double*>(lds + xs_bytes<double, CT>());
   for (int it = xcd_remap(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const BItem I = items[it];
     const BProb& P = probs[I.prob];
@@ -497,18 +503,18 @@ int launch_pass(const sorsvd_batch* b, void* ws, int mode, int qiter, const Cfg&
     switch ((ci + 1) * 4 + (tn ? 2 : 0) + (rt - 1)) {
 #define SORSVD_LP(C)                                                                                          \
   case C * 4 + 0:                                                                                             \
-    hipLaunchKernelGGL((k_bpass<TA, false, 1, C>), grid, dim3(256), kTileLds, st, probs, it, n, mode, qiter,   \
+    hipLaunchKernelGGL((k_bpass<TA, false, 1, C>), grid, dim3(256), (tile_lds<TA, C>()), st, probs, it, n, mode, qiter,   \
                        want_norm);                                                                            \
     break;                                                                                                    \
   case C * 4 + 1:                                                                                             \
-    hipLaunchKernelGGL((k_bpass<TA, false, sizeof(TA) == 8 ? 1 : 2, C>), grid, dim3(256), kTileLds, st, probs, \
+    hipLaunchKernelGGL((k_bpass<TA, false, sizeof(TA) == 8 ? 1 : 2, C>), grid, dim3(256), (tile_lds<TA, C>()), st, probs, \
                        it, n, mode, qiter, want_norm);                                                        \
     break;                                                                                                    \
   case C * 4 + 2:                                                                                             \
-    hipLaunchKernelGGL((k_bpass<TA, true, 1, C>), grid, dim3(256), kTileLds, st, probs, it, n, mode, qiter, 0); \
+    hipLaunchKernelGGL((k_bpass<TA, true, 1, C>), grid, dim3(256), (tile_lds<TA, C>()), st, probs, it, n, mode, qiter, 0); \
     break;                                                                                                    \
   case C * 4 + 3:                                                                                             \
-    hipLaunchKernelGGL((k_bpass<TA, true, sizeof(TA) == 8 ? 1 : 2, C>), grid, dim3(256), kTileLds, st, probs,  \
+    hipLaunchKernelGGL((k_bpass<TA, true, sizeof(TA) == 8 ? 1 : 2, C>), grid, dim3(256), (tile_lds<TA, C>()), st, probs,  \
                        it, n, mode, qiter, 0);                                                                \
     break;
       SORSVD_CT_CASES(SORSVD_LP)
@@ -532,7 +538,7 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int skip3, 
       switch (ci + 1) {
 #define SORSVD_LP(C)                                                                                                \
   case C:                                                                                                           \
-    hipLaunchKernelGGL(k_bgram<C>, grid, dim3(256), kTileLds, st, probs, it, n, mode, qiter, skip3);              \
+    hipLaunchKernelGGL(k_bgram<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, mode, qiter, skip3);              \
     break;
         SORSVD_CT_CASES(SORSVD_LP)
 #undef SORSVD_LP
@@ -542,7 +548,7 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int skip3, 
       switch (ci + 1) {
 #define SORSVD_LP(C)                                                                                                \
   case C:                                                                                                           \
-    hipLaunchKernelGGL(k_bapply<C>, grid, dim3(256), kTileLds, st, probs, it, n, which, qiter, skip3);            \
+    hipLaunchKernelGGL(k_bapply<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, which, qiter, skip3);            \
     break;
         SORSVD_CT_CASES(SORSVD_LP)
 #undef SORSVD_LP
@@ -552,7 +558,7 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int skip3, 
       switch (ci + 1) {
 #define SORSVD_LP(C)                                                                                                \
   case C:                                                                                                           \
-    hipLaunchKernelGGL(k_blift<C>, grid, dim3(256), kTileLds, st, probs, it, n, which);                           \
+    hipLaunchKernelGGL(k_blift<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, which);                           \
     break;
         SORSVD_CT_CASES(SORSVD_LP)
 #undef SORSVD_LP

@@ -82,7 +82,8 @@ constexpr int xs_elems() { return 2 * 4 * Traits<T>::VK * (CT * kTile + 2); }
 // output rows, after it has read all of its input rows. If nrm != null the
 // FP64 sum of squares of the A elements this workgroup read is stored there.
 // Xs: LDS of xs_elems<T, CT>() elements; red: LDS of 4 doubles.
-template <typename T, bool TRANS, int RT, int CT>
+// PD: A fragments are loaded PD steps ahead (1 or 2).
+template <typename T, bool TRANS, int RT, int CT, int PD = (sizeof(T) == 4 ? 2 : 1)>
 __device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t k0, int64_t k1,
                                    const T* __restrict__ X, int64_t ldx, int64_t base, int vec_ok,
                                    typename Traits<T>::acc_t* P, double* Tout, int64_t ldo,
@@ -142,9 +143,9 @@ __device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t
     }
   };
 
-  // A fragments are loaded PD steps ahead (FP32: two, to cover the HBM
-  // latency under load with the MFMA time of one step; FP64: one, registers)
-  constexpr int PD = sizeof(T) == 4 ? 2 : 1;
+  // A fragments PD steps ahead (FP32 by default two, to cover the HBM latency
+  // under load with the MFMA time of one step; FP64 one, for the registers)
+  static_assert(PD == 1 || PD == 2, "prefetch depth");
   T a[RT][VK];
   T an[RT][VK];
   T xr[XPT];
