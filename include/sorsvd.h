@@ -292,6 +292,9 @@ void sorsvd_batch_destroy(sorsvd_batch* b);
  *   leaves a subspace error near 1e-3). If the judge
  *   rejects, or no predicted width fits, the fallback k = min(128, m, n),
  *   q = 2 runs and is judged. params = NULL skips the network (fallback only).
+ *   With the network, every run starts from the probe: Omega is nested in its
+ *   width and Cholesky QR keeps column prefixes, so the leading k columns of
+ *   the probe's Q are Q1 of the run's first sketch (one pass and one QR fewer).
  *   U, V need ldu, ldv >= min(128, m, n) (the first k_used columns are the
  *   result), S as many entries. Synchronous: waits for `stream`. Returns
  *   SORSVD_OK, or SORSVD_ETOL with the fallback's result left in U, S, V.

@@ -263,12 +263,22 @@ __global__ void __launch_bounds__(kSmallThreads) k_bchol(const BProb* __restrict
   chol_inv_body(P.gpart, nparts, (int64_t)P.LP * P.LP, P.LP, P.l, rows, mode, P.Rinv, P.skip3, P.info, sm);
 }
 
+// One workgroup per problem; the row-block count follows the problem's l.
 template <bool V_LDS>
-__global__ void __launch_bounds__(kSmallThreads) k_bjacobi(const BProb* __restrict__ probs, int max_sweeps) {
+__global__ void __launch_bounds__(kJacThreads) k_bjacobi(const BProb* __restrict__ probs, int max_sweeps) {
   extern __shared__ double sm[];
   const BProb& P = probs[blockIdx.x];
-  jacobi_body<V_LDS>(P.gpart, P.gch_m, (int64_t)P.LP * P.LP, P.LP, P.l, P.k, max_sweeps, P.Ut, P.S, P.Vt,
-                     P.KP, P.Vg, P.info, sm);
+  const double tol2 = (double)P.l * 0x1p-104;
+#define SOR_BJAC(R)                                                                                          \
+  case R:                                                                                                    \
+    jacobi_body<V_LDS, true, R>(P.gpart, P.gch_m, (int64_t)P.LP * P.LP, P.LP, P.l, P.k, max_sweeps, tol2,   \
+                                P.Ut, P.S, P.Vt, P.KP, P.Vg, P.info, sm);                                    \
+    break;
+  switch (jac_nrb(P.l)) {
+    SOR_BJAC(1) SOR_BJAC(2) SOR_BJAC(4) SOR_BJAC(6) SOR_BJAC(8) SOR_BJAC(10) SOR_BJAC(13) SOR_BJAC(16)
+    default: break;
+  }
+#undef SOR_BJAC
 }
 
 // Sign convention: the largest-|.| entry of each U column (lowest row on
@@ -569,12 +579,6 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int skip3, 
   return SORSVD_OK;
 }
 
-size_t jacobi_shm(int l, bool* v_lds) {
-  const size_t one = (size_t)l * l * 8, vec = (size_t)l * 8;
-  *v_lds = 2 * one + vec <= 160 * 1024 - 256;
-  return (*v_lds ? 2 * one : one) + vec;
-}
-
 template <typename TA>
 int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
   const BProb* probs = dev_table(b, ws);
@@ -629,12 +633,13 @@ int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
   if ((rc = launch_pass<TA>(b, ws, M_PROJ, -1, b->cfg[2], timed, st))) return rc;
   if ((rc = launch_f64(b, ws, M_PGRAM, -1, 0, st))) return rc;
   // core SVD, truncated to k (Alg. 3 step 6)
+  // (the layout of each problem follows its own l; LDS is sized for the largest)
   bool v_lds = false;
-  const size_t jshm = jacobi_shm(b->max_l, &v_lds);
+  const size_t jshm = jacobi_lds(b->max_l, true, &v_lds);
   if (v_lds)
-    hipLaunchKernelGGL(k_bjacobi<true>, dim3(np), dim3(kSmallThreads), jshm, st, probs, b->max_sweeps);
+    hipLaunchKernelGGL(k_bjacobi<true>, dim3(np), dim3(kJacThreads), jshm, st, probs, b->max_sweeps);
   else
-    hipLaunchKernelGGL(k_bjacobi<false>, dim3(np), dim3(kSmallThreads), jshm, st, probs, b->max_sweeps);
+    hipLaunchKernelGGL(k_bjacobi<false>, dim3(np), dim3(kJacThreads), jshm, st, probs, b->max_sweeps);
   SORSVD_TRY(hipGetLastError());
   // lift (Alg. 3 step 7) and the sign convention
   if ((rc = launch_f64(b, ws, M_LIFTU, -1, 0, st))) return rc;
@@ -773,7 +778,8 @@ int sorsvd_batch_create(int32_t count, const sorsvd_problem* probs, int32_t a_ty
     off += align256(rows * LP * b->es);                                 // Xc
     off += 2 * align256(P.m * LP * 8) + align256(P.m * KP * 8);         // T1, W, U64
     off += align256(P.n * LP * 8) + align256(P.n * KP * 8);             // T2, V64
-    off += 2 * align256(LP * LP * 8) + 2 * align256(LP * KP * 8);       // Rinv, Vg, Ut, Vt
+    off += align256(LP * LP * 8) + align256(LP * jac_vg_ld(P.l) * 8);  // Rinv, Vg
+    off += 2 * align256(LP * KP * 8);                                   // Ut, Vt
     off += align256((size_t)std::max(P.gch_m, P.gch_n) * LP * LP * 8);  // gpart
     off += align256((size_t)P.ntile1 * 8);                              // normp
     off += 2 * align256((size_t)P.sblocks * KP * 8) + align256(KP * 8); // pval, pidx, sgn
@@ -807,7 +813,7 @@ int sorsvd_batch_upload(sorsvd_batch* b, void* ws, size_t ws_bytes, void* stream
     P.T2 = (double*)take(P.n * LP * 8);
     P.V64 = (double*)take(P.n * KP * 8);
     P.Rinv = (double*)take(LP * LP * 8);
-    P.Vg = (double*)take(LP * LP * 8);
+    P.Vg = (double*)take(LP * jac_vg_ld(P.l) * 8);
     P.Ut = (double*)take(LP * KP * 8);
     P.Vt = (double*)take(LP * KP * 8);
     P.gpart = (double*)take((size_t)std::max(P.gch_m, P.gch_n) * LP * LP * 8);

@@ -72,8 +72,10 @@ __device__ inline double wave_sum(double v) {
 template <int CTRL>
 __device__ inline double dpp_f64(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  // every control used here has a valid source lane for every lane, so the
+  // old value is never kept (and needs no initialising move)
+  const int lo2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, false);
+  const int hi2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, false);
   return __hiloint2double(hi2, lo2);
 }
 

@@ -12,13 +12,13 @@ k_chol_inv(const double* __restrict__ G, int LP, int l, int64_t rows, int mode,
   chol_inv_body(G, 1, 0, LP, l, rows, mode, Rinv, skip3, info, sm);
 }
 
-template <bool V_LDS>
-__global__ void __launch_bounds__(kSmallThreads)
-k_jacobi(const double* __restrict__ Min, int LP, int l, int k, int max_sweeps,
+template <bool V_LDS, bool WANT_V, int NRB>
+__global__ void __launch_bounds__(kJacThreads)
+k_jacobi(const double* __restrict__ Min, int LP, int l, int k, int max_sweeps, double tol2,
          double* __restrict__ Ut, double* __restrict__ sv, double* __restrict__ Vt, int ldk,
          double* __restrict__ Vg, DevInfo* __restrict__ info) {
   extern __shared__ double sm[];
-  jacobi_body<V_LDS>(Min, 1, 0, LP, l, k, max_sweeps, Ut, sv, Vt, ldk, Vg, info, sm);
+  jacobi_body<V_LDS, WANT_V, NRB>(Min, 1, 0, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, info, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -162,24 +162,38 @@ hipError_t launch_chol_inv(const double* G, int LP, int l, int64_t rows, int mod
   return hipGetLastError();
 }
 
-static size_t jacobi_lds_bytes(int l, int* v_in_lds) {
-  const size_t one = (size_t)l * l * sizeof(double);
-  const size_t vec = (size_t)l * sizeof(double);
-  const size_t limit = 160 * 1024 - 256;  // room for the static LDS words
-  *v_in_lds = (2 * one + vec <= limit) ? 1 : 0;
-  return (*v_in_lds ? 2 * one : one) + vec;
+template <bool V_LDS, bool WANT_V>
+static void launch_jacobi_nrb(int nrb, size_t shm, hipStream_t st, const double* M, int LP, int l, int k,
+                              int max_sweeps, double tol2, double* Ut, double* sv, double* Vt, int ldk,
+                              double* Vg, DevInfo* info) {
+#define SOR_JAC(R)                                                                                       \
+  case R:                                                                                                \
+    hipLaunchKernelGGL((k_jacobi<V_LDS, WANT_V, R>), dim3(1), dim3(kJacThreads), shm, st, M, LP, l, k,  \
+                       max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, info);                                     \
+    break;
+  switch (nrb) {
+    SOR_JAC(1) SOR_JAC(2) SOR_JAC(4) SOR_JAC(6) SOR_JAC(8) SOR_JAC(10) SOR_JAC(13) SOR_JAC(16)
+    default: break;
+  }
+#undef SOR_JAC
 }
 
+// tol <= 0 selects the default orthogonality threshold sqrt(l) 2^-52.
 hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, double* Ut,
-                         double* sv, double* Vt, int ldk, double* Vg, void* info, hipStream_t st) {
-  int v_in_lds = 0;
-  const size_t shm = jacobi_lds_bytes(l, &v_in_lds);
-  if (v_in_lds)
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(kSmallThreads), shm, st, M, LP, l, k, max_sweeps,
-                       Ut, sv, Vt, ldk, Vg, (DevInfo*)info);
+                         double* sv, double* Vt, int ldk, double* Vg, void* info, hipStream_t st,
+                         bool want_v, double tol) {
+  if (l < 1 || l > 128) return hipErrorInvalidValue;
+  bool v_lds = false;
+  const size_t shm = jacobi_lds(l, want_v, &v_lds);
+  const double tol2 = tol > 0.0 ? tol * tol : (double)l * 0x1p-104;
+  const int nrb = jac_nrb(l);
+  DevInfo* di = (DevInfo*)info;
+  if (!want_v)
+    launch_jacobi_nrb<false, false>(nrb, shm, st, M, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, di);
+  else if (v_lds)
+    launch_jacobi_nrb<true, true>(nrb, shm, st, M, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, di);
   else
-    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(kSmallThreads), shm, st, M, LP, l, k, max_sweeps,
-                       Ut, sv, Vt, ldk, Vg, (DevInfo*)info);
+    launch_jacobi_nrb<false, true>(nrb, shm, st, M, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, di);
   return hipGetLastError();
 }
 

@@ -145,42 +145,85 @@ __device__ inline void chol_inv_body(const double* __restrict__ G, int nparts, i
 // m_p <- c m_p - s m_q, m_q <- s m_p + c m_q (and the same on V), which makes
 // the pair orthogonal. A sweep visits every pair once in round-robin order
 // (l' - 1 steps of l'/2 disjoint pairs, l' = l rounded up to even); sweeps
-// stop when no pair had |gamma| > tol sqrt(alpha beta), tol = sqrt(l) 2^-52,
-// or after max_sweeps. Then sigma_j = |m_j|, U~_j = m_j / sigma_j, V~_j = v_j,
-// sorted descending; the first k are written (Ut, Vt: l x k, ld ldk; s: k).
-// Each pair is handled by a group of 16 lanes (one DPP row); each lane keeps
-// its (at most 8) rows of the two columns in registers for the step, and the
-// dot products are reduced with DPP. M lives in LDS; V lives in LDS when both
-// fit, else in the global scratch `Vg` (l x l).
-constexpr int kJacRows = 8;  // rows per lane: l <= 16 * kJacRows
+// stop when no pair had |gamma| > tol sqrt(alpha beta), or after max_sweeps.
+// Then sigma_j = |m_j|, U~_j = m_j / sigma_j, V~_j = v_j, sorted descending;
+// the first k are written (Ut, and Vt if WANT_V: l x k, ld ldk; s: k).
+//
+// One workgroup of kJacThreads. Each pair is handled by a group of 8 lanes;
+// lane g of a group holds rows g, g + 8, ... of the two columns in registers
+// for the step (NRB of them, a compile-time row-block count), and the three
+// dot products are reduced with DPP. The step cost is VALU issue on one CU,
+// so the layout avoids per-row masks: M lives in LDS column-major with its
+// columns padded with zero rows to ldm = 8 NRB (rotations keep them zero).
+// V, when wanted, lives in LDS when it fits: column stride ldm, or, where
+// only the unpadded form fits, stride l followed by one dummy word that takes
+// the rows past l of the last row block; else in the global scratch `Vg`
+// (at least l x ldm, stride ldm). V is not needed for singular values alone
+// (WANT_V = false).
+constexpr int kJacThreads = 512;
 
-// Min is given as nparts partial sums (stride pstride elements), added in order.
-template <bool V_LDS>
+// Row blocks per lane for a given l (a few sizes, to bound the number of
+// compiled variants): M's padded column length is 8 jac_nrb(l).
+__host__ __device__ constexpr int jac_nrb(int l) {
+  return l <= 8 ? 1 : l <= 16 ? 2 : l <= 32 ? 4 : l <= 48 ? 6 : l <= 64 ? 8 : l <= 80 ? 10 : l <= 104 ? 13 : 16;
+}
+__host__ __device__ constexpr int jac_ldm(int l) { return 8 * jac_nrb(l); }
+// Column stride of the global scratch Vg (LP x this): holds V with padded
+// columns, or the singular values.
+__host__ __device__ constexpr int jac_vg_ld(int l) { return jac_ldm(l) > ((l + 15) & ~15) ? jac_ldm(l) : ((l + 15) & ~15); }
+constexpr size_t kJacLdsLimit = 160 * 1024 - 256;  // room for the static LDS words
+// V in LDS with padded columns / with unpadded columns (+ the dummy word).
+__host__ __device__ inline bool jac_vpad_fits(int l) {
+  return (size_t)l * jac_ldm(l) * 16 <= kJacLdsLimit;
+}
+__host__ __device__ inline bool jac_vtail_fits(int l) {
+  return ((size_t)l * jac_ldm(l) + (size_t)l * l + 1) * 8 <= kJacLdsLimit;
+}
+// Dynamic LDS of the Jacobi body and whether V is in it.
+__host__ __device__ inline size_t jacobi_lds(int l, bool want_v, bool* v_lds) {
+  const size_t mbytes = (size_t)l * jac_ldm(l) * 8;
+  *v_lds = want_v && (jac_vpad_fits(l) || jac_vtail_fits(l));
+  if (!*v_lds) return mbytes + (size_t)l * 8;  // M and the singular values
+  return jac_vpad_fits(l) ? 2 * mbytes : mbytes + ((size_t)l * l + 1) * 8;
+}
+
+// Min is given as nparts partial sums (stride pstride elements), added in
+// order. tol2 = tol^2 (the main path takes tol = sqrt(l) 2^-52).
+template <bool V_LDS, bool WANT_V, int NRB>
 __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, int64_t pstride, int LP,
-                                   int l, int k, int max_sweeps, double* __restrict__ Ut,
+                                   int l, int k, int max_sweeps, double tol2, double* __restrict__ Ut,
                                    double* __restrict__ sv, double* __restrict__ Vt, int ldk,
                                    double* __restrict__ Vg, DevInfo* __restrict__ info, double* sm) {
-  double* Mc = sm;                             // column-major: Mc[c * l + r]
-  double* Vc;                                  // column-major
-  if constexpr (V_LDS) Vc = sm + l * l; else Vc = Vg;
-  double* sig = sm + (V_LDS ? 2 * l * l : l * l);  // l
+  static_assert(WANT_V || !V_LDS, "V in LDS only when wanted");
+  constexpr int ldm = 8 * NRB;
+  const bool vtail = V_LDS && !jac_vpad_fits(l);  // V columns unpadded (stride l)
+  double* Mc = sm;                              // column-major: Mc[c * ldm + r]
+  double* Vc = V_LDS ? sm + (size_t)l * ldm : Vg;
+  const int vld = vtail ? l : ldm;              // column stride of V
+  const int vdummy = l * vld;                   // (vtail) the dummy word
+  // singular values: after M (and V) in LDS, or in the unused global scratch
+  double* sig = V_LDS ? Vg : sm + (size_t)l * ldm;
   __shared__ int s_rot;
   const int tid = threadIdx.x;
-  const int grp = tid / 16, gl = tid % 16;
-  constexpr int ngroups = kSmallThreads / 16;
+  const int grp = tid / 8, gl = tid % 8;
+  constexpr int ngroups = kJacThreads / 8;
 
-  for (int i = tid; i < l * l; i += kSmallThreads) {
-    const int c = i / l, r = i % l;
+  for (int i = tid; i < l * ldm; i += kJacThreads) {
+    const int c = i / ldm, r = i % ldm;
     double mv = 0.0;
-    for (int p = 0; p < nparts; ++p) mv += Min[p * pstride + r * LP + c];
+    if (r < l)
+      for (int p = 0; p < nparts; ++p) mv += Min[p * pstride + r * LP + c];
     Mc[i] = mv;
-    Vc[i] = (r == c) ? 1.0 : 0.0;
   }
+  if (WANT_V)
+    for (int i = tid; i < l * vld; i += kJacThreads) {
+      const int c = i / vld, r = i % vld;
+      Vc[i] = (r == c) ? 1.0 : 0.0;
+    }
   __syncthreads();
 
   const int lp = (l + 1) & ~1;
   const int npairs = lp / 2;
-  const double tol2 = (double)l * 0x1p-104;  // (sqrt(l) 2^-52)^2
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) s_rot = 0;
@@ -197,43 +240,53 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
         int p = player(pr), q = player(lp - 1 - pr);
         if (p >= l || q >= l) continue;
         if (p > q) { int t = p; p = q; q = t; }
-        double* mp = Mc + p * l;
-        double* mq = Mc + q * l;
-        double* vp = Vc + p * l;
-        double* vq = Vc + q * l;
-        double x[kJacRows], y[kJacRows], vx[kJacRows], vy[kJacRows];
+        double* mp = Mc + p * ldm + gl;
+        double* mq = Mc + q * ldm + gl;
+        double x[NRB], y[NRB];
 #pragma unroll
-        for (int i = 0; i < kJacRows; ++i) {
-          // clamped, unconditional loads (all issued before the first use)
-          const int r = gl + 16 * i;
-          const int rc = r < l ? r : l - 1;
-          const double a = mp[rc], b = mq[rc], va = vp[rc], vb = vq[rc];
-          const bool in = r < l;
-          x[i] = in ? a : 0.0;
-          y[i] = in ? b : 0.0;
-          vx[i] = in ? va : 0.0;
-          vy[i] = in ? vb : 0.0;
-        }
+        for (int i = 0; i < NRB; ++i) { x[i] = mp[8 * i]; y[i] = mq[8 * i]; }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int i = 0; i < kJacRows; ++i) {
-          al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i];
-        }
-        al = sum16(al); be = sum16(be); ga = sum16(ga);
+        for (int i = 0; i < NRB; ++i) { al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i]; }
+        al = sum8(al); be = sum8(be); ga = sum8(ga);
         if (!(ga * ga > tol2 * (al * be))) continue;  // orthogonal enough (or zero column)
+        // V: the row blocks before the last one are whole; in the last one
+        // (registers vxl, vyl) rows past l go to the dummy word when V's
+        // columns are not padded
+        double vx[NRB], vy[NRB], vxl = 0.0, vyl = 0.0;
+        int ipl = 0, iql = 0;
+        if (WANT_V) {
+          // read before the rotation is formed, so that the latency overlaps
+          // the divisions and square roots
+#pragma unroll
+          for (int i = 0; i < NRB - 1; ++i) {
+            vx[i] = Vc[p * vld + gl + 8 * i];
+            vy[i] = Vc[q * vld + gl + 8 * i];
+          }
+          const int rl = gl + 8 * (NRB - 1);
+          const bool okl = !vtail || rl < l;
+          ipl = okl ? p * vld + rl : vdummy;
+          iql = okl ? q * vld + rl : vdummy;
+          vxl = Vc[ipl];
+          vyl = Vc[iql];
+        }
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t);
         const double s = c * t;
 #pragma unroll
-        for (int i = 0; i < kJacRows; ++i) {
-          const int r = gl + 16 * i;
-          if (r < l) {
-            mp[r] = c * x[i] - s * y[i];
-            mq[r] = s * x[i] + c * y[i];
-            vp[r] = c * vx[i] - s * vy[i];
-            vq[r] = s * vx[i] + c * vy[i];
+        for (int i = 0; i < NRB; ++i) {
+          mp[8 * i] = c * x[i] - s * y[i];
+          mq[8 * i] = s * x[i] + c * y[i];
+        }
+        if (WANT_V) {
+#pragma unroll
+          for (int i = 0; i < NRB - 1; ++i) {
+            Vc[p * vld + gl + 8 * i] = c * vx[i] - s * vy[i];
+            Vc[q * vld + gl + 8 * i] = s * vx[i] + c * vy[i];
           }
+          Vc[ipl] = c * vxl - s * vyl;
+          Vc[iql] = s * vxl + c * vyl;
         }
         if (gl == 0) s_rot = 1;
       }
@@ -250,8 +303,8 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
   // column norms -> singular values
   for (int c = grp; c < l; c += ngroups) {
     double a = 0.0;
-    for (int r = gl; r < l; r += 16) a += Mc[c * l + r] * Mc[c * l + r];
-    a = sum16(a);
+    for (int r = gl; r < l; r += 8) a += Mc[c * ldm + r] * Mc[c * ldm + r];
+    a = sum8(a);
     if (gl == 0) sig[c] = sqrt(a);
   }
   __syncthreads();
@@ -259,13 +312,13 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
   for (int c = grp; c < l; c += ngroups) {
     const double sc = sig[c];
     int rank = 0;
-    for (int i = gl; i < l; i += 16) rank += (sig[i] > sc || (sig[i] == sc && i < c)) ? 1 : 0;
-    for (int off = 8; off >= 1; off >>= 1) rank += __shfl_xor(rank, off, kWave);
+    for (int i = gl; i < l; i += 8) rank += (sig[i] > sc || (sig[i] == sc && i < c)) ? 1 : 0;
+    for (int off = 4; off >= 1; off >>= 1) rank += __shfl_xor(rank, off, kWave);
     if (rank < k) {
       const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
-      for (int r = gl; r < l; r += 16) {
-        Ut[r * ldk + rank] = Mc[c * l + r] * inv;
-        Vt[r * ldk + rank] = Vc[c * l + r];
+      for (int r = gl; r < l; r += 8) {
+        Ut[r * ldk + rank] = Mc[c * ldm + r] * inv;
+        if (WANT_V) Vt[r * ldk + rank] = Vc[c * vld + r];
       }
       if (gl == 0) sv[rank] = sc;
     }

@@ -63,7 +63,8 @@ hipError_t launch_omega_rowmajor_f32(uint64_t seed, int64_t rows, int64_t cols, 
 hipError_t launch_chol_inv(const double* G, int LP, int l, int64_t rows, int mode, double* Rinv,
                            int* skip3, void* info, hipStream_t st);
 hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, double* Ut,
-                         double* sv, double* Vt, int ldk, double* Vg, void* info, hipStream_t st);
+                         double* sv, double* Vt, int ldk, double* Vg, void* info, hipStream_t st,
+                         bool want_v = true, double tol = 0.0);
 hipError_t launch_signfix(const double* U64, int64_t m, const double* V64, int64_t n, int ld, int k,
                           double* pval, int64_t* pidx, int nblocks_max, double* sgn, double* U,
                           int64_t ldu, double* V, int64_t ldv, hipStream_t st);
@@ -214,7 +215,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->off_m = L.take((size_t)LP * LP * 8);
   p->off_ut = L.take((size_t)LP * KP * 8);
   p->off_vt = L.take((size_t)LP * KP * 8);
-  p->off_vg = L.take((size_t)LP * LP * 8);
+  p->off_vg = L.take((size_t)LP * kMaxLP * 8);  // Jacobi's V: l columns of up to kMaxLP padded rows
   p->off_pval = L.take((size_t)kSignBlocks * KP * 8);
   p->off_pidx = L.take((size_t)kSignBlocks * KP * 8);
   p->off_sgn = L.take((size_t)KP * 8);
@@ -341,8 +342,14 @@ const void* as_operand(const Plan& p, const double* Q, int64_t rows, void* ws, h
   return Xc;
 }
 
+// q1 != null: Q1 of the first sketch is given (q1, leading dimension ldq1, at
+// least l columns: the leading l columns of an orthonormal basis of a wider
+// sketch A Omega' with Omega nested in Omega'), together with the sums of
+// squares of A (normp_ext, nparts_ext slots); the first pass and its QR are
+// skipped.
 int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int64_t ldu, double* S,
-        double* V, int64_t ldv, void* ws, hipStream_t st) {
+        double* V, int64_t ldv, void* ws, hipStream_t st, const double* q1 = nullptr, int64_t ldq1 = 0,
+        const double* normp_ext = nullptr, int nparts_ext = 0) {
   const int LP = (int)p.LP, KP = (int)p.KP;
   void* info = at<void>(ws, p.off_info);
   double* T1 = at<double>(ws, p.off_t1);
@@ -354,7 +361,9 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
 
   // Omega, n x l (Alg. 3 / Alg. 4 step 1), straight into the compute-type operand.
   void* Xc = at<void>(ws, p.off_xc);
-  if (p.a_type == SORSVD_F64 || p.a_type == SORSVD_DIAG) {
+  if (q1) {
+    // nothing to draw
+  } else if (p.a_type == SORSVD_F64 || p.a_type == SORSVD_DIAG) {
     SORSVD_TRY(launch_fill((double*)Xc, p.n * LP, 0.0, st));
     SORSVD_TRY(launch_omega_rowmajor_f64(seed, p.n, p.l, (double*)Xc, LP, st));
   } else if (p.a_type == SORSVD_F32) {
@@ -366,8 +375,12 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   }
 
   // T1 = A Omega (eq. T1), with ||A||_F^2 accumulated on the way; Q1 = qr(T1).
-  if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
-  if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+  if (q1) {
+    SORSVD_TRY(launch_pack_f64(q1, p.m, (int)p.l, ldq1, T1, LP, st));
+  } else {
+    if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
+    if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+  }
   // T2 = A^T Q1 (eq. AT1; the span of A^T T1 by Lemma 1); Q2 = qr(T2).
   const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true);
   if (rc) return rc;
@@ -410,7 +423,8 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   SORSVD_TRY(launch_signfix(U64, p.m, V64, p.n, KP, (int)p.k, at<double>(ws, p.off_pval),
                             at<int64_t>(ws, p.off_pidx), kSignBlocks, at<double>(ws, p.off_sgn), U, ldu,
                             V, ldv, st));
-  SORSVD_TRY(launch_finalize(normp, p.nn_blocks, S, (int)p.k, info, st));
+  SORSVD_TRY(launch_finalize(normp_ext ? normp_ext : normp, normp_ext ? nparts_ext : p.nn_blocks, S, (int)p.k,
+                             info, st));
   // Error check as one more pass (the identity above is free; this one is
   // exact up to the pass arithmetic, and for BF16 A also measures the
   // rounding of A to BF16).
@@ -446,18 +460,19 @@ int probe(const Plan& p, const void* A, int64_t lda, uint64_t seed, float* feat,
   if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
   SORSVD_TRY(launch_pack_f64(T1, p.m, LP, LP, Wc, LP, st));
   if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+  // R^T = Y0^T Q: its rows are the columns of R, whose norms fall with the
+  // singular values, and one-sided Jacobi on that graded form takes a few
+  // sweeps fewer than on R. Only singular values are needed: no V, and the
+  // pairs stop at an orthogonality of 1e-8 (values to ~1e-14 relative).
   double* P = at<double>(ws, p.off_p);
   double* G = at<double>(ws, p.off_g);
-  SORSVD_TRY(launch_skinny_f64(true, T1, LP, LP, p.m, Wc, LP, LP, p.gram_m.kchunk, p.gram_m.nsplit, P, nullptr,
+  SORSVD_TRY(launch_skinny_f64(true, Wc, LP, LP, p.m, T1, LP, LP, p.gram_m.kchunk, p.gram_m.nsplit, P, nullptr,
                                nullptr, st));
   SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.gram_m.nsplit, G, LP, LP, st));
   double* Ut = at<double>(ws, p.off_ut);
-  double* Vt = at<double>(ws, p.off_vt);
   double* sv = at<double>(ws, p.off_sgn);
-  SORSVD_TRY(launch_fill(Ut, (int64_t)LP * KP, 0.0, st));
-  SORSVD_TRY(launch_fill(Vt, (int64_t)LP * KP, 0.0, st));
-  SORSVD_TRY(launch_jacobi(G, LP, (int)p.l, (int)p.l, p.max_sweeps, Ut, sv, Vt, KP, at<double>(ws, p.off_vg),
-                           info, st));
+  SORSVD_TRY(launch_jacobi(G, LP, (int)p.l, (int)p.l, p.max_sweeps, Ut, sv, nullptr, KP, at<double>(ws, p.off_vg),
+                           info, st, false, 1e-8));
   SORSVD_TRY(launch_features(sv, (int)p.l, feat, st));
   return SORSVD_OK;
 }
@@ -770,7 +785,16 @@ static int auto_plan(int64_t m, int64_t n, int32_t a_type, Plan* p) {
   return make_plan(m, n, kcap, 3, a_type, &o, p);
 }
 
-static size_t auto_tail_bytes() { return 256 + 4096 + round_up((int64_t)mlp_work_floats(1) * 4, 256); }
+// Tail of the sorsvd_auto workspace: features and network outputs, network
+// scratch, and the probe's Q (m x its padded width) and norm slots, kept for
+// the runs that start from them.
+static size_t auto_tail_bytes(int64_t m, int64_t n, int32_t a_type) {
+  Plan pp;
+  size_t keep = 0;
+  if (probe_plan(m, n, a_type, &pp) == SORSVD_OK)
+    keep = round_up((int64_t)m * pp.LP * 8, kAlign) + round_up((int64_t)std::max(pp.nn_blocks, 1) * 8, kAlign);
+  return 256 + 4096 + round_up((int64_t)mlp_work_floats(1) * 4, 256) + keep;
+}
 
 // Largest workspace of any run sorsvd_auto may start (k a multiple of 8 or the
 // cap, any q <= 3) and of the probe; the tail (features, outputs, network
@@ -795,7 +819,7 @@ static size_t auto_main_bytes(int64_t m, int64_t n, int32_t a_type) {
 
 size_t sorsvd_auto_workspace_bytes(int64_t m, int64_t n, int32_t a_type) {
   const size_t mb = auto_main_bytes(m, n, a_type);
-  return mb ? mb + auto_tail_bytes() : 0;
+  return mb ? mb + auto_tail_bytes(m, n, a_type) : 0;
 }
 
 int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed, double tol,
@@ -808,7 +832,7 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
   if (!A || !U || !S || !V || !workspace || !out || lda < n || ldu < kcap || ldv < kcap || !(tol > 0.0))
     return SORSVD_EINVAL;
   const size_t main_bytes = auto_main_bytes(m, n, a_type);
-  if (ws_bytes < main_bytes + auto_tail_bytes()) return SORSVD_EWORKSPACE;
+  if (ws_bytes < main_bytes + auto_tail_bytes(m, n, a_type)) return SORSVD_EWORKSPACE;
   if (((uintptr_t)workspace) % kAlign) return SORSVD_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   std::memset(out, 0, sizeof(*out));
@@ -816,6 +840,10 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
   float* feat = (float*)(tail + 256);
   float* y = feat + 128;
   float* work = (float*)(tail + 256 + 4096);
+  double* keep_q = (double*)(tail + 256 + 4096 + round_up((int64_t)mlp_work_floats(1) * 4, 256));
+  double* keep_n = nullptr;
+  int64_t keep_ld = 0;
+  int keep_parts = 0;
   const double ridge = a_type == SORSVD_BF16 ? 312.0 : 39.0;  // width where a pass turns MFMA-bound
   int64_t k = kcap;
   int q = kAutoFallbackQ;
@@ -824,6 +852,14 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     Plan pp;
     if ((rc = probe_plan(m, n, a_type, &pp))) return rc;
     if ((rc = probe(pp, A, lda, seed, feat, workspace, st))) return rc;
+    // keep the probe's Q and norm slots: Omega is nested in its width and
+    // Cholesky QR keeps column prefixes, so the leading k columns of that Q
+    // are Q1 of the run's first sketch
+    keep_ld = pp.LP;
+    keep_n = keep_q + round_up((int64_t)m * pp.LP * 8, kAlign) / 8;
+    keep_parts = pp.nn_blocks;
+    SORSVD_TRY(launch_pack_f64(at<double>(workspace, pp.off_t1), m, (int)pp.LP, pp.LP, keep_q, (int)pp.LP, st));
+    SORSVD_TRY(launch_pack_f64(at<double>(workspace, pp.off_normp), pp.nn_blocks, 1, 1, keep_n, 1, st));
     SORSVD_TRY(launch_mlp_forward(params, feat, 1, y, work, st));
     float yh[4];
     SORSVD_TRY(hipMemcpyAsync(yh, y, sizeof(yh), hipMemcpyDeviceToHost, st));
@@ -854,7 +890,10 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     o.residual = a_type == SORSVD_BF16 ? 1 : 0;  // BF16: the identity cannot resolve 1e-3
     Plan p;
     if ((rc = make_plan(m, n, k, q, a_type, &o, &p))) return rc;
-    if ((rc = run(p, A, lda, seed, U, ldu, S, V, ldv, workspace, st))) return rc;
+    const bool reuse = keep_n && p.l <= keep_ld;
+    if ((rc = run(p, A, lda, seed, U, ldu, S, V, ldv, workspace, st, reuse ? keep_q : nullptr, keep_ld,
+                  reuse ? keep_n : nullptr, keep_parts)))
+      return rc;
     sorsvd_info info;
     SORSVD_TRY(hipMemcpyAsync(&info, workspace, sizeof(info), hipMemcpyDeviceToHost, st));
     SORSVD_TRY(hipStreamSynchronize(st));

@@ -124,6 +124,29 @@ def test_auto_fallback_and_judge(lib):
     assert not info2["met"] and info2["err"] > 1e-3
 
 
+def test_auto_run_from_probe_matches_oracle(lib):
+    # with the network, the run starts from the probe's Q (its leading k
+    # columns are Q1 of the run's first sketch): the result is the oracle's
+    # SOR-SVD with the chosen (k, q) and the same seed
+    from paper_1804_00462_amd import predictor as PR
+    m, n = 1500, 1200
+    A, _, _ = W.spectral(m, n, np.arange(1, n + 1) ** -2.5, 21)
+    U, S, V, info = lib.auto(torch.as_tensor(A).cuda(), 1e-3, PR.load_params(), seed=3)
+    assert info["met"] and info["used_fallback"] == 0 and info["runs"] == 1
+    k, q = info["k_used"], info["q_used"]
+    assert k < 128
+    Uo, So, Vo, io = osvd.sorsvd(A, k, q=q, seed=3)
+    S = host(S)
+    assert np.linalg.norm(S - So) <= 1e-10 * np.linalg.norm(So)
+    # identity e^2 = 1 - sum s^2 / ||A||^2: rounding of ~1e-14 in the two sums moves e by ~1e-14 / (2 e)
+    assert abs(info["err"] - io["err_fro"]) <= 1e-10
+    U, V = host(U), host(V)
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-11 and np.abs(V.T @ V - np.eye(k)).max() < 1e-11
+    # error record against the explicit residual
+    E = A - (U * S) @ V.T
+    assert abs(np.linalg.norm(E) / np.linalg.norm(A) - info["err"]) <= 1e-6 * info["err"]
+
+
 @pytest.mark.slow
 def test_learned_choice_gains_over_fixed_fallback(lib):
     """The trained network (committed weights) against the method without it
