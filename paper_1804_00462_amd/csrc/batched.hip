@@ -153,15 +153,25 @@ k_bdiag(const BProb* __restrict__ probs, const BItem* __restrict__ items, int ni
   }
 }
 
+// Whether a problem skips Cholesky-QR step `step` of the QR at power step
+// qiter (-1: before the loop): the third step runs only where the first one
+// shifted; a basis that only feeds the next product (every QR but those of
+// the problem's last power step) skips the second step as well, which leaves
+// it orthonormal to ~cond^2 u, a well-conditioned basis of the same span.
+__device__ inline bool qr_step_skipped(const BProb& P, int step, int qiter) {
+  if (step == 2) return *P.skip3 != 0;
+  return step == 1 && qiter != P.q - 1;
+}
+
 // FP64 products on the tall sketches, 64-row tiles, problems with LP = 16 CT
 // (lifts: KP = 16 CT).
 // Gram: T^T T (or Q1^T W) over one 512-row chunk, output rows [base, base + 64)
-// of that chunk's LP x LP partial. skip3 != 0: third Cholesky-QR step, only
-// for problems that asked for it.
+// of that chunk's LP x LP partial. step: the Cholesky-QR step (0 for the
+// projection); see qr_step_skipped.
 template <int CT>
 __global__ void __launch_bounds__(256, 2)
 k_bgram(const BProb* __restrict__ probs, const BItem* __restrict__ items, int nitems, int mode, int qiter,
-        int skip3) {
+        int step) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   double* Xs = reinterpret_cast<double*>(lds);
   double* red = reinterpret_cast<double*>(lds + xs_bytes<double, CT>());
@@ -169,7 +179,7 @@ k_bgram(const BProb* __restrict__ probs, const BItem* __restrict__ items, int ni
     const BItem I = items[it];
     const BProb& P = probs[I.prob];
     if (qiter >= 0 && qiter >= P.q) continue;
-    if (skip3 && *P.skip3) continue;
+    if (qr_step_skipped(P, step, qiter)) continue;
     const double* T = mode == M_GRAM2 ? P.T2 : P.T1;
     const double* Y = mode == M_PGRAM ? P.W : T;
     const int64_t rows = mode == M_GRAM2 ? P.n : P.m;
@@ -185,7 +195,7 @@ k_bgram(const BProb* __restrict__ probs, const BItem* __restrict__ items, int ni
 template <int CT>
 __global__ void __launch_bounds__(256, 2)
 k_bapply(const BProb* __restrict__ probs, const BItem* __restrict__ items, int nitems, int which, int qiter,
-         int skip3) {
+         int step) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   double* Xs = reinterpret_cast<double*>(lds);
   double* red = reinterpret_cast<double*>(lds + xs_bytes<double, CT>());
@@ -193,7 +203,7 @@ k_bapply(const BProb* __restrict__ probs, const BItem* __restrict__ items, int n
     const BItem I = items[it];
     const BProb& P = probs[I.prob];
     if (qiter >= 0 && qiter >= P.q) continue;
-    if (skip3 && *P.skip3) continue;
+    if (qr_step_skipped(P, step, qiter)) continue;
     double* T = which == 2 ? P.T2 : P.T1;
     skinny_tile<double, false, 1, CT>(T, P.LP, which == 2 ? P.n : P.m, 0, P.LP, P.Rinv, P.LP, I.base, 1,
                                       nullptr, T, P.LP, nullptr, Xs, red);
@@ -260,6 +270,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_bchol(const BProb* __restrict
   if (qiter >= 0 && qiter >= P.q) return;
   const int nparts = which == 2 ? P.gch_n : P.gch_m;
   const int64_t rows = which == 2 ? P.n : P.m;
+  if (mode == 1 && qr_step_skipped(P, 1, qiter)) return;
   chol_inv_body(P.gpart, nparts, (int64_t)P.LP * P.LP, P.LP, P.l, rows, mode, P.Rinv, P.skip3, P.info, sm);
 }
 
@@ -537,7 +548,7 @@ int launch_pass(const sorsvd_batch* b, void* ws, int mode, int qiter, const Cfg&
 }
 
 // mode: M_GRAM1 / M_GRAM2 / M_PGRAM, M_APPLY1 / M_APPLY2, M_LIFTU / M_LIFTV.
-int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int skip3, hipStream_t st) {
+int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int step, hipStream_t st) {
   const BProb* probs = dev_table(b, ws);
   for (int ci = 0; ci < 8; ++ci) {
     const int n = (int)b->items[mode][0][ci].size();
@@ -548,7 +559,7 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int skip3, 
       switch (ci + 1) {
 #define SORSVD_LP(C)                                                                                                \
   case C:                                                                                                           \
-    hipLaunchKernelGGL(k_bgram<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, mode, qiter, skip3);              \
+    hipLaunchKernelGGL(k_bgram<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, mode, qiter, step);              \
     break;
         SORSVD_CT_CASES(SORSVD_LP)
 #undef SORSVD_LP
@@ -558,7 +569,7 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int skip3, 
       switch (ci + 1) {
 #define SORSVD_LP(C)                                                                                                \
   case C:                                                                                                           \
-    hipLaunchKernelGGL(k_bapply<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, which, qiter, skip3);            \
+    hipLaunchKernelGGL(k_bapply<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, which, qiter, step);            \
     break;
         SORSVD_CT_CASES(SORSVD_LP)
 #undef SORSVD_LP
@@ -599,10 +610,10 @@ int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
     const int amode = which == 2 ? M_APPLY2 : M_APPLY1;
     for (int it = 0; it < 3; ++it) {
       int r;
-      if ((r = launch_f64(b, ws, gmode, qiter, it == 2, st))) return r;
+      if ((r = launch_f64(b, ws, gmode, qiter, it, st))) return r;
       hipLaunchKernelGGL(k_bchol, dim3(np), dim3(kSmallThreads), chol_shm, st, probs, which, it, qiter);
       SORSVD_TRY(hipGetLastError());
-      if ((r = launch_f64(b, ws, amode, qiter, it == 2, st))) return r;
+      if ((r = launch_f64(b, ws, amode, qiter, it, st))) return r;
     }
     return SORSVD_OK;
   };

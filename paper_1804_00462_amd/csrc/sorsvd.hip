@@ -236,7 +236,13 @@ template <typename T> T* at(void* ws, size_t off) { return reinterpret_cast<T*>(
 // Cholesky QR of T (rows x LP, FP64, padding columns zero) in place: two
 // steps T <- T R^{-1}, the first shifted when T is ill-conditioned, and then
 // a third step whose kernels return at once unless the first was shifted.
-int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void* ws, hipStream_t st) {
+// A basis that only feeds the next product (final = false: the Q1 and Q2 of
+// every power step but the last) takes one step when that step needed no
+// shift: its columns are then orthonormal to ~cond(T)^2 u, which is a
+// well-conditioned basis of the same span, and only the span enters the next
+// product. The bases that form M and the lifted factors take both steps.
+int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void* ws, hipStream_t st,
+                 bool final = true) {
   double* P = at<double>(ws, p.off_p);
   double* G = at<double>(ws, p.off_g);
   double* Rinv = at<double>(ws, p.off_rinv);
@@ -244,6 +250,7 @@ int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void
   void* info = at<void>(ws, p.off_info);
   const int LP = (int)p.LP;
   for (int it = 0; it < 3; ++it) {
+    if (!final && it == 1) continue;
     const int* skip = it == 2 ? skip3 : nullptr;
     SORSVD_TRY(launch_skinny_f64(true, T, LP, LP, rows, T, LP, LP, gram.kchunk, gram.nsplit, P,
                                  nullptr, skip, st));
@@ -379,23 +386,24 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
     SORSVD_TRY(launch_pack_f64(q1, p.m, (int)p.l, ldq1, T1, LP, st));
   } else {
     if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
-    if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+    if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st, p.q == 0))) return rc;
   }
   // T2 = A^T Q1 (eq. AT1; the span of A^T T1 by Lemma 1); Q2 = qr(T2).
   const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true);
   if (rc) return rc;
   if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
-  if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st))) return rc;
+  if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st, p.q == 0))) return rc;
   // Power method (Alg. 4 loop), orthonormalising after each product.
   for (int it = 0; it < p.q; ++it) {
+    const bool last = it == p.q - 1;
     const void* X = as_operand(p, T2, p.n, ws, st, &rc);
     if (rc) return rc;
     if ((rc = pass(p, false, A, lda, X, T1, nullptr, ws, st))) return rc;
-    if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+    if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st, last))) return rc;
     Y = as_operand(p, T1, p.m, ws, st, &rc, true);
     if (rc) return rc;
     if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
-    if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st))) return rc;
+    if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st, last))) return rc;
   }
   // M = Q1^T (A Q2) (eq. M): W = A Q2 in the pass kernel, then the FP64 Q1^T W.
   const void* X = as_operand(p, T2, p.n, ws, st, &rc, false, p.refine != 0);
