@@ -595,7 +595,7 @@ int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
   const BProb* probs = dev_table(b, ws);
   const unsigned np = (unsigned)b->count;
   const dim3 g2((unsigned)std::max<int64_t>(1, (b->max_elems + kElemsPerBlock - 1) / kElemsPerBlock), np);
-  const size_t chol_shm = ((size_t)b->max_l * b->max_l + b->max_l) * 8;
+  const size_t chol_shm = chol_lds(b->max_l);
   int rc;
 
   hipLaunchKernelGGL((k_bclear<TA>), g2, dim3(256), 0, st, probs);

@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) k_fill(double* p, int64_t n, double v) {
 
 hipError_t launch_chol_inv(const double* G, int LP, int l, int64_t rows, int mode, double* Rinv,
                            int* skip3, void* info, hipStream_t st) {
-  const size_t shm = ((size_t)l * l + l) * sizeof(double);
+  const size_t shm = chol_lds(l);
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kSmallThreads), shm, st, G, LP, l, rows, mode, Rinv,
                      skip3, (DevInfo*)info);
   return hipGetLastError();

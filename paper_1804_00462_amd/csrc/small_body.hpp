@@ -43,96 +43,199 @@ struct DevInfo {  // mirrors sorsvd_info
 // up to ~1/u into that range. A pivot that is still not positive after the
 // shift (a column dependent to rounding, or NaN) drops its column: it
 // eliminates nothing and its column of R^{-1} is zero (flag bit 2).
-constexpr int kCholRetry = 1;
 
-// LDL^T elimination of the l x l SPD matrix held in the upper triangle of S,
-// carrying W = L^{-1} (unit lower triangular) in the strict lower triangle:
-// step j subtracts f_a = S[j][a] / S[j][j] times row j from every row a > j,
-// on the trailing upper triangle of S and on W's columns 0..j. The pivots
-// d_j stay on the diagonal. One barrier per step. Then R = D^{1/2} L^T and
+// LDL^T elimination of the l x l SPD matrix G (+ shift on the diagonal),
+// carrying W = L^{-1} (unit lower triangular) in the strict lower part of each
+// row: step j subtracts f_a = S[j][a] / S[j][j] times row j from every row
+// a > j, on the trailing upper part (columns >= a) and on W's columns 0..j.
+// The pivots d_j stay on the diagonal. Then R = D^{1/2} L^T and
 // R^{-1} = L^{-T} D^{-1/2} = W^T D^{-1/2}.
-__device__ inline int ldl_inverse(double* S, int l, double shift, const double* d0, bool check,
-                                  DevInfo* info) {
-  const int tid = threadIdx.x;
-  const int tx = tid % 32, ty = tid / 32;
-  if (shift != 0.0)
-    for (int i = tid; i < l; i += kSmallThreads) S[i * l + i] += shift;
-  __syncthreads();
-  for (int j = 0; j < l; ++j) {
-    const double d = S[j * l + j];
-    if (check && !(d > 1e-13 * d0[j])) return kCholRetry;  // every thread sees the same d
-    double dinv = 1.0 / d;
-    if (!(d > 0.0)) {  // not positive after the shift (or NaN): drop column j
-      if (tid == 0) atomicOr(&info->flags, kFlagQrBreakdown);
-      dinv = 0.0;
-    }
-    const double* rowj = S + j * l;
-    for (int a = j + 1 + ty; a < l; a += kSmallThreads / 32) {
-      const double f = rowj[a] * dinv;
-      double* rowa = S + a * l;
-#pragma unroll 4
-      for (int c = a + tx; c < l; c += 32) rowa[c] -= f * rowj[c];
-#pragma unroll 4
-      for (int c = tx; c <= j; c += 32) rowa[c] -= f * (c == j ? 1.0 : rowj[c]);
-    }
-    __syncthreads();
-  }
-  return 0;
+//
+// Dataflow form: wave w holds rows a = w + 16 i in registers (lane holds
+// columns lane and lane + 64) and finishes them in increasing order, each by
+// applying the steps j < a in order from the published rows j (left-looking:
+// the same operations in the same order as the row-by-row elimination). A
+// finished row is published to LDS with 1 in place of its pivot d_a (the
+// unit diagonal of W, which is what the later steps subtract) and with
+// 1/d_a beside it, and a counter of published
+// rows is raised; rows finish in index order, so the chain costs one step and
+// one hand-off per row instead of a workgroup barrier per step. Every wait is
+// bounded: after ~1e6 polls a wave stops waiting and the result is flagged as
+// a breakdown.
+constexpr int kCholWaves = kSmallThreads / 64;
+constexpr int kCholRowsPerWave = (128 + kCholWaves - 1) / kCholWaves;  // l <= 128
+
+struct CholRows {
+  double v[kCholRowsPerWave][2];
+};
+
+__device__ inline double chol_gval(const double* __restrict__ G, int nparts, int64_t pstride, int LP, int r,
+                                   int c) {
+  double v = 0.0;
+  for (int p = 0; p < nparts; ++p) v += G[p * pstride + r * LP + c];
+  return v;
 }
 
+// check: a pivot below 1e-13 of the original diagonal sets *retry (every
+// wave finishes its rows regardless, so that no wait is left open). Pub: LDS
+// of l * l doubles; pinv: l doubles; *nready and *retry zero on entry.
+__device__ inline void ldl_flow(const double* __restrict__ G, int nparts, int64_t pstride, int LP, int l,
+                                double shift, const double* d0, bool check, double* Pub, double* pinv,
+                                int* nready, int* retry, DevInfo* info, CholRows& R) {
+  // (the wave index through readfirstlane: known uniform, so that row and
+  // step bounds live in scalar registers and the loops are not divergent)
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  bool bail = false;
+  int known = 0;  // rows known to be published
+#pragma unroll
+  for (int i = 0; i < kCholRowsPerWave; ++i) {
+    const int a = w + kCholWaves * i;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = lane + 64 * h;
+      double v = 0.0;
+      if (a < l && c < l && c >= a) v = chol_gval(G, nparts, pstride, LP, a, c) + (c == a ? shift : 0.0);
+      R.v[i][h] = v;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kCholRowsPerWave; ++i) {
+    const int a = w + kCholWaves * i;
+    if (a < l) {
+    // steps j < a in chunks of published rows: the multipliers f_j of a chunk
+    // (at most 64) are read at once, one per lane, and broadcast from there
+    bool ge_a[2];
+    int cc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      ge_a[h] = lane + 64 * h >= a;
+      cc[h] = min(lane + 64 * h, l - 1);  // clamped column: loads stay in row t
+    }
+    int j = 0;
+    while (j < a) {
+      if (j >= known) {
+        int spins = 0;
+        while (!bail) {
+          known = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(nready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+          if (known > j) break;
+          if (spins > 64) __builtin_amdgcn_s_sleep(1);  // poll tightly for a while first
+          if (++spins > (1 << 20)) bail = true;
+        }
+        if (bail) known = a;
+      }
+      const int jend = min(min(known, a), j + 64);
+      const int jl = j + lane;
+      const double fv = jl < jend ? Pub[jl * l + a] * pinv[jl] : 0.0;
+      const int flo = __double2loint(fv), fhi = __double2hiint(fv);
+      // published row t holds W[t][c] (c < t), 1 (c = t), S[t][c] (c > t):
+      // lane c < a takes it for c <= t, lane c >= a always. Loads and FMAs
+      // are unconditional with the mask on the multiplier (v - 0 p = v), and
+      // the loads of four steps are issued before their FMAs.
+      double v0 = R.v[i][0], v1 = R.v[i][1];
+      int t = j;
+      for (; t + 4 <= jend; t += 4) {
+        double p0[4], p1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          p0[u] = Pub[(t + u) * l + cc[0]];
+          p1[u] = Pub[(t + u) * l + cc[1]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double f = __hiloint2double(__builtin_amdgcn_readlane(fhi, t + u - j),
+                                            __builtin_amdgcn_readlane(flo, t + u - j));
+          v0 = fma(-((lane <= t + u || ge_a[0]) ? f : 0.0), p0[u], v0);
+          v1 = fma(-((lane + 64 <= t + u || ge_a[1]) ? f : 0.0), p1[u], v1);
+        }
+      }
+      for (; t < jend; ++t) {
+        const double f = __hiloint2double(__builtin_amdgcn_readlane(fhi, t - j), __builtin_amdgcn_readlane(flo, t - j));
+        v0 = fma(-((lane <= t || ge_a[0]) ? f : 0.0), Pub[t * l + cc[0]], v0);
+        v1 = fma(-((lane + 64 <= t || ge_a[1]) ? f : 0.0), Pub[t * l + cc[1]], v1);
+      }
+      R.v[i][0] = v0;
+      R.v[i][1] = v1;
+      j = jend;
+    }
+    // row a is final: its pivot, then publish
+    const double dsrc = a < 64 ? R.v[i][0] : R.v[i][1];
+    const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(dsrc), a % 64),
+                                      __builtin_amdgcn_readlane(__double2loint(dsrc), a % 64));
+    double dinv = 1.0 / d;
+    if (check) {
+      if (!(d > 1e-13 * d0[a]) && lane == 0) *retry = 1;
+    } else if (!(d > 0.0)) {  // not positive after the shift (or NaN): drop column a
+      if (lane == 0) atomicOr(&info->flags, kFlagQrBreakdown);
+      dinv = 0.0;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = lane + 64 * h;
+      if (c < l) Pub[a * l + c] = c == a ? 1.0 : R.v[i][h];
+    }
+    if (lane == 0) pinv[a] = dinv;
+    __hip_atomic_store(nready, a + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+  if (bail && lane == 0) atomicOr(&info->flags, kFlagQrBreakdown);
+}
+
+// LDS of the Cholesky body: published rows, 1/d, the diagonal of G, and two
+// counters.
+__host__ __device__ inline size_t chol_lds(int l) { return ((size_t)l * l + 2 * l) * 8 + 16; }
+
 // G is given as nparts partial sums (stride pstride elements), added here in
-// order; sm: LDS of (l * l + l) doubles.
+// order; sm: LDS of chol_lds(l) bytes.
 __device__ inline void chol_inv_body(const double* __restrict__ G, int nparts, int64_t pstride, int LP,
                                      int l, int64_t rows, int mode, double* __restrict__ Rinv,
                                      int* __restrict__ skip3, DevInfo* __restrict__ info, double* sm) {
   if (mode == 2 && *skip3) return;
-  double* S = sm;               // l x l: upper = S, strict lower = W
-  double* d0 = sm + l * l;      // l: diagonal of G
+  double* Pub = sm;             // l x l: published final rows
+  double* pinv = sm + l * l;    // l: 1 / d
+  double* d0 = pinv + l;        // l: diagonal of G
+  int* nready = reinterpret_cast<int*>(d0 + l);
+  int* retry = nready + 1;
   const int tid = threadIdx.x;
-  auto gval = [&](int r, int c) {
-    double v = 0.0;
-    for (int p = 0; p < nparts; ++p) v += G[p * pstride + r * LP + c];
-    return v;
-  };
-
-  auto load = [&]() {
-    for (int i = tid; i < l * l; i += kSmallThreads) {
-      const int r = i / l, c = i % l;
-      S[i] = (c >= r) ? gval(r, c) : 0.0;
-    }
-  };
-  load();
-  for (int i = tid; i < l; i += kSmallThreads) d0[i] = gval(i, i);
+  for (int i = tid; i < l; i += kSmallThreads) d0[i] = chol_gval(G, nparts, pstride, LP, i, i);
+  if (tid == 0) { *nready = 0; *retry = 0; }
+  __syncthreads();
+  CholRows R;
+  ldl_flow(G, nparts, pstride, LP, l, 0.0, d0, true, Pub, pinv, nready, retry, info, R);
   __syncthreads();
   bool shifted = false;
-  if (ldl_inverse(S, l, 0.0, d0, true, info) == kCholRetry) {
-    __syncthreads();
+  if (*retry) {
     double tr = 0.0;
     for (int i = 0; i < l; ++i) tr += d0[i];
     const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 0x1p-53 * tr;
-    load();
     __syncthreads();
-    ldl_inverse(S, l, shift, d0, false, info);
+    if (tid == 0) *nready = 0;
+    __syncthreads();
+    ldl_flow(G, nparts, pstride, LP, l, shift, d0, false, Pub, pinv, nready, retry, info, R);
     shifted = true;
   }
   if (tid == 0) {
     if (shifted) *skip3 = 0;
     else if (mode == 0) *skip3 = 1;
   }
-  __syncthreads();
   // R^{-1}[r][c] = W[c][r] / sqrt(d_c) for r < c, 1 / sqrt(d_c) on the diagonal;
-  // a dropped column (d_c not positive) is zero.
-  for (int i = tid; i < LP * LP; i += kSmallThreads) {
-    const int r = i / LP, c = i % LP;
-    double v = 0.0;
-    if (r < l && c < l && c >= r) {
-      const double d = S[c * l + c];
-      if (d > 0.0) {
-        const double isd = 1.0 / sqrt(d);
-        v = (r == c) ? isd : S[c * l + r] * isd;
-      }
+  // a dropped column (d_c not positive) is zero. Zeros first, then each wave
+  // writes the columns of its rows.
+  for (int i = tid; i < LP * LP; i += kSmallThreads) Rinv[i] = 0.0;
+  __syncthreads();
+  const int w = tid / 64, lane = tid % 64;
+#pragma unroll
+  for (int i = 0; i < kCholRowsPerWave; ++i) {
+    const int c = w + kCholWaves * i;  // row c of the factor = column c of R^{-1}
+    if (c >= l) continue;
+    const double dc = __shfl(c < 64 ? R.v[i][0] : R.v[i][1], c % 64, kWave);
+    const double isd = dc > 0.0 ? 1.0 / sqrt(dc) : 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = lane + 64 * h;
+      if (r < c) Rinv[r * LP + c] = R.v[i][h] * isd;
+      else if (r == c) Rinv[r * LP + c] = isd;
     }
-    Rinv[i] = v;
   }
 }
 
