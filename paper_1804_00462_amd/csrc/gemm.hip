@@ -64,6 +64,40 @@ k_reduce(const Acc* __restrict__ P, int64_t OUT, int LP, int nsplit, double* __r
   }
 }
 
+// FP32 partials: out[r][c] = sum_{s = 0..nsplit-1} P[s][r][c] in FP64, added
+// in split order. Each thread takes four consecutive outputs (16-byte loads;
+// LP is a multiple of 16, so the four share a row) and issues the loads of
+// eight splits before adding them.
+__global__ void __launch_bounds__(256)
+k_reduce4(const float* __restrict__ P, int64_t OUT, int LP, int nsplit, double* __restrict__ out, int64_t ldo,
+          int ncols) {
+  const int64_t total = OUT * LP;
+  const int64_t idx = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (idx >= total) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int s = 0;
+  for (; s + 8 <= nsplit; s += 8) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const float4*>(P + (int64_t)(s + u) * total + idx);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a0 += (double)v[u].x; a1 += (double)v[u].y; a2 += (double)v[u].z; a3 += (double)v[u].w;
+    }
+  }
+  for (; s < nsplit; ++s) {
+    const float4 v = *reinterpret_cast<const float4*>(P + (int64_t)s * total + idx);
+    a0 += (double)v.x; a1 += (double)v.y; a2 += (double)v.z; a3 += (double)v.w;
+  }
+  const int64_t r = idx / LP;
+  const int c = (int)(idx % LP);
+  double* o = out + r * ldo + c;
+  if (c < ncols) o[0] = a0;
+  if (c + 1 < ncols) o[1] = a1;
+  if (c + 2 < ncols) o[2] = a2;
+  if (c + 3 < ncols) o[3] = a3;
+}
+
 // dst[r][c] = src[r][c] for c < cols, 0 for cols <= c < LP (row-major, element type T).
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -182,8 +216,9 @@ hipError_t launch_reduce_f32(const float* P, int64_t OUT, int LP, int nsplit, do
                              int64_t ldo, int ncols, hipStream_t st) {
   const int64_t total = OUT * LP;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_reduce<float>), dim3((unsigned)ceil_div(total, 64)), dim3(512), 0, st,
-                     P, OUT, LP, nsplit, out, ldo, ncols);
+  if (LP % 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce4, dim3((unsigned)ceil_div(total / 4, 256)), dim3(256), 0, st, P, OUT, LP, nsplit,
+                     out, ldo, ncols);
   return hipGetLastError();
 }
 
