@@ -12,6 +12,10 @@
 // slab of the skinny operand, which then stays in that XCD's L2.
 #include <algorithm>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "skinny_body.hpp"
 
 namespace sor {
@@ -201,6 +205,53 @@ hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OU
 }
 
 int skinny_rows_per_block(int a_type, int64_t OUT) { return 64 * skinny_rt(a_type, OUT); }
+
+// Workgroups of the pass kernel (FP64 a_type 0 / FP32 a_type 1, LP = 16 CT)
+// that the current device holds at once: resident workgroups per CU (from
+// the kernel's registers and LDS) times the CUs. 0 when no device answers.
+template <typename T, bool TRANS>
+static int skinny_blocks_per_cu(int CT) {
+  constexpr int RT = has_rt1<T>() ? 1 : 2;
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define SORSVD_CASE(C)                                                                                     \
+  case C:                                                                                                  \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_skinny<T, TRANS, RT, C>), \
+                                                     256, 0);                                              \
+    break;
+  switch (CT) {
+    SORSVD_CASE(1) SORSVD_CASE(2) SORSVD_CASE(3) SORSVD_CASE(4)
+    SORSVD_CASE(5) SORSVD_CASE(6) SORSVD_CASE(7) SORSVD_CASE(8)
+    default: break;
+  }
+#undef SORSVD_CASE
+  return e == hipSuccess ? nb : 0;
+}
+
+int skinny_slots(int a_type, bool trans, int LP) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, bool, int>, int> cache;
+  if ((a_type != 0 && a_type != 1) || LP % kTile || LP < kTile || LP > 8 * kTile) return 0;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  std::lock_guard<std::mutex> g(mu);
+  const auto key = std::make_tuple(dev, a_type, trans, LP);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+  const int CT = LP / kTile;
+  int nb;
+  if (a_type == 0) nb = trans ? skinny_blocks_per_cu<double, true>(CT) : skinny_blocks_per_cu<double, false>(CT);
+  else nb = trans ? skinny_blocks_per_cu<float, true>(CT) : skinny_blocks_per_cu<float, false>(CT);
+  (void)hipGetLastError();
+  const int slots = cus > 0 && nb > 0 ? cus * nb : 0;
+  cache[key] = slots;
+  return slots;
+}
 int skinny_step(int a_type) { return a_type == 0 ? 32 : (a_type == 1 ? 32 : 128); }
 
 hipError_t launch_reduce_f64(const double* P, int64_t OUT, int LP, int nsplit, double* out,

@@ -40,6 +40,7 @@ hipError_t launch_zero_lower(double* R, int l, hipStream_t st);
 hipError_t launch_diag_pass(const double* sigma, int64_t n, int LP, const double* X, double* T, double* normp,
                             int nparts, hipStream_t st);
 int skinny_rows_per_block(int a_type, int64_t OUT);
+int skinny_slots(int a_type, bool trans, int LP);
 int skinny_step(int a_type);
 // gemm_bf16.hip
 hipError_t launch_bf16_pass(bool trans, const bf16_t* A, int64_t lda, int64_t OUT, int64_t K,
@@ -101,9 +102,13 @@ struct Split {
 // Split of a contraction of length K for OUT output rows: enough workgroups
 // to fill 256 CUs several times over, each split at least `min_steps` steps
 // long, and partial sums no larger than 1/`part_div` of the bytes of the
-// streamed operand.
+// streamed operand. slots > 0 (workgroups the device holds at once): among
+// the splits from half of that count up to it, the one whose workgroups fill
+// whole waves of `slots` best (a last, mostly empty wave of workgroups costs
+// as much as a full one); never more splits than without it, so a workspace
+// sized without a device also fits.
 Split choose_split(int64_t OUT, int64_t K, int rows_per_block, int KS, int LP, int es_a,
-                   int acc_bytes, int forced, int min_steps = 8, int part_div = 8) {
+                   int acc_bytes, int forced, int min_steps = 8, int part_div = 8, int slots = 0) {
   Split sp;
   if (K <= 0) { sp.kchunk = KS; sp.nsplit = 1; return sp; }
   const int64_t tiles = std::max<int64_t>(1, ceil_div(OUT, rows_per_block));
@@ -113,6 +118,22 @@ Split choose_split(int64_t OUT, int64_t K, int rows_per_block, int KS, int LP, i
   if (forced > 0) s = forced;
   sp.kchunk = round_up(ceil_div(K, s), KS);
   sp.nsplit = (int)ceil_div(K, sp.kchunk);
+  if (forced <= 0 && slots > 0 && sp.nsplit > 1) {
+    double best = -1.0;
+    Split pick = sp;
+    for (int64_t c = sp.nsplit; c >= std::max<int64_t>(1, sp.nsplit / 2); --c) {
+      Split t;
+      t.kchunk = round_up(ceil_div(K, c), KS);
+      t.nsplit = (int)ceil_div(K, t.kchunk);
+      const int64_t W = tiles * t.nsplit;
+      const double fill = (double)W / (double)(ceil_div(W, slots) * slots);
+      if (fill > best + 1e-9) {
+        best = fill;
+        pick = t;
+      }
+    }
+    sp = pick;
+  }
   return sp;
 }
 
@@ -180,8 +201,12 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   const int rpb_n = a_type == SORSVD_BF16 ? 64 * p->rt_tn : skinny_rows_per_block(t64, n);
   const int ks_nn = a_type == SORSVD_BF16 ? bf16_step(false, p->rt_nn) : ks;
   const int ks_tn = a_type == SORSVD_BF16 ? bf16_step(true, p->rt_tn) : ks;
-  p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced);
-  p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced);
+  const bool skinny_pass = a_type == SORSVD_F32 || a_type == SORSVD_F64;
+  const int tcode = a_type == SORSVD_F32 ? 1 : 0;
+  p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced, 8, 8,
+                       skinny_pass ? skinny_slots(tcode, false, (int)LP) : 0);
+  p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced, 8, 8,
+                       skinny_pass ? skinny_slots(tcode, true, (int)LP) : 0);
   p->projb = choose_split(m, n, 64 * p->rt_proj, 128, (int)LP * (p->refine ? 2 : 1), p->es, acc, forced);
   // l x l products over a tall FP64 operand: many short splits (the partial
   // sums are small next to the operand)
