@@ -22,6 +22,10 @@
 //     permutation (position 8 g + t of each 32-block holds row 4 t + g), so
 //     its fragment is again one 16-byte read.
 // Partial sums per contraction split are summed afterwards in a fixed order.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "common.hpp"
 
 namespace sor {
@@ -383,6 +387,53 @@ hipError_t launch_bf16_pass(bool trans, const bf16_t* A, int64_t lda, int64_t OU
     case 4: return launch_bf16_rt<4>(trans, A, lda, OUT, K, XT, ldx, LP, kchunk, nsplit, P, normp, Tout, fold, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Workgroups of a BF16 pass kernel that the current device holds at once
+// (resident workgroups per CU times the CUs); 0 when no device answers.
+template <int RT>
+static int bf16_blocks_per_cu(bool trans, int CT) {
+  constexpr int KST = RT >= 4 ? 64 : 128;
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define SORSVD_BF(C, D)                                                                                       \
+  case C:                                                                                                     \
+    e = trans ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                 \
+                    &nb, reinterpret_cast<const void*>(&k_bf16_tn<RT, C, KST>), 256, 0)                      \
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                 \
+                    &nb, reinterpret_cast<const void*>(&k_bf16_nn<RT, C, D>), 256, 0);                       \
+    break;
+  switch (CT) {
+    SORSVD_BF(1, 4) SORSVD_BF(2, 4) SORSVD_BF(3, 4) SORSVD_BF(4, 4) SORSVD_BF(5, 3) SORSVD_BF(6, 3)
+    SORSVD_BF(7, 3) SORSVD_BF(8, 3) SORSVD_BF(10, 2) SORSVD_BF(12, 2) SORSVD_BF(14, 2) SORSVD_BF(16, 2)
+    default: break;
+  }
+#undef SORSVD_BF
+  return e == hipSuccess ? nb : 0;
+}
+
+int bf16_slots(bool trans, int rt, int LP) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, bool, int, int>, int> cache;
+  if (LP % kTile || LP < kTile || (rt != 1 && rt != 2 && rt != 4)) return 0;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  std::lock_guard<std::mutex> g(mu);
+  const auto key = std::make_tuple(dev, trans, rt, LP);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+  const int CT = LP / kTile;
+  const int nb = rt == 1 ? bf16_blocks_per_cu<1>(trans, CT)
+                         : (rt == 2 ? bf16_blocks_per_cu<2>(trans, CT) : bf16_blocks_per_cu<4>(trans, CT));
+  (void)hipGetLastError();
+  const int slots = cus > 0 && nb > 0 ? cus * nb : 0;
+  cache[key] = slots;
+  return slots;
 }
 
 // contraction step of the bf16 kernels for a given rt (splits are multiples of it)

@@ -41,6 +41,7 @@ hipError_t launch_diag_pass(const double* sigma, int64_t n, int LP, const double
                             int nparts, hipStream_t st);
 int skinny_rows_per_block(int a_type, int64_t OUT);
 int skinny_slots(int a_type, bool trans, int LP);
+int bf16_slots(bool trans, int rt, int LP);
 int skinny_step(int a_type);
 // gemm_bf16.hip
 hipError_t launch_bf16_pass(bool trans, const bf16_t* A, int64_t lda, int64_t OUT, int64_t K,
@@ -203,11 +204,16 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   const int ks_tn = a_type == SORSVD_BF16 ? bf16_step(true, p->rt_tn) : ks;
   const bool skinny_pass = a_type == SORSVD_F32 || a_type == SORSVD_F64;
   const int tcode = a_type == SORSVD_F32 ? 1 : 0;
+  const bool bf16 = a_type == SORSVD_BF16;
   p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced, 8, 8,
-                       skinny_pass ? skinny_slots(tcode, false, (int)LP) : 0);
+                       skinny_pass ? skinny_slots(tcode, false, (int)LP)
+                                   : (bf16 ? bf16_slots(false, p->rt_nn, (int)LP) : 0));
   p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced, 8, 8,
-                       skinny_pass ? skinny_slots(tcode, true, (int)LP) : 0);
-  p->projb = choose_split(m, n, 64 * p->rt_proj, 128, (int)LP * (p->refine ? 2 : 1), p->es, acc, forced);
+                       skinny_pass ? skinny_slots(tcode, true, (int)LP)
+                                   : (bf16 ? bf16_slots(true, p->rt_tn, (int)LP) : 0));
+  const int LPproj = (int)LP * (p->refine ? 2 : 1);
+  p->projb = choose_split(m, n, 64 * p->rt_proj, 128, LPproj, p->es, acc, forced, 8, 8,
+                          bf16 ? bf16_slots(false, p->rt_proj, LPproj) : 0);
   // l x l products over a tall FP64 operand: many short splits (the partial
   // sums are small next to the operand)
   const int ks64 = skinny_step(SORSVD_F64);
