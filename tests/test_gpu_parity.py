@@ -100,7 +100,8 @@ def test_sketch_and_orbit_fp32(lib, m, n, l):
     assert np.abs(T2 - ref2).max() <= 2e-6 * np.sqrt(m) * np.abs(A).max() * np.abs(Y).max()
 
 
-@pytest.mark.parametrize("rows,l,cond", [(1000, 20, 1e2), (20000, 100, 1e4), (333, 17, 1e7), (64, 64, 10.0)])
+@pytest.mark.parametrize("rows,l,cond", [(1000, 20, 1e2), (20000, 100, 1e4), (333, 17, 1e7), (64, 64, 10.0),
+                                         (5000, 128, 1e9), (3000, 77, 1e11)])
 def test_qr_matches_householder_with_positive_diagonal(lib, rows, l, cond):
     gen = W.rng(rows + l)
     U = W.haar_columns(rows, l, gen)
