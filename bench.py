@@ -36,7 +36,11 @@ WORKLOADS = {
            "BF16 MFMA passes, hi+lo refinement projection, FP64 QR and core SVD"),
     "c1": (1000, 800, 20, 0, "float64", 0,
            "plain SOR-SVD FP64: A = X Y^T + 1e-3 E (1000 x 800, seed 0), k = 20, q = 0, Omega seed 1"),
+    "c2pe": (20000, 20000, 100, 1, "float32", 0,
+             "C2 with the pass-efficient core matrix (eq. M_approx, formed as T2^T Q2 from the last orbit "
+             "product: 2q + 2 = 4 passes over A)"),
 }
+PASS_EFFICIENT = {"c2pe"}
 
 C4_DESC = ("batched SOR-SVD FP32: 512 RPCA-style problems L + S (L = X Y^T, N(0,1) factors of rank r, "
            "S = 5% outliers U[-10, 10]), m ~ U[256, 4096], n ~ U[128, 2048], r ~ U[4, 64] (seed 3), "
@@ -82,7 +86,7 @@ def make_input(name, torch, quick=False):
         g = torch.Generator(device="cuda")
         g.manual_seed(7)
         return torch.randn(m, n, generator=g, device="cuda", dtype=torch.float32).to(getattr(torch, dname))
-    if name == "c2":
+    if name in ("c2", "c2pe"):
         return W.c2_torch("cuda")
     if name == "c3":
         return W.c3_torch("cuda")
@@ -123,14 +127,15 @@ def run_workload(name, steps, warmup, torch, P, quick=False):
     A = make_input(name, torch, quick)
     torch.cuda.synchronize()
     log(f"[bench] input ready in {time.perf_counter() - t0:.1f} s; dtype {A.dtype}")
-    plan = P.Plan(m, n, k, q, A.dtype, refine=refine)
+    pe = 1 if name in PASS_EFFICIENT else 0
+    plan = P.Plan(m, n, k, q, A.dtype, refine=refine, pass_efficient=pe)
     es = A.element_size()
 
     for _ in range(warmup):
         plan.run(A, seed)
     torch.cuda.synchronize()
 
-    passes = 2 * q + 3
+    passes = 2 * q + 3 - pe
     P.pass_timing(True, capacity=steps * passes + 8)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -262,7 +267,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
-    ap.add_argument("--extra", default="c3,c1,c4,c5", help="comma-separated extra workloads ('' for none)")
+    ap.add_argument("--extra", default="c3,c1,c4,c5,c2pe", help="comma-separated extra workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick-input", action="store_true",
                     help="N(0, 1) entries of the workload's shape instead of its spectrum (counter runs only)")

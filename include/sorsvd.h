@@ -67,7 +67,14 @@ typedef struct sorsvd_opts {
                          FP32 MFMA for FP32 / BF16 A, FP64 for FP64 A, FP64 accumulation) */
   int32_t split;      /* split of the contraction in the passes; 0 = automatic */
   int32_t tile;       /* BF16 passes: 64*tile rows (columns) of A per workgroup, tile in {1,2,4}; 0 = automatic */
-  int32_t reserved1;
+  int32_t pass_efficient; /* 1 = the pass-efficient core matrix (Sec. III, eq. M_approx): 2q + 2
+                             passes instead of 2q + 3. With orthonormalisation after every
+                             product, Q2 spans A^T Q1, so Q1^T A = R2^T Q2^T and M_approx equals
+                             M = Q1^T A Q2 in exact arithmetic; it is formed as T2^T Q2 from the
+                             last orbit product T2 = A^T Q1 kept before its QR (FP64, no
+                             pseudo-inverse, no pass over A). FP32 / FP64 / diagonal A only
+                             (SORSVD_EUNSUPPORTED for BF16 A, whose core matrix needs the
+                             refinement pass). The error identity stays valid. */
 } sorsvd_opts;
 
 /* Result record, kept by the library in the first 256 bytes of the workspace. */

@@ -9,6 +9,14 @@ Alg. 3 (basic SOR-SVD) and Alg. 4 (SOR-SVD with power method):
      implied by the lift in step 6)
   6. A_hat = (Q1 U~_k) S~_k (Q2 V~_k)^T
 
+Step 4 has two forms (``m_form``):
+  * ``"exact"`` (default): M = Q1^T A Q2 (eq. M), one more pass over A.
+  * ``"approx"``: the pass-efficient M_approx = Q1^T T1 (Q2^T X)^+ (eq.
+    M_approx), from A ~ A Q2 Q2^T: X is the operand that produced the last T1
+    (Omega when q = 0; in Alg. 4 the non-updated T2 of the last round, in
+    the canonical reading the Q2 of the previous round), and ^+ is the
+    Moore-Penrose pseudo-inverse.
+
 Two readings of step 2 are offered:
   * ``mode="canonical"`` (default): orthonormalise after every product,
     Q1 = qr(A Q2), Q2 = qr(A^T Q1). By Lemma 1 (Gu) QR(B X) and QR(B X Y) give
@@ -57,7 +65,7 @@ def omega(seed, n, l):
     return gaussian_matrix(seed, n, l, stream=0)
 
 
-def sorsvd(A, k, q=0, seed=0, l=None, mode="canonical", Omega=None, return_all=False):
+def sorsvd(A, k, q=0, seed=0, l=None, mode="canonical", Omega=None, return_all=False, m_form="exact"):
     """SOR-SVD of A (m x n) to rank k with sketch width l (default l = k) and q power steps.
 
     Returns (U, s, V, info): U m x k, s length k (descending), V n x k, and
@@ -76,23 +84,33 @@ def sorsvd(A, k, q=0, seed=0, l=None, mode="canonical", Omega=None, return_all=F
     if Omega is None:
         Omega = omega(seed, n, l)
 
+    if m_form not in ("exact", "approx"):
+        raise ValueError(m_form)
     if mode == "canonical":
-        Q1, _ = qr_pos(A @ Omega)                 # eq. (T1) + QR
+        X = Omega
+        T1 = A @ X                                # eq. (T1)
+        Q1, _ = qr_pos(T1)
         Q2, R2 = qr_pos(A.T @ Q1)                 # eq. (AT1) + QR (span of A^T T1)
         for _ in range(q):                        # Alg. 4 power loop
-            Q1, _ = qr_pos(A @ Q2)
+            X = Q2
+            T1 = A @ X
+            Q1, _ = qr_pos(T1)
             Q2, R2 = qr_pos(A.T @ Q1)
     elif mode == "literal":
         T2 = Omega
         for _ in range(q + 1):                    # Alg. 4 loop, no intermediate QR
-            T1 = A @ T2
+            X = T2                                # the non-updated T2 of this round
+            T1 = A @ X
             T2 = A.T @ T1
         Q1, _ = qr_pos(T1)
         Q2, R2 = qr_pos(T2)
     else:
         raise ValueError(mode)
 
-    M = Q1.T @ (A @ Q2)                           # eq. (M)
+    if m_form == "exact":
+        M = Q1.T @ (A @ Q2)                       # eq. (M)
+    else:
+        M = (Q1.T @ T1) @ np.linalg.pinv(Q2.T @ X)  # eq. (M_approx)
     Ut, s, Vt = np.linalg.svd(M)                  # core SVD, descending
     Uk, sk, Vk = Ut[:, :k], s[:k], Vt[:k, :].T    # truncation to rank k
     U = Q1 @ Uk                                   # lift (Alg. 3 step 7)
@@ -109,7 +127,7 @@ def sorsvd(A, k, q=0, seed=0, l=None, mode="canonical", Omega=None, return_all=F
         info["err_fro"] = 0.0
         info["err_fro_identity"] = 0.0
     if return_all:
-        info.update(Q1=Q1, Q2=Q2, M=M, Omega=Omega, R2=R2, s_all=s)
+        info.update(Q1=Q1, Q2=Q2, M=M, Omega=Omega, R2=R2, s_all=s, X=X, T1=T1)
     return U, sk, V, info
 
 

@@ -29,7 +29,7 @@ class SorsvdError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("l", c_i64), ("max_sweeps", c_i32), ("refine", c_i32), ("residual", c_i32),
-                ("split", c_i32), ("tile", c_i32), ("reserved1", c_i32)]
+                ("split", c_i32), ("tile", c_i32), ("pass_efficient", c_i32)]
 
 
 class Problem(ctypes.Structure):

@@ -47,8 +47,9 @@ def _info_dict(o):
             "sweeps": o.sweeps, "flags": o.flags, "a_noise_rel": o.a_noise_rel}
 
 
-def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0):
-    return Opts(l=l, max_sweeps=max_sweeps, refine=refine, residual=residual, split=split, tile=tile)
+def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0, pass_efficient=0):
+    return Opts(l=l, max_sweeps=max_sweeps, refine=refine, residual=residual, split=split, tile=tile,
+                pass_efficient=pass_efficient)
 
 
 def workspace_bytes(m, n, k, q, dtype_or_code, **opts):

@@ -155,6 +155,7 @@ struct Plan {
   int max_sweeps;
   int refine;     // BF16: projection pass with Q2 = hi + lo
   int residual;   // explicit residual pass after the lift
+  int pass_eff;   // M from the last orbit product (no projection pass)
   int64_t ldt;    // BF16: leading dimension of the transposed skinny operands
   int rt_nn, rt_tn, rt_proj;  // BF16: rows (NN) / columns (TN) of A per workgroup = 64 rt
   Split projb;    // BF16: split of the refinement projection pass
@@ -162,6 +163,7 @@ struct Plan {
   int nn_blocks;
   size_t off_info, off_xc, off_t1, off_t2, off_w, off_u64, off_v64, off_p, off_normp;
   size_t off_g, off_rinv, off_m, off_ut, off_vt, off_vg, off_pval, off_pidx, off_sgn, off_skip, off_res;
+  size_t off_t2p;  // pass_eff: the last orbit product before its QR (n x LP FP64)
   size_t total;
 };
 
@@ -187,6 +189,8 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
   p->refine = (a_type == SORSVD_BF16 && o && o->refine) ? 1 : 0;
   p->residual = (o && o->residual) ? 1 : 0;
+  p->pass_eff = (o && o->pass_efficient) ? 1 : 0;
+  if (p->pass_eff && a_type == SORSVD_BF16) return SORSVD_EUNSUPPORTED;
   p->ldt = round_up(std::max(m, n), 128) + 128;  // room for the last step's over-read
   const int forced = o ? o->split : 0;
   const int ks = skinny_step(a_type == SORSVD_DIAG ? SORSVD_F64 : a_type);
@@ -252,6 +256,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->off_sgn = L.take((size_t)KP * 8);
   p->off_skip = L.take(64);
   p->off_res = p->residual ? L.take((size_t)2 * residual_parts(m, n) * 8) : 0;
+  p->off_t2p = p->pass_eff ? L.take((size_t)n * LP * 8) : 0;
   p->total = L.total;
   return SORSVD_OK;
 }
@@ -393,6 +398,7 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   double* T1 = at<double>(ws, p.off_t1);
   double* T2 = at<double>(ws, p.off_t2);
   double* W = at<double>(ws, p.off_w);
+  double* T2P = p.pass_eff ? at<double>(ws, p.off_t2p) : nullptr;
   double* normp = at<double>(ws, p.off_normp);
   int rc;
   SORSVD_TRY(launch_info_init(info, st));
@@ -423,6 +429,7 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true);
   if (rc) return rc;
   if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
+  if (p.pass_eff && p.q == 0) SORSVD_TRY(launch_pack_f64(T2, p.n, LP, LP, T2P, LP, st));
   if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st, p.q == 0))) return rc;
   // Power method (Alg. 4 loop), orthonormalising after each product.
   for (int it = 0; it < p.q; ++it) {
@@ -434,17 +441,26 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
     Y = as_operand(p, T1, p.m, ws, st, &rc, true);
     if (rc) return rc;
     if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
+    if (p.pass_eff && last) SORSVD_TRY(launch_pack_f64(T2, p.n, LP, LP, T2P, LP, st));
     if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st, last))) return rc;
   }
-  // M = Q1^T (A Q2) (eq. M): W = A Q2 in the pass kernel, then the FP64 Q1^T W.
-  const void* X = as_operand(p, T2, p.n, ws, st, &rc, false, p.refine != 0);
-  if (rc) return rc;
-  if ((rc = pass(p, false, A, lda, X, W, nullptr, ws, st, p.refine != 0, true))) return rc;
   double* P = at<double>(ws, p.off_p);
   double* M = at<double>(ws, p.off_m);
-  SORSVD_TRY(launch_skinny_f64(true, T1, LP, LP, p.m, W, LP, LP, p.proj.kchunk, p.proj.nsplit, P,
-                                   nullptr, nullptr, st));
-  SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.proj.nsplit, M, LP, LP, st));
+  if (p.pass_eff) {
+    // pass-efficient core matrix (eq. M_approx): Q1^T A = T2^T for the kept
+    // T2 = A^T Q1, so Q1^T A Q2 = T2^T Q2 (an FP64 l x l product over n rows)
+    SORSVD_TRY(launch_skinny_f64(true, T2P, LP, LP, p.n, T2, LP, LP, p.gram_n.kchunk, p.gram_n.nsplit, P,
+                                 nullptr, nullptr, st));
+    SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.gram_n.nsplit, M, LP, LP, st));
+  } else {
+    // M = Q1^T (A Q2) (eq. M): W = A Q2 in the pass kernel, then the FP64 Q1^T W.
+    const void* X = as_operand(p, T2, p.n, ws, st, &rc, false, p.refine != 0);
+    if (rc) return rc;
+    if ((rc = pass(p, false, A, lda, X, W, nullptr, ws, st, p.refine != 0, true))) return rc;
+    SORSVD_TRY(launch_skinny_f64(true, T1, LP, LP, p.m, W, LP, LP, p.proj.kchunk, p.proj.nsplit, P,
+                                 nullptr, nullptr, st));
+    SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.proj.nsplit, M, LP, LP, st));
+  }
 
   // Core SVD M = U~ S~ V~^T, truncated to k (Alg. 3 step 6).
   double* Ut = at<double>(ws, p.off_ut);

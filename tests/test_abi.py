@@ -39,6 +39,10 @@ def test_workspace_query_validates_shapes():
     assert P.workspace_bytes(10, 8, 3, 0, 9) == 0                   # unknown dtype
     # workspace grows with the sketch width
     assert P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F32) > P.workspace_bytes(5000, 4000, 16, 1, P.SORSVD_F32)
+    # the pass-efficient core matrix keeps the last orbit product (n x LP FP64); not for BF16 A
+    assert (P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F32, pass_efficient=1)
+            == P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F32) + 4000 * 64 * 8)
+    assert P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, pass_efficient=1) == 0
 
 
 def _call(clib, A=1, lda=800, t=0, m=1000, n=800, k=20, q=0, U=1, ldu=20, S=1, V=1, ldv=20, ws=256, wsb=1 << 40,

@@ -151,11 +151,13 @@ def test_core_svd_against_lapack(lib, l, k):
 
 # ------------------------------------------------------------------ whole method
 
-def check_against_oracle(lib, A_np, A_dev, k, q, seed, l=None, tol_s=1e-10, tol_vec=1e-8):
+def check_against_oracle(lib, A_np, A_dev, k, q, seed, l=None, tol_s=1e-10, tol_vec=1e-8, pass_efficient=0):
     opts = {} if l is None else {"l": l}
+    if pass_efficient:
+        opts["pass_efficient"] = 1
     U, S, V, info = lib.sorsvd(A_dev, k, q=q, seed=seed, **opts)
     U, S, V = host(U), host(S), host(V)
-    Uo, So, Vo, io = osvd.sorsvd(A_np, k, q=q, seed=seed, l=l)
+    Uo, So, Vo, io = osvd.sorsvd(A_np, k, q=q, seed=seed, l=l, m_form="approx" if pass_efficient else "exact")
     assert normwise(S, So) <= tol_s, normwise(S, So)
     assert np.all(np.diff(S) <= 0)
     kk = k
@@ -276,3 +278,34 @@ def test_residual_of_exact_low_rank_is_tiny(lib):
     A = gen.standard_normal((700, 12)) @ gen.standard_normal((12, 530))
     _, _, _, info = lib.sorsvd(dev(A), 12, q=0, seed=2, residual=1)
     assert info["err_fro_explicit"] < 1e-13
+
+
+# ------------------------------------------------------------------ pass-efficient core matrix
+
+@pytest.mark.parametrize("m,n,k,q,l", [(300, 200, 10, 0, None), (517, 389, 17, 1, 29), (200, 300, 12, 2, None),
+                                       (2000, 1200, 128, 1, None)])
+def test_pass_efficient_fp64_against_oracle(lib, m, n, k, q, l):
+    sigma = 1.0 / np.arange(1, min(m, n) + 1) ** 1.5
+    A, _, _ = W.spectral(m, n, sigma, m + 2 * n + k)
+    S, So, info, io = check_against_oracle(lib, A, dev(A), k, q, 4, l=l, tol_s=1e-10, tol_vec=1e-7,
+                                           pass_efficient=1)
+    # the Th. 2 identity stays exact: the core matrix is Q1^T A Q2
+    assert abs(info["err_fro"] - io["err_fro"]) <= 1e-9 * max(io["err_fro"], 1e-6)
+
+
+def test_pass_efficient_fp32_against_oracle_on_stored_values(lib):
+    sigma = 1.0 / np.arange(1, 1501) ** 2
+    A, _, _ = W.spectral(2000, 1500, sigma, 2)
+    A32 = A.astype(np.float32)
+    S, So, info, io = check_against_oracle(lib, A32.astype(np.float64), dev(A32, torch.float32), 100, 1, 9,
+                                           tol_s=1e-4, tol_vec=1e9, pass_efficient=1)
+    assert normwise(S, So) <= 1e-5
+
+
+def test_pass_efficient_equals_exact_core_to_rounding(lib):
+    # same Q1, Q2 in both forms; the core matrices agree to FP64 rounding
+    A, _, _ = W.spectral(800, 600, 0.97 ** np.arange(600), 5)
+    _, S1, _, i1 = lib.sorsvd(dev(A), 40, q=1, seed=3)
+    _, S2, _, i2 = lib.sorsvd(dev(A), 40, q=1, seed=3, pass_efficient=1)
+    assert normwise(host(S1), host(S2)) <= 1e-12
+    assert abs(i1["err_fro"] - i2["err_fro"]) <= 1e-10

@@ -198,3 +198,64 @@ def test_c1_signal_recovered():
     floor = bounds.ey_floor(ref, 20) / np.linalg.norm(A)
     assert info["err_fro"] >= floor
     assert math.isfinite(info["err_fro"])
+
+
+# ---------------------------------------------------------------- pass-efficient M (eq. M_approx)
+
+def test_m_approx_is_exact_for_exact_rank():
+    # rank(A) <= l: the row space of A is span(Q2), so A = A Q2 Q2^T and
+    # M_approx = M; the approximation is then the SVD of A itself
+    for (m, n, r, l, q) in [(120, 80, 5, 8, 0), (80, 120, 12, 12, 1), (300, 40, 3, 20, 2)]:
+        gen = W.rng(m + n + 1)
+        A = gen.standard_normal((m, r)) @ gen.standard_normal((r, n))
+        U, s, V, info = sorsvd(A, l, q=q, seed=9, m_form="approx")
+        assert info["err_fro"] < 1e-11
+        ref = np.linalg.svd(A, compute_uv=False)
+        assert np.max(np.abs(s[:r] - ref[:r])) <= 1e-11 * ref[0]
+
+
+def test_m_approx_deviation_bounded_by_the_left_out_part():
+    # M_approx - M = Q1^T A (I - Q2 Q2^T) X (Q2^T X)^+ when Q2^T X is invertible,
+    # so ||M_approx - M||_2 <= ||A (I - Q2 Q2^T)||_2 ||X||_2 / sigma_min(Q2^T X)
+    A, sigma, _, _ = matrix2(200, seed=3)
+    for k, l, q in [(10, 10, 0), (10, 15, 1), (20, 20, 2)]:
+        _, _, _, ie = sorsvd(A, k, q=q, seed=5, l=l, return_all=True)
+        _, _, _, ia = sorsvd(A, k, q=q, seed=5, l=l, return_all=True, m_form="approx")
+        Q2, X = ie["Q2"], ie["X"]
+        assert np.array_equal(Q2, ia["Q2"]) and np.array_equal(ie["Q1"], ia["Q1"])
+        left = np.linalg.norm(A - (A @ Q2) @ Q2.T, 2)
+        smin = np.linalg.svd(Q2.T @ X, compute_uv=False)[-1]
+        bound = left * np.linalg.norm(X, 2) / smin
+        dev = np.linalg.norm(ia["M"] - ie["M"], 2)
+        assert dev <= bound * (1 + 1e-8) + 1e-14, (k, l, q, dev, bound)
+
+
+def test_m_approx_canonical_equals_literal_when_well_conditioned():
+    # the operand X of the literal form is the canonical one times an
+    # invertible l x l factor, which cancels in T1 (Q2^T X)^+ (Lemma 1 argument)
+    sigma = np.concatenate([np.linspace(1.0, 0.5, 40), 1e-2 * np.ones(60)])
+    A, _, _ = W.spectral(150, 100, sigma, 43)
+    for q in (0, 1, 2):
+        _, s1, _, _ = sorsvd(A, 8, q=q, seed=7, l=12, mode="canonical", m_form="approx")
+        _, s2, _, _ = sorsvd(A, 8, q=q, seed=7, l=12, mode="literal", m_form="approx")
+        assert np.max(np.abs(s1 - s2)) < 1e-10
+
+
+def test_m_approx_equals_m_because_q2_spans_a_t_q1():
+    # Q2 is an orthonormal basis of A^T Q1, so Q1^T A (I - Q2 Q2^T) = 0 and the
+    # pass-efficient core matrix equals M = Q1^T A Q2 up to rounding
+    A, sigma, _, _ = matrix2(250, seed=11)
+    nA = np.linalg.norm(A, 2)
+    for q in (0, 1, 2):
+        _, se, _, ie = sorsvd(A, 10, q=q, seed=2, l=14, return_all=True)
+        _, sa, _, ia = sorsvd(A, 10, q=q, seed=2, l=14, return_all=True, m_form="approx")
+        Q1, Q2 = ie["Q1"], ie["Q2"]
+        left = Q1.T @ A
+        assert np.linalg.norm(left - (left @ Q2) @ Q2.T, 2) <= 1e-14 * nA
+        cond = np.linalg.cond(Q2.T @ ia["X"])
+        assert np.linalg.norm(ia["M"] - ie["M"], 2) <= 1e-14 * nA * cond
+        assert np.max(np.abs(sa - se)) <= 1e-14 * nA * cond
+        # the literal loop's products lose precision with q (cond(Q2^T X) grows
+        # like the spectrum's ratio to the power q), but the values still agree
+        _, sl, _, _ = sorsvd(A, 10, q=q, seed=2, l=14, mode="literal", m_form="approx")
+        assert np.max(np.abs(sl - se)) <= 1e-10 * nA
