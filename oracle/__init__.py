@@ -15,6 +15,7 @@ Contents
            Th. 6 / Th. 7 expectation bounds.
   mlp      FP64 reference of the (k, q) predictor network (forward, backward,
            Adam) used to check the GPU training kernels.
+  rpca     Robust PCA by the ALM-SOR-SVD iteration (Table III).
 
 Every function is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``
 against something other than itself (numpy's independent Philox, closed forms,
