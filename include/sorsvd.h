@@ -334,6 +334,47 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
                 const float* params, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
                 void* workspace, size_t ws_bytes, void* stream, sorsvd_auto_info* out);
 
+/* ------------------------------------------------------------------------
+ * Robust PCA by the ALM-SOR-SVD iteration (Sec. V, "Robust Principal
+ * Component Analysis", Table III): split X = L + S (L low-rank, S sparse) by
+ * the inexact augmented-Lagrange-multiplier method with a SOR-SVD of width l
+ * and q power steps in place of the SVD of every iteration:
+ *   (U, z, V) = SOR-SVD(X - S + Y / mu),  L = U shrink_{1/mu}(z) V^T,
+ *   S = shrink_{lambda/mu}(X - L + Y / mu),  Y += mu (X - L - S),
+ *   mu = min(1.5 mu, mu_bar),
+ * with shrink_e(x) = sgn(x) max(|x| - e, 0), lambda = 1 / sqrt(max(m, n)),
+ * Y_0 = X / max(||X||_2, ||X||_max / lambda), mu_0 = 1.25 / ||X||_2,
+ * mu_bar = 1e7 mu_0, S_0 = 0 (the inexact ALM's initial values, which the
+ * paper adopts; the table's max in the mu update is read as the capped min).
+ * ||X||_2 is estimated by a SOR-SVD of X of width min(32, m, n) with eight
+ * power steps. Iteration i draws Omega with seed + i. It stops when
+ * ||X - L - S||_F < tol ||X||_F or after max_iter iterations.
+ *   X: m x n FP64 row-major device array (ldx >= n), read only.
+ *   L, S: m x n FP64 row-major device outputs (ld >= n); S also holds the
+ *     iterate during the run.
+ *   l: 1 <= l <= min(m, n, 128) (the paper's experiments use l = 2 rank(L));
+ *   q >= 0; tol > 0; max_iter >= 1.
+ *   workspace: sorsvd_rpca_workspace_bytes(m, n, l, q) bytes, 256-byte
+ *   aligned; the library synchronises `stream` once per iteration to read the
+ *   residual.
+ * Returns SORSVD_OK (tolerance met), SORSVD_ETOL (max_iter reached; L and S
+ * hold the last iterate), or an error status; *out is filled in both of the
+ * first two cases.
+ * ------------------------------------------------------------------------ */
+typedef struct sorsvd_rpca_info {
+  int32_t iters;   /* iterations taken */
+  int32_t rank;    /* singular values kept by the last thresholding */
+  int64_t nnz_s;   /* nonzero entries of S */
+  double xi;       /* ||X - L - S||_F / ||X||_F after the last iteration */
+  double lambda;   /* 1 / sqrt(max(m, n)) */
+  double norm2;    /* the estimate of ||X||_2 used for mu_0 and Y_0 */
+} sorsvd_rpca_info;
+
+size_t sorsvd_rpca_workspace_bytes(int64_t m, int64_t n, int64_t l, int32_t q);
+int sorsvd_rpca(const double* X, int64_t ldx, int64_t m, int64_t n, int64_t l, int32_t q, uint64_t seed,
+                double tol, int32_t max_iter, double* L, double* S, int64_t ld, void* workspace, size_t ws_bytes,
+                void* stream, sorsvd_rpca_info* out);
+
 /* Human-readable text of a status code (static storage). */
 const char* sorsvd_status_string(int status);
 

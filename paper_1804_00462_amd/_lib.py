@@ -43,6 +43,11 @@ class AutoInfo(ctypes.Structure):
                 ("err", c_dbl), ("k_pred", c_dbl * 4), ("flags", c_i32), ("reserved", c_i32)]
 
 
+class RpcaInfo(ctypes.Structure):
+    _fields_ = [("iters", c_i32), ("rank", c_i32), ("nnz_s", c_i64), ("xi", c_dbl), ("lam", c_dbl),
+                ("norm2", c_dbl)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("a_fro", c_dbl), ("err_fro", c_dbl), ("err_fro_explicit", c_dbl),
                 ("sweeps", c_i32), ("flags", c_i32), ("a_noise_rel", c_dbl)]
@@ -84,6 +89,9 @@ _SIGS = {
                                 ctypes.c_float, c_vp]),
     "sorsvd_mlp_train_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, ctypes.c_float, c_vp, c_vp,
                                       c_vp, c_vp]),
+    "sorsvd_rpca_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i32]),
+    "sorsvd_rpca": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i64, c_i32, c_u64, c_dbl, c_i32, c_vp, c_vp, c_i64,
+                            c_vp, c_sz, c_vp, c_vp]),
     "sorsvd_auto_workspace_bytes": (c_sz, [c_i64, c_i64, c_i32]),
     "sorsvd_auto": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_u64, c_dbl, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64,
                             c_vp, c_sz, c_vp, c_vp]),

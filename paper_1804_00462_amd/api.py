@@ -424,3 +424,29 @@ def auto(A, tol, params=None, seed=0):
     info = {"k_used": k, "q_used": out.q_used, "used_fallback": out.used_fallback, "runs": out.runs,
             "err": out.err, "k_pred": list(out.k_pred), "flags": out.flags, "met": st == 0}
     return U[:, :k], S[:k], V[:, :k], info
+
+
+def rpca(X, l, q=1, seed=0, tol=1e-7, max_iter=100):
+    """Robust PCA X = L + S by the ALM-SOR-SVD iteration (FP64 X on the device).
+    Returns (L, S, info dict); info["met"] tells whether the tolerance was met."""
+    torch = _torch()
+    lib = _lib.load()
+    _check_matrix(X)
+    if X.dtype != torch.float64:
+        raise TypeError("rpca takes FP64 X")
+    m, n = X.shape
+    nbytes = int(lib.sorsvd_rpca_workspace_bytes(m, n, l, q))
+    if nbytes == 0:
+        raise _lib.SorsvdError(-1, "sorsvd_rpca_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    L = torch.empty(m, n, dtype=torch.float64, device=X.device)
+    S = torch.empty(m, n, dtype=torch.float64, device=X.device)
+    out = _lib.RpcaInfo()
+    st = lib.sorsvd_rpca(_ptr(X), X.stride(0), m, n, l, q, seed, float(tol), int(max_iter), _ptr(L), _ptr(S), n,
+                         _ptr(ws), nbytes, _stream(), ctypes.byref(out))
+    if st not in (0, -6):
+        check(st, "sorsvd_rpca")
+    info = {"iters": out.iters, "rank": out.rank, "nnz_s": out.nnz_s, "xi": out.xi, "lambda": out.lam,
+            "norm2": out.norm2, "met": st == 0}
+    return L, S, info
+

@@ -27,6 +27,7 @@ SOURCES = {
     "batched.hip": [],
     "residual.hip": [],
     "mlp.hip": [],
+    "rpca.hip": [],
 }
 
 COMMON = [

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -41,6 +42,18 @@ hipError_t launch_diag_pass(const double* sigma, int64_t n, int LP, const double
                             int nparts, hipStream_t st);
 int skinny_rows_per_block(int a_type, int64_t OUT);
 int skinny_slots(int a_type, bool trans, int LP);
+// rpca.hip
+int rpca_stat_blocks(int64_t m, int64_t n);
+int64_t rpca_step_blocks(int64_t m, int64_t n);
+hipError_t launch_rpca_stats(const double* X, int64_t ldx, int64_t m, int64_t n, double* psq, double* pmax,
+                             hipStream_t st);
+hipError_t launch_rpca_init(const double* X, int64_t ldx, int64_t m, int64_t n, double inv_j, double inv_mu,
+                            double* S, int64_t lds, double* Y, double* W, hipStream_t st);
+hipError_t launch_rpca_step(const double* X, int64_t ldx, int64_t m, int64_t n, const double* U, const double* V,
+                            const double* z, int l, double inv_mu, double thr_s, double mu, double inv_mu_next,
+                            double* L, double* S, int64_t ld, double* Y, double* W, double* rpart,
+                            hipStream_t st);
+hipError_t launch_rpca_nnz(const double* S, int64_t ld, int64_t m, int64_t n, double* pcount, hipStream_t st);
 int bf16_slots(bool trans, int rt, int LP);
 int skinny_step(int a_type);
 // gemm_bf16.hip
@@ -977,6 +990,134 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     q = kAutoFallbackQ;
   }
   return SORSVD_ETOL;
+}
+
+// ------------------------------------------------------------------ robust PCA (ALM-SOR-SVD)
+
+static constexpr int kRpcaNormWidth = 32;  // sketch width of the ||X||_2 estimate
+static constexpr int kRpcaNormQ = 8;
+
+static int rpca_plans(int64_t m, int64_t n, int64_t l, int32_t q, Plan* p, Plan* pn) {
+  if (m < 1 || n < 1 || l < 1 || l > std::min<int64_t>(kMaxLP, std::min(m, n)) || q < 0) return SORSVD_EINVAL;
+  int rc = make_plan(m, n, l, q, SORSVD_F64, nullptr, p);
+  if (rc) return rc;
+  return make_plan(m, n, std::min<int64_t>(kRpcaNormWidth, std::min(m, n)), kRpcaNormQ, SORSVD_F64, nullptr, pn);
+}
+
+// Layout after the SOR-SVD workspace: Y, W (m x n), U (m x l), V (n x l), z (l),
+// the norm sketch's factors, and the per-block partial sums.
+struct RpcaLayout {
+  size_t y, w, u, v, z, un, vn, zn, part, total;
+};
+static RpcaLayout rpca_layout(const Plan& p, const Plan& pn, int64_t m, int64_t n, int64_t l) {
+  Layout L;
+  L.take(std::max(p.total, pn.total));
+  RpcaLayout r;
+  r.y = L.take((size_t)m * n * 8);
+  r.w = L.take((size_t)m * n * 8);
+  r.u = L.take((size_t)m * l * 8);
+  r.v = L.take((size_t)n * l * 8);
+  r.z = L.take((size_t)l * 8);
+  r.un = L.take((size_t)m * pn.k * 8);
+  r.vn = L.take((size_t)n * pn.k * 8);
+  r.zn = L.take((size_t)pn.k * 8);
+  const int64_t parts = std::max<int64_t>(rpca_step_blocks(m, n), 2 * (int64_t)rpca_stat_blocks(m, n));
+  r.part = L.take((size_t)parts * 8);
+  r.total = L.total;
+  return r;
+}
+
+size_t sorsvd_rpca_workspace_bytes(int64_t m, int64_t n, int64_t l, int32_t q) {
+  Plan p, pn;
+  if (rpca_plans(m, n, l, q, &p, &pn)) return 0;
+  return rpca_layout(p, pn, m, n, l).total;
+}
+
+int sorsvd_rpca(const double* X, int64_t ldx, int64_t m, int64_t n, int64_t l, int32_t q, uint64_t seed,
+                double tol, int32_t max_iter, double* L, double* S, int64_t ld, void* workspace, size_t ws_bytes,
+                void* stream, sorsvd_rpca_info* out) {
+  Plan p, pn;
+  int rc = rpca_plans(m, n, l, q, &p, &pn);
+  if (rc) return rc;
+  if (!X || !L || !S || !workspace || !out || ldx < n || ld < n || !(tol > 0.0) || max_iter < 1)
+    return SORSVD_EINVAL;
+  const RpcaLayout R = rpca_layout(p, pn, m, n, l);
+  if (ws_bytes < R.total) return SORSVD_EWORKSPACE;
+  if (((uintptr_t)workspace) % kAlign) return SORSVD_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  std::memset(out, 0, sizeof(*out));
+  double* Y = at<double>(workspace, R.y);
+  double* W = at<double>(workspace, R.w);
+  double* U = at<double>(workspace, R.u);
+  double* V = at<double>(workspace, R.v);
+  double* z = at<double>(workspace, R.z);
+  double* part = at<double>(workspace, R.part);
+  const int kn = (int)pn.k;
+
+  // ||X||_F, ||X||_max (fixed-order sums on the host of per-block partials)
+  const int sb = rpca_stat_blocks(m, n);
+  SORSVD_TRY(launch_rpca_stats(X, ldx, m, n, part, part + sb, st));
+  std::vector<double> hp(2 * (size_t)sb);
+  SORSVD_TRY(hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, st));
+  SORSVD_TRY(hipStreamSynchronize(st));
+  double fro2 = 0.0, xmax = 0.0;
+  for (int i = 0; i < sb; ++i) {
+    fro2 += hp[i];
+    xmax = std::max(xmax, hp[sb + i]);
+  }
+  const double xfro = std::sqrt(fro2);
+  // ||X||_2: the leading value of a narrow SOR-SVD of X with power steps
+  if ((rc = run(pn, X, ldx, seed ^ 0x9E3779B97F4A7C15ull, at<double>(workspace, R.un), kn,
+                at<double>(workspace, R.zn), at<double>(workspace, R.vn), kn, workspace, st)))
+    return rc;
+  double norm2 = 0.0;
+  SORSVD_TRY(hipMemcpyAsync(&norm2, at<double>(workspace, R.zn), 8, hipMemcpyDeviceToHost, st));
+  SORSVD_TRY(hipStreamSynchronize(st));
+  out->norm2 = norm2;
+  if (!(xfro > 0.0) || !(norm2 > 0.0) || !std::isfinite(fro2)) return SORSVD_EINVAL;
+  const double lambda = 1.0 / std::sqrt((double)std::max(m, n));
+  out->lambda = lambda;
+  double mu = 1.25 / norm2;
+  const double mu_bar = 1e7 * mu, rho = 1.5;
+  const double J = std::max(norm2, xmax / lambda);
+  SORSVD_TRY(launch_rpca_init(X, ldx, m, n, 1.0 / J, 1.0 / mu, S, ld, Y, W, st));
+
+  const int64_t nb = rpca_step_blocks(m, n);
+  std::vector<double> rp((size_t)nb);
+  double mu_used = mu;
+  int it = 0;
+  double xi = 0.0;
+  while (it < max_iter) {
+    if ((rc = run(p, W, n, seed + (uint64_t)it, U, l, z, V, l, workspace, st))) return rc;
+    const double mu_next = std::min(rho * mu, mu_bar);
+    SORSVD_TRY(launch_rpca_step(X, ldx, m, n, U, V, z, (int)l, 1.0 / mu, lambda / mu, mu, 1.0 / mu_next, L, S, ld,
+                                Y, W, part, st));
+    SORSVD_TRY(hipMemcpyAsync(rp.data(), part, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+    SORSVD_TRY(hipStreamSynchronize(st));
+    double r2 = 0.0;
+    for (int64_t i = 0; i < nb; ++i) r2 += rp[i];
+    mu_used = mu;
+    mu = mu_next;
+    ++it;
+    xi = std::sqrt(r2) / xfro;
+    if (!std::isfinite(xi) || xi < tol) break;
+  }
+  out->iters = it;
+  out->xi = xi;
+  // singular values kept by the last thresholding; nonzeros of S
+  std::vector<double> hz((size_t)l);
+  SORSVD_TRY(hipMemcpyAsync(hz.data(), z, (size_t)l * 8, hipMemcpyDeviceToHost, st));
+  SORSVD_TRY(launch_rpca_nnz(S, ld, m, n, part, st));
+  std::vector<double> hc((size_t)sb);
+  SORSVD_TRY(hipMemcpyAsync(hc.data(), part, (size_t)sb * 8, hipMemcpyDeviceToHost, st));
+  SORSVD_TRY(hipStreamSynchronize(st));
+  int kept = 0;
+  for (int64_t t = 0; t < l; ++t) kept += hz[t] - 1.0 / mu_used > 0.0 ? 1 : 0;
+  out->rank = kept;
+  double nnz = 0.0;
+  for (int i = 0; i < sb; ++i) nnz += hc[i];
+  out->nnz_s = (int64_t)nnz;
+  return xi < tol ? SORSVD_OK : SORSVD_ETOL;
 }
 
 const char* sorsvd_status_string(int status) {
