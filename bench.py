@@ -228,6 +228,45 @@ def run_batched(steps, warmup, torch, P):
             "err_fro_median": float(sorted(i["err_fro"] for i in infos)[len(infos) // 2])}
 
 
+RPCA_DESC = ("robust PCA by the ALM-SOR-SVD iteration (Table III): X = L + S, n x n, rank(L) = 0.05 n "
+             "(N(0,1) factors), 5% of entries +-50, l = 2 rank, q = 1, tol 1e-7 (the paper's Table IV setup)")
+
+
+def run_rpca(torch, P, sizes=(1000, 1280), reps=3):
+    """Time to solve one RPCA problem (all iterations, host loop included)."""
+    import numpy as np
+    out = {"workload": RPCA_DESC, "cases": {}}
+    for n in sizes:
+        r = int(0.05 * n)
+        g = np.random.default_rng(n)
+        L0 = g.standard_normal((n, r)) @ g.standard_normal((r, n))
+        S0 = np.zeros((n, n))
+        idx = g.choice(n * n, int(0.05 * n * n), replace=False)
+        S0.flat[idx] = g.choice([-50.0, 50.0], size=idx.size)
+        X = torch.as_tensor(L0 + S0).cuda()
+        P.rpca(X, 2 * r, q=1, seed=3)
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L, S, info = P.rpca(X, 2 * r, q=1, seed=3)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = sorted(times)[len(times) // 2]
+        Lh, Sh = L.cpu().numpy(), S.cpu().numpy()
+        case = {"n": n, "rank_true": r, "l": 2 * r, "ms": round(ms, 2), "ms_per_iter": round(ms / info["iters"], 3),
+                "iters": info["iters"], "rank": info["rank"], "nnz_s": info["nnz_s"],
+                "nnz_true": int(np.count_nonzero(S0)), "xi": info["xi"], "met": info["met"],
+                "support_exact": bool(np.array_equal(Sh != 0, S0 != 0)),
+                "l_rel_err": float(np.linalg.norm(Lh - L0) / np.linalg.norm(L0))}
+        log(f"[rpca n={n}] {ms:.1f} ms, {info['iters']} iterations, rank {info['rank']}/{r}, "
+            f"nnz {info['nnz_s']}/{case['nnz_true']}, xi {info['xi']:.2e}")
+        out["cases"][str(n)] = case
+        del X, L, S
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_c5(torch, P):
     """Time to tolerance 1e-3 (relative Frobenius, against the FP64 matrix) on
     32768 x 32768 A = U diag(sigma) V^T (Haar U, V on the leading 2048 singular
@@ -267,7 +306,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
-    ap.add_argument("--extra", default="c3,c1,c4,c5,c2pe", help="comma-separated extra workloads ('' for none)")
+    ap.add_argument("--extra", default="c3,c1,c4,c5,c2pe,rpca", help="comma-separated extra workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick-input", action="store_true",
                     help="N(0, 1) entries of the workload's shape instead of its spectrum (counter runs only)")
@@ -319,6 +358,8 @@ def main():
             extra[name] = run_batched(args.steps, args.warmup, torch, P)
         elif name == "c5":
             extra[name] = run_c5(torch, P)
+        elif name == "rpca":
+            extra[name] = run_rpca(torch, P)
         else:
             res, A = run_workload(name, args.steps, args.warmup, torch, P)
             del A
