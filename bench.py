@@ -34,6 +34,10 @@ WORKLOADS = {
     "c3": (200000, 4000, 64, 1, "bfloat16", 1,
            "BF16-stored A = U diag(0.9^j) V^T + N(0, (1e-6)^2), 200000 x 4000, k = 64, q = 1, "
            "BF16 MFMA passes, hi+lo refinement projection, FP64 QR and core SVD"),
+    "c3h": (200000, 4000, 64, 1, "float16", 1,
+            "C3's matrix in FP16 with power-of-two column scaling (packed on the GPU from FP64: "
+            "e_j = 14 - floor(log2 max_i |a_ij|)), FP16 MFMA passes, hi+lo refinement projection, "
+            "FP64 QR and core SVD"),
     "c1": (1000, 800, 20, 0, "float64", 0,
            "plain SOR-SVD FP64: A = X Y^T + 1e-3 E (1000 x 800, seed 0), k = 20, q = 0, Omega seed 1"),
     "c2pe": (20000, 20000, 100, 1, "float32", 0,
@@ -48,8 +52,9 @@ C4_DESC = ("batched SOR-SVD FP32: 512 RPCA-style problems L + S (L = X Y^T, N(0,
 
 # dominant-kernel roofline: (bound, peak, unit)
 PEAK = {"float32": ("mfma", 157.3, "TFLOP/s"), "float64": ("mfma", 78.6, "TFLOP/s"),
-        "bfloat16": ("hbm", 8000.0, "GB/s")}
-DTYPE_TAG = {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}
+        "bfloat16": ("hbm", 8000.0, "GB/s"), "float16": ("hbm", 8000.0, "GB/s")}
+DTYPE_TAG = {"float32": "f32", "float64": "f64", "bfloat16": "bf16", "float16": "f16"}
+REDUCED = {"c3", "c3h"}  # 16-bit storage: also the error against the FP64 matrix
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -79,20 +84,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_input(name, torch, quick=False):
+def make_input(name, torch, P, quick=False):
+    """(A as stored, plan options, FP64 matrix it stands for or None)."""
     import workloads as W
+    m, n, _, _, dname, _, _ = WORKLOADS[name]
     if quick:  # same shape and dtype, N(0, 1) entries: for counter runs where the spectrum does not matter
-        m, n, _, _, dname, _, _ = WORKLOADS[name]
         g = torch.Generator(device="cuda")
         g.manual_seed(7)
-        return torch.randn(m, n, generator=g, device="cuda", dtype=torch.float32).to(getattr(torch, dname))
+        A = torch.randn(m, n, generator=g, device="cuda", dtype=torch.float32)
+        if dname == "float16":
+            Ah, e = P.pack_f16(A)
+            return Ah, {"col_exp": e}, None
+        return A.to(getattr(torch, dname)), {}, None
     if name in ("c2", "c2pe"):
-        return W.c2_torch("cuda")
-    if name == "c3":
-        return W.c3_torch("cuda")
+        return W.c2_torch("cuda"), {}, None
+    if name in ("c3", "c3h"):
+        A64 = W.c3_torch("cuda", out_dtype=torch.float64)
+        if name == "c3":
+            return A64.to(torch.bfloat16), {}, A64
+        Ah, e = P.pack_f16(A64)
+        return Ah, {"col_exp": e}, A64
     if name == "c1":
-        return torch.as_tensor(W.c1()).cuda()
+        return torch.as_tensor(W.c1()).cuda(), {}, None
     raise ValueError(name)
+
+
+def error_vs_fp64(A64, U, S, V, torch):
+    """||A64 - U S V^T||_F / ||A64||_F in FP64 on the device (row blocks)."""
+    num = 0.0
+    W = (V * S[None, :]).T.contiguous()
+    for r0 in range(0, A64.shape[0], 20000):
+        R = A64[r0:r0 + 20000] - U[r0:r0 + 20000] @ W
+        num += float((R * R).sum())
+    return (num ** 0.5) / float(torch.linalg.norm(A64))
 
 
 def cpu_baseline(A_host, k, q, seed, budget_s=20.0, max_reps=5):
@@ -124,11 +148,11 @@ def run_workload(name, steps, warmup, torch, P, quick=False):
     seed = 1
     log(f"[bench] building input {name}: {desc}")
     t0 = time.perf_counter()
-    A = make_input(name, torch, quick)
+    A, extra_opts, A64 = make_input(name, torch, P, quick)
     torch.cuda.synchronize()
     log(f"[bench] input ready in {time.perf_counter() - t0:.1f} s; dtype {A.dtype}")
     pe = 1 if name in PASS_EFFICIENT else 0
-    plan = P.Plan(m, n, k, q, A.dtype, refine=refine, pass_efficient=pe)
+    plan = P.Plan(m, n, k, q, A.dtype, refine=refine, pass_efficient=pe, **extra_opts)
     es = A.element_size()
 
     for _ in range(warmup):
@@ -174,6 +198,10 @@ def run_workload(name, steps, warmup, torch, P, quick=False):
            "hbm_gbps_algorithmic": round(float(m) * n * es * passes / (ms_per_step / 1e3) / 1e9, 1),
            "roofline": roofline, "err_fro": info["err_fro"], "jacobi_sweeps": info["sweeps"],
            "flags": info["flags"]}
+    if A64 is not None:
+        res["err_vs_fp64"] = error_vs_fp64(A64, plan.U, plan.S, plan.V, torch)
+        log(f"[bench] {name}: relative error against the FP64 matrix {res['err_vs_fp64']:.4e}")
+        del A64
     return res, A
 
 
@@ -306,7 +334,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
-    ap.add_argument("--extra", default="c3,c1,c4,c5,c2pe,rpca", help="comma-separated extra workloads ('' for none)")
+    ap.add_argument("--extra", default="c3,c3h,c1,c4,c5,c2pe,rpca",
+                    help="comma-separated extra workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick-input", action="store_true",
                     help="N(0, 1) entries of the workload's shape instead of its spectrum (counter runs only)")

@@ -49,8 +49,23 @@ typedef enum sorsvd_status {
  *   BF16 -> BF16 MFMA, FP32 accumulation; the skinny operands are rounded to
  *           BF16 (with opts.refine the projection pass splits Q2 into a BF16
  *           high and low part).
+ *   F16  -> IEEE binary16 A (raw 16-bit words), FP16 MFMA, FP32 accumulation;
+ *           as BF16, with 11 instead of 8 significant bits in A and in the
+ *           skinny operands. FP16's range (normal 2^-14 .. 65504) is covered
+ *           by power-of-two column scaling: opts.col_exp gives e_j with
+ *           A = A_stored diag(2^-e_j) (sorsvd_pack_f16 chooses them), and the
+ *           library undoes the scaling exactly on the skinny operands and the
+ *           FP64 outputs. Skinny operands are stored multiplied by 2^12 (and
+ *           by 2^(min e - e_j) on row j of an A X operand) to stay clear of
+ *           FP16 subnormals; the output is scaled back exactly.
  * QR, the core SVD and the lift always run in FP64. */
-typedef enum sorsvd_dtype { SORSVD_F64 = 0, SORSVD_F32 = 1, SORSVD_BF16 = 2, SORSVD_DIAG = 3 } sorsvd_dtype;
+typedef enum sorsvd_dtype {
+  SORSVD_F64 = 0,
+  SORSVD_F32 = 1,
+  SORSVD_BF16 = 2,
+  SORSVD_DIAG = 3,
+  SORSVD_F16 = 4
+} sorsvd_dtype;
 /* SORSVD_DIAG: A = diag(sigma), m = n, given by its diagonal: A points to n FP64
  * values on the device (lda is not used). Every pass is diag(sigma) X in FP64;
  * everything else is the FP64 path. The Gaussian Omega is rotation-invariant,
@@ -62,19 +77,25 @@ typedef enum sorsvd_dtype { SORSVD_F64 = 0, SORSVD_F32 = 1, SORSVD_BF16 = 2, SOR
 typedef struct sorsvd_opts {
   int64_t l;          /* sketch width l, k <= l <= min(m, n); 0 means l = k */
   int32_t max_sweeps; /* Jacobi sweep cap of the core SVD; 0 means 40 */
-  int32_t refine;     /* BF16 A only: 1 = projection pass with Q2 split hi+lo */
+  int32_t refine;     /* BF16 / FP16 A only: 1 = projection pass with Q2 split hi+lo */
   int32_t residual;   /* 1 = also compute ||A - U S V^T||_F explicitly (one more pass over A,
-                         FP32 MFMA for FP32 / BF16 A, FP64 for FP64 A, FP64 accumulation) */
+                         FP32 MFMA for FP32 / BF16 / FP16 A, FP64 for FP64 A, FP64 accumulation) */
   int32_t split;      /* split of the contraction in the passes; 0 = automatic */
-  int32_t tile;       /* BF16 passes: 64*tile rows (columns) of A per workgroup, tile in {1,2,4}; 0 = automatic */
+  int32_t tile;       /* BF16 / FP16 passes: 64*tile rows (columns) of A per workgroup, tile in {1,2,4};
+                         0 = automatic */
   int32_t pass_efficient; /* 1 = the pass-efficient core matrix (Sec. III, eq. M_approx): 2q + 2
                              passes instead of 2q + 3. With orthonormalisation after every
                              product, Q2 spans A^T Q1, so Q1^T A = R2^T Q2^T and M_approx equals
                              M = Q1^T A Q2 in exact arithmetic; it is formed as T2^T Q2 from the
                              last orbit product T2 = A^T Q1 kept before its QR (FP64, no
                              pseudo-inverse, no pass over A). FP32 / FP64 / diagonal A only
-                             (SORSVD_EUNSUPPORTED for BF16 A, whose core matrix needs the
-                             refinement pass). The error identity stays valid. */
+                             (SORSVD_EUNSUPPORTED for BF16 / FP16 A, whose core matrix needs
+                             the refinement pass). The error identity stays valid. */
+  const int32_t* col_exp; /* FP16 A only (else SORSVD_EUNSUPPORTED): DEVICE array of n column
+                             exponents, A = A_stored diag(2^-e_j); NULL = no scaling. The
+                             result (U, S, V, ||A||_F, errors) is that of A, not of A_stored.
+                             |e_j| <= 256 keeps every FP64 intermediate in range; larger
+                             values set flags bit 3 and the run goes on with them. */
 } sorsvd_opts;
 
 /* Result record, kept by the library in the first 256 bytes of the workspace. */
@@ -86,9 +107,10 @@ typedef struct sorsvd_info {
   int32_t flags;           /* bit 0: sweep cap reached; bit 1: non-finite entry in A;
                               bit 2: a Cholesky-QR pivot stayed <= 0 after the shift, so its
                               column was dropped from Q (sketch columns dependent to
-                              rounding: a sketch condition number near 1/u) */
-  double a_noise_rel;      /* opts.residual with BF16 A: sqrt(sum ulp(a_ij)^2 / 12) / ||A||_F, the
-                              expected relative size of the rounding of A to BF16; the error
+                              rounding: a sketch condition number near 1/u);
+                              bit 3: a column exponent outside +-256 (opts.col_exp) */
+  double a_noise_rel;      /* opts.residual with BF16 / FP16 A: sqrt(sum ulp(a_ij)^2 / 12) / ||A||_F,
+                              the expected relative size of the rounding of A to 16 bits; the error
                               against A before rounding is about
                               sqrt(err_fro_explicit^2 - a_noise_rel^2) plus twice the
                               share of the noise the rank-k fit absorbs (see
@@ -126,6 +148,26 @@ int sorsvd(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
 int sorsvd_read_info(const void* workspace, sorsvd_info* out, void* stream);
 
 /*
+ * sorsvd_pack_f16 - FP16 storage of an FP32 / FP64 matrix with power-of-two
+ * column scaling (the input form of SORSVD_F16 with opts.col_exp). Not part
+ * of the method: it extends the reduced-precision storage of A to FP16's
+ * range.
+ *
+ *   A        m x n, a_type SORSVD_F32 or SORSVD_F64 (else SORSVD_EUNSUPPORTED),
+ *            leading dimension lda >= n. Read only.
+ *   out      m x n FP16 (raw binary16 words), leading dimension ldo >= n:
+ *            out_ij = fp16(A_ij 2^e_j), rounded once to nearest-even.
+ *   col_exp  n int32: e_j = 14 - floor(log2 max_i |A_ij|), clamped to
+ *            [-256, 256]; 0 for a column without a finite nonzero entry. Every
+ *            column's largest entry lands in [2^14, 2^15].
+ * Non-finite entries are ignored when choosing e_j and stored as Inf / NaN.
+ * Two kernels on `stream`; no workspace. SORSVD_EINVAL for bad shapes or
+ * leading dimensions, or null pointers with m, n > 0.
+ */
+int sorsvd_pack_f16(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint16_t* out,
+                    int64_t ldo, int32_t* col_exp, void* stream);
+
+/*
  * sorsvd_philox_normal - the Gaussian draw of Alg. 3 / Alg. 4 step 1.
  * out (device, FP64) is rows x cols COLUMN-major with leading dimension rows:
  * element (i, j) is draw e = i + j*rows of key (seed, stream_id): Philox4x64-10
@@ -138,7 +180,9 @@ int sorsvd_philox_normal(uint64_t seed, uint64_t stream_id, uint64_t word2,
 /*
  * Single steps of the path, for callers that compose their own pipeline and
  * for per-step checks. Skinny operands are FP64 row-major with leading
- * dimension l; they are rounded to A's compute type inside the pass.
+ * dimension l; they are rounded to A's compute type inside the pass (FP16:
+ * after the 2^12 lift, without column exponents; BF16 and FP16 projections
+ * split Q2 into high and low parts).
  *
  * sorsvd_step_sketch: T (m x l) = A X, X n x l           (eq. T1; Alg. 4 T1 update)
  * sorsvd_step_orbit:  T (n x l) = A^T Y, Y m x l         (eq. AT1; Alg. 4 T2 update)
@@ -270,7 +314,8 @@ void sorsvd_batch_destroy(sorsvd_batch* b);
  *   Omega of key (seed, 0) as in sorsvd(); s_j = singular values of Y0 (Cholesky
  *   QR of Y0, then the core SVD of R); features (device, 128 FP32):
  *   f_j = clamp(log10(s_j / s_1) / 8, -1, 0) for j < l, -1 beyond.
- *   Workspace: sorsvd_probe_workspace_bytes(m, n, a_type).
+ *   Workspace: sorsvd_probe_workspace_bytes(m, n, a_type). FP16 A:
+ *   SORSVD_EUNSUPPORTED here and in sorsvd_auto (workspace sizes 0).
  *
  * The network: 128 -> 64 (tanh) -> 64 (tanh) -> 4, FP32, parameters one flat
  * device vector of sorsvd_mlp_param_count() = 12676 values: W1 (64 x 128,

@@ -14,7 +14,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "sorsvd.h")
 c_i32, c_i64, c_u64, c_sz, c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
 c_vp = ctypes.c_void_p
 
-SORSVD_F64, SORSVD_F32, SORSVD_BF16, SORSVD_DIAG = 0, 1, 2, 3
+SORSVD_F64, SORSVD_F32, SORSVD_BF16, SORSVD_DIAG, SORSVD_F16 = 0, 1, 2, 3, 4
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error",
           -4: "Jacobi sweep cap reached", -5: "non-finite input", -6: "tolerance not met",
@@ -29,7 +29,7 @@ class SorsvdError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("l", c_i64), ("max_sweeps", c_i32), ("refine", c_i32), ("residual", c_i32),
-                ("split", c_i32), ("tile", c_i32), ("pass_efficient", c_i32)]
+                ("split", c_i32), ("tile", c_i32), ("pass_efficient", c_i32), ("col_exp", c_vp)]
 
 
 class Problem(ctypes.Structure):
@@ -58,6 +58,7 @@ _SIGS = {
     "sorsvd": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_i64, c_i32, c_u64,
                        c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp, c_vp]),
     "sorsvd_read_info": (c_i32, [c_vp, c_vp, c_vp]),
+    "sorsvd_pack_f16": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "sorsvd_philox_normal": (c_i32, [c_u64, c_u64, c_u64, c_i64, c_i64, c_vp, c_vp]),
     "sorsvd_step_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i32]),
     "sorsvd_step_sketch": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),

@@ -6,7 +6,7 @@ computation runs in the library's kernels. Names follow the C entry points.
 import ctypes
 
 from . import _lib
-from ._lib import SORSVD_BF16, SORSVD_DIAG, SORSVD_F32, SORSVD_F64, AutoInfo, Info, Opts, Problem, check
+from ._lib import SORSVD_BF16, SORSVD_DIAG, SORSVD_F16, SORSVD_F32, SORSVD_F64, AutoInfo, Info, Opts, Problem, check
 
 
 def _torch():
@@ -22,6 +22,8 @@ def dtype_code(dtype):
         return SORSVD_F32
     if dtype == torch.bfloat16:
         return SORSVD_BF16
+    if dtype == torch.float16:
+        return SORSVD_F16
     raise TypeError(f"unsupported dtype {dtype}")
 
 
@@ -47,9 +49,17 @@ def _info_dict(o):
             "sweeps": o.sweeps, "flags": o.flags, "a_noise_rel": o.a_noise_rel}
 
 
-def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0, pass_efficient=0):
+def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0, pass_efficient=0, col_exp=None):
+    """col_exp: None, or a device int32 tensor of n column exponents (FP16 A;
+    the caller keeps it alive while the options are in use)."""
+    ce = None
+    if col_exp is not None:
+        torch = _torch()
+        if col_exp.dtype != torch.int32 or not col_exp.is_cuda or not col_exp.is_contiguous():
+            raise ValueError("col_exp must be a contiguous int32 device tensor")
+        ce = col_exp.data_ptr()
     return Opts(l=l, max_sweeps=max_sweeps, refine=refine, residual=residual, split=split, tile=tile,
-                pass_efficient=pass_efficient)
+                pass_efficient=pass_efficient, col_exp=ce)
 
 
 def workspace_bytes(m, n, k, q, dtype_or_code, **opts):
@@ -65,6 +75,9 @@ class Plan:
         torch = _torch()
         self.m, self.n, self.k, self.q = m, n, k, q
         self.code = dtype if isinstance(dtype, int) else dtype_code(dtype)
+        self.col_exp = opts.get("col_exp")  # kept alive with the plan
+        if self.col_exp is not None and self.col_exp.numel() != n:
+            raise ValueError("col_exp needs one exponent per column")
         self.opts = make_opts(**opts)
         lib = _lib.load()
         nbytes = int(lib.sorsvd_workspace_bytes(m, n, k, q, self.code, ctypes.byref(self.opts)))
@@ -104,6 +117,21 @@ def sorsvd(A, k, q=0, seed=0, **opts):
     plan = Plan(A.shape[0], A.shape[1], k, q, A.dtype, device=A.device, **opts)
     U, S, V = plan.run(A, seed)
     return U, S, V, plan.info()
+
+
+def pack_f16(A, stream=None):
+    """FP16 storage of an FP32 / FP64 device matrix with power-of-two column
+    scaling: (A_stored, col_exp) with A = A_stored diag(2^-col_exp), the
+    input of sorsvd(A_stored, ..., col_exp=col_exp)."""
+    torch = _torch()
+    _check_matrix(A)
+    m, n = A.shape
+    out = torch.empty(m, n, dtype=torch.float16, device=A.device)
+    e = torch.empty(n, dtype=torch.int32, device=A.device)
+    st = _lib.load().sorsvd_pack_f16(_ptr(A), A.stride(0), dtype_code(A.dtype), m, n, _ptr(out), n, _ptr(e),
+                                     _stream(stream))
+    check(st, "sorsvd_pack_f16")
+    return out, e
 
 
 def sorsvd_diag(sigma, k, q=0, seed=0, **opts):

@@ -11,6 +11,7 @@ documented one.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -19,12 +20,14 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsorsvd.so")
 
 SOURCES = {
+    "gemm_bf16.hip": [],
+    "gemm_f16.hip": [],
+    "batched.hip": [],
+    "small.hip": [],
     "philox.hip": ["-ffp-contract=off"],
     "gemm.hip": [],
-    "gemm_bf16.hip": [],
-    "small.hip": [],
     "sorsvd.hip": [],
-    "batched.hip": [],
+    "pack.hip": [],
     "residual.hip": [],
     "mlp.hip": [],
     "rpca.hip": [],
@@ -49,19 +52,26 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False):
+def _compile(src, extra, verbose):
+    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+    cmd = [hipcc(), *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"hipcc failed on {src}")
+    return obj
+
+
+def build(verbose=False, jobs=None):
+    """Compiles the sources in parallel (jobs: worker count, default
+    min(8, CPUs)) and links the library."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src, extra in SOURCES.items():
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
-        objs.append(obj)
+    jobs = jobs or max(1, min(8, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:  # SOURCES lists the slowest units first
+        futs = {src: ex.submit(_compile, src, SOURCES[src], verbose) for src in SOURCES}
+        objs = [futs[src].result() for src in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -721,7 +721,9 @@ int sorsvd_batch_create(int32_t count, const sorsvd_problem* probs, int32_t a_ty
   *out = nullptr;
   *ws_bytes = 0;
   if (a_type != SORSVD_F32 && a_type != SORSVD_F64 && a_type != SORSVD_DIAG) return SORSVD_EUNSUPPORTED;
-  if (opts && (opts->refine || opts->residual || opts->split || opts->tile || opts->l)) return SORSVD_EUNSUPPORTED;
+  if (opts && (opts->refine || opts->residual || opts->split || opts->tile || opts->l || opts->pass_efficient ||
+               opts->col_exp))
+    return SORSVD_EUNSUPPORTED;
   sorsvd_batch* b = new sorsvd_batch();
   b->count = count;
   b->a_type = a_type;

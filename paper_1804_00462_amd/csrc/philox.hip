@@ -13,7 +13,7 @@
 //           f = ((2t+1) - qd 2^51) 2^-51;  x = f PIO2;  z = x x;
 //           S = 1 - (z S)/((2j)(2j+1)),  C = 1 - (z C)/((2j-1)(2j))  (j = 10..1);
 //           (sin, cos)(x) = (x S, C), rotated by qd quarter turns.
-#include "common.hpp"
+#include "half16.hpp"
 
 namespace sor {
 
@@ -137,6 +137,28 @@ __global__ void __launch_bounds__(256) k_omega(uint64_t seed, uint64_t stream, u
   }
 }
 
+// FP16 Omega for an NN pass, transposed (element (i, j) at j * ldx + i, as
+// mode 2) and scaled: row i (column i of A) by 2^(nn_base - e_i), the
+// scaling of every FP16 NN operand (H16Scale). Same draws as k_omega.
+__global__ void __launch_bounds__(256) k_omega_f16_t(uint64_t seed, int64_t rows, int64_t cols,
+                                                     uint16_t* __restrict__ out, int64_t ldx,
+                                                     const H16Scale* __restrict__ sc,
+                                                     const int* __restrict__ cexp) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t count = rows * cols;
+  if (4 * b >= count) return;
+  double z[4];
+  normals4((uint64_t)b, 0, seed, 0, z);
+  const int base = sc->nn_base;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t e = 4 * b + t;
+    if (e >= count) break;
+    const int64_t i = e % rows, j = e / rows;
+    out[j * ldx + i] = f64_to_f16(ldexp(z[t], base - (cexp ? cexp[i] : 0)));
+  }
+}
+
 // Batched Omega: blockIdx.y selects the job; one thread per Philox block,
 // element (i, j) of job y is draw i + j * rows of key (seed_y, 0), exactly as
 // in the single-problem kernel (mode 1).
@@ -191,6 +213,14 @@ hipError_t launch_omega_bf16_t(uint64_t seed, int64_t rows, int64_t cols, bf16_t
   int64_t blocks = ceil_div(ceil_div(rows * cols, 4), 256);
   hipLaunchKernelGGL((k_omega<2, bf16_t>), dim3((unsigned)blocks), dim3(256), 0, st,
                      seed, (uint64_t)0, (uint64_t)0, rows, cols, out, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega_f16_t(uint64_t seed, int64_t rows, int64_t cols, uint16_t* out, int64_t ldx,
+                              const H16Scale* sc, const int* cexp, hipStream_t st) {
+  const int64_t blocks = ceil_div(ceil_div(rows * cols, 4), 256);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_omega_f16_t, dim3((unsigned)blocks), dim3(256), 0, st, seed, rows, cols, out, ldx, sc, cexp);
   return hipGetLastError();
 }
 

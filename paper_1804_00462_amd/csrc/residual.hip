@@ -7,13 +7,19 @@
 // A_hat = U W on MFMA (FP32 for FP32 / BF16 A, FP64 for FP64 A), read the
 // matching elements of A, and accumulate (a - a_hat)^2 in FP64.
 //
-// For BF16-stored A the same pass also accumulates sum ulp(a)^2 / 12, the
-// expected squared rounding error of storing A to BF16 (round-to-nearest,
-// error uniform within half an ulp). Against the matrix before rounding, the
+// For BF16- or FP16-stored A the same pass also accumulates sum ulp(a)^2 / 12,
+// the expected squared rounding error of storing A in 16 bits (round-to-
+// nearest, error uniform within half an ulp). FP16 A may come with column
+// exponents e (A = A_stored diag(2^-e_j)): the residual is then formed in the
+// stored scale (column j of W = S V^T multiplied by 2^e_j before the MFMA, so
+// FP32 sees values of the stored range) and its square, like the rounding
+// noise, weighted by 4^-e_j (exact). Against the matrix before rounding, the
 // approximation error is then estimated as sqrt(e_stored^2 - that sum / ||A||^2):
 // the rounding error is spread over all n singular directions, so only a
 // fraction (k / n)^2 of it is captured by the rank-k approximation.
-#include "common.hpp"
+#include <type_traits>
+
+#include "half16.hpp"
 
 namespace sor {
 
@@ -26,6 +32,10 @@ template <typename TA> __device__ inline double load_a(const TA* p);
 template <> __device__ inline double load_a<double>(const double* p) { return *p; }
 template <> __device__ inline double load_a<float>(const float* p) { return (double)*p; }
 template <> __device__ inline double load_a<bf16_t>(const bf16_t* p) { return (double)bf16_to_f32(*p); }
+struct f16_word {  // FP16 storage (distinct from the BF16 word type)
+  uint16_t bits;
+};
+template <> __device__ inline double load_a<f16_word>(const f16_word* p) { return (double)f16_to_f32(p->bits); }
 
 // ulp(a)^2 / 12 of a BF16 value (8 significant bits): ulp = 2^(e - 127 - 7),
 // subnormals and zero take the smallest exponent.
@@ -33,6 +43,15 @@ __device__ inline double bf16_noise(bf16_t b) {
   int e = (b >> 7) & 0xFF;
   if (e == 0) e = 1;
   const double ulp = ldexp(1.0, e - 127 - 7);
+  return ulp * ulp * (1.0 / 12.0);
+}
+
+// ulp(a)^2 / 12 of an FP16 value (11 significant bits): ulp = 2^(e - 15 - 10),
+// subnormals and zero take the smallest exponent.
+__device__ inline double f16_noise(uint16_t h) {
+  int e = (h >> 10) & 0x1F;
+  if (e == 0) e = 1;
+  const double ulp = ldexp(1.0, e - 15 - 10);
   return ulp * ulp * (1.0 / 12.0);
 }
 
@@ -53,7 +72,7 @@ template <typename TA, typename T>
 __global__ void __launch_bounds__(256)
 k_residual(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, const double* __restrict__ U,
            int64_t ldu, const double* __restrict__ S, const double* __restrict__ V, int64_t ldv, int k, int KP,
-           double* __restrict__ part) {
+           double* __restrict__ part, const int* __restrict__ cexp) {
   using M = ResMfma<T>;
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   T* Ws = reinterpret_cast<T*>(lds_raw);  // KP x kResLd
@@ -62,7 +81,11 @@ k_residual(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, const do
   for (int i = threadIdx.x; i < KP * kResCols; i += 256) {
     const int j = i / KP, c = i % KP;  // c fastest: contiguous reads of a row of V
     T w = T(0);
-    if (c < k && c0 + j < n) w = (T)(S[c] * V[(c0 + j) * ldv + c]);
+    if (c < k && c0 + j < n) {
+      double x = S[c] * V[(c0 + j) * ldv + c];
+      if (cexp) x = ldexp(x, cexp[c0 + j]);
+      w = (T)x;
+    }
     Ws[c * kResLd + j] = w;
   }
   __syncthreads();
@@ -90,9 +113,16 @@ k_residual(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, const do
         const int64_t row = rbase + M::row(l, r);
         if (row < m && col < n) {
           const TA* p = A + row * lda + col;
-          const double d = load_a<TA>(p) - (double)acc[ct][r];
-          res += d * d;
-          if constexpr (sizeof(TA) == 2) noise += bf16_noise(*p);
+          if constexpr (std::is_same<TA, f16_word>::value) {
+            const int e = cexp ? cexp[col] : 0;
+            const double d = load_a<TA>(p) - (double)acc[ct][r];
+            res += ldexp(d * d, -2 * e);
+            noise += ldexp(f16_noise(p->bits), -2 * e);
+          } else {
+            const double d = load_a<TA>(p) - (double)acc[ct][r];
+            res += d * d;
+            if constexpr (sizeof(TA) == 2) noise += bf16_noise(*p);
+          }
         }
       }
     }
@@ -160,23 +190,28 @@ int64_t residual_row_groups(int64_t m, int64_t n) {
 
 int64_t residual_parts(int64_t m, int64_t n) { return ceil_div(n, kResCols) * residual_row_groups(m, n); }
 
-// a_type: 0 FP64, 1 FP32, 2 BF16. part: 2 residual_parts(m, n) doubles.
+// a_type: 0 FP64, 1 FP32, 2 BF16, 4 FP16 (cexp: its column exponents, or
+// null). part: 2 residual_parts(m, n) doubles.
 hipError_t launch_residual(int a_type, const void* A, int64_t lda, int64_t m, int64_t n, const double* U,
                            int64_t ldu, const double* S, const double* V, int64_t ldv, int k, int KP, double* part,
-                           void* info, hipStream_t st) {
+                           void* info, hipStream_t st, const int* cexp) {
   const dim3 grid((unsigned)ceil_div(n, kResCols), (unsigned)residual_row_groups(m, n));
   if (a_type == 0) {
     const size_t shm = (size_t)KP * kResLd * sizeof(double);
     hipLaunchKernelGGL((k_residual<double, double>), grid, dim3(256), shm, st, (const double*)A, lda, m, n, U, ldu,
-                       S, V, ldv, k, KP, part);
+                       S, V, ldv, k, KP, part, nullptr);
   } else if (a_type == 1) {
     const size_t shm = (size_t)KP * kResLd * sizeof(float);
     hipLaunchKernelGGL((k_residual<float, float>), grid, dim3(256), shm, st, (const float*)A, lda, m, n, U, ldu, S,
-                       V, ldv, k, KP, part);
+                       V, ldv, k, KP, part, nullptr);
+  } else if (a_type == 4) {
+    const size_t shm = (size_t)KP * kResLd * sizeof(float);
+    hipLaunchKernelGGL((k_residual<f16_word, float>), grid, dim3(256), shm, st, (const f16_word*)A, lda, m, n, U,
+                       ldu, S, V, ldv, k, KP, part, cexp);
   } else {
     const size_t shm = (size_t)KP * kResLd * sizeof(float);
     hipLaunchKernelGGL((k_residual<bf16_t, float>), grid, dim3(256), shm, st, (const bf16_t*)A, lda, m, n, U, ldu,
-                       S, V, ldv, k, KP, part);
+                       S, V, ldv, k, KP, part, nullptr);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "../../include/sorsvd.h"
-#include "common.hpp"
+#include "half16.hpp"
 
 namespace sor {
 
@@ -54,20 +54,26 @@ hipError_t launch_rpca_step(const double* X, int64_t ldx, int64_t m, int64_t n, 
                             double* L, double* S, int64_t ld, double* Y, double* W, double* rpart,
                             hipStream_t st);
 hipError_t launch_rpca_nnz(const double* S, int64_t ld, int64_t m, int64_t n, double* pcount, hipStream_t st);
-int bf16_slots(bool trans, int rt, int LP);
 int skinny_step(int a_type);
-// gemm_bf16.hip
-hipError_t launch_bf16_pass(bool trans, const bf16_t* A, int64_t lda, int64_t OUT, int64_t K,
-                            const bf16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit,
-                            float* P, double* normp, double* Tout, int fold, int rt, hipStream_t st);
+// gemm_bf16.hip (16-bit passes; FP16 instantiations in gemm_f16.hip)
+hipError_t launch_h16_pass(int fmt, bool trans, const uint16_t* A, int64_t lda, int64_t OUT, int64_t K,
+                           const uint16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit, float* P,
+                           double* normp, double* Tout, int fold, int rt, const H16Scale* sc, const int* cexp,
+                           hipStream_t st);
+int h16_slots(int fmt, bool trans, int rt, int LP);
 int bf16_step(bool trans, int rt);
-hipError_t launch_cast_bf16_t(const double* Q, int64_t rows, int LP, int64_t ldt, int permute,
-                              int with_lo, bf16_t* QT, hipStream_t st);
+hipError_t launch_cast_h16_t(int fmt, const double* Q, int64_t rows, int LP, int64_t ldt, int permute,
+                             int with_lo, uint16_t* QT, const H16Scale* sc, const int* cexp, hipStream_t st);
 hipError_t launch_reduce_fold(const float* P, int64_t OUT, int LP2, int nsplit, double* out,
                               int64_t ldo, int ncols, hipStream_t st);
+hipError_t launch_reduce_h16(bool trans, const float* P, int64_t OUT, int LP2, int nsplit, double* out, int64_t ldo,
+                             int ncols, int fold, const H16Scale* sc, const int* cexp, hipStream_t st);
+hipError_t launch_h16_scale(const int* cexp, int64_t n, int shift, H16Scale* sc, int* flags, hipStream_t st);
 // philox.hip
 hipError_t launch_omega_bf16_t(uint64_t seed, int64_t rows, int64_t cols, bf16_t* out,
                                int64_t ldx, hipStream_t st);
+hipError_t launch_omega_f16_t(uint64_t seed, int64_t rows, int64_t cols, uint16_t* out, int64_t ldx,
+                              const H16Scale* sc, const int* cexp, hipStream_t st);
 hipError_t launch_omega_f64_colmajor(uint64_t seed, uint64_t stream_id, uint64_t word2,
                                      int64_t rows, int64_t cols, double* out, hipStream_t st);
 hipError_t launch_omega_rowmajor_f64(uint64_t seed, int64_t rows, int64_t cols, double* out,
@@ -99,7 +105,7 @@ hipError_t launch_features(const double* sv, int l, float* feat, hipStream_t st)
 int64_t residual_parts(int64_t m, int64_t n);
 hipError_t launch_residual(int a_type, const void* A, int64_t lda, int64_t m, int64_t n, const double* U,
                            int64_t ldu, const double* S, const double* V, int64_t ldv, int k, int KP, double* part,
-                           void* info, hipStream_t st);
+                           void* info, hipStream_t st, const int* cexp);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 
 namespace {
@@ -166,21 +172,29 @@ struct Plan {
   int q;
   int es;
   int max_sweeps;
-  int refine;     // BF16: projection pass with Q2 = hi + lo
+  int fmt;        // 16-bit A: kFmtBF16 / kFmtF16; -1 otherwise
+  const int* cexp;  // FP16 A: column exponents (A = A_stored diag(2^-e_j)), or null
+  int refine;     // 16-bit A: projection pass with Q2 = hi + lo
   int residual;   // explicit residual pass after the lift
   int pass_eff;   // M from the last orbit product (no projection pass)
-  int64_t ldt;    // BF16: leading dimension of the transposed skinny operands
-  int rt_nn, rt_tn, rt_proj;  // BF16: rows (NN) / columns (TN) of A per workgroup = 64 rt
-  Split projb;    // BF16: split of the refinement projection pass
+  int64_t ldt;    // 16-bit A: leading dimension of the transposed skinny operands
+  int rt_nn, rt_tn, rt_proj;  // 16-bit A: rows (NN) / columns (TN) of A per workgroup = 64 rt
+  Split projb;    // 16-bit A: split of the refinement projection pass
   Split nn, tn, gram_m, gram_n, proj;
   int nn_blocks;
   size_t off_info, off_xc, off_t1, off_t2, off_w, off_u64, off_v64, off_p, off_normp;
   size_t off_g, off_rinv, off_m, off_ut, off_vt, off_vg, off_pval, off_pidx, off_sgn, off_skip, off_res;
   size_t off_t2p;  // pass_eff: the last orbit product before its QR (n x LP FP64)
+  size_t off_hsc;  // FP16 A: the operand scale record (H16Scale)
   size_t total;
 };
 
 int elem_size(int t) { return (t == SORSVD_F64 || t == SORSVD_DIAG) ? 8 : (t == SORSVD_F32 ? 4 : 2); }
+
+// FP16 skinny operands are lifted by 2^12 (orthonormal entries |q| <= 1 and
+// Gaussian draws below 7 stay under 2^15), which keeps all but entries below
+// 2^-26 out of the FP16 subnormal range.
+constexpr int kF16Shift = 12;
 
 size_t partial_bytes(int64_t OUT, int64_t LP, const Split& s, int acc) {
   return (size_t)s.nsplit * OUT * LP * acc;
@@ -188,8 +202,11 @@ size_t partial_bytes(int64_t OUT, int64_t LP, const Split& s, int acc) {
 
 int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const sorsvd_opts* o,
               Plan* p) {
-  if (a_type != SORSVD_F64 && a_type != SORSVD_F32 && a_type != SORSVD_BF16 && a_type != SORSVD_DIAG)
+  if (a_type != SORSVD_F64 && a_type != SORSVD_F32 && a_type != SORSVD_BF16 && a_type != SORSVD_DIAG &&
+      a_type != SORSVD_F16)
     return SORSVD_EINVAL;
+  const bool h16 = a_type == SORSVD_BF16 || a_type == SORSVD_F16;
+  if (o && o->col_exp && a_type != SORSVD_F16) return SORSVD_EUNSUPPORTED;
   if (m < 1 || n < 1 || k < 1 || q < 0) return SORSVD_EINVAL;
   if (a_type == SORSVD_DIAG && m != n) return SORSVD_EINVAL;
   if (a_type == SORSVD_DIAG && o && o->residual) return SORSVD_EUNSUPPORTED;
@@ -200,37 +217,38 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->a_type = a_type; p->m = m; p->n = n; p->k = k; p->l = l; p->LP = LP; p->KP = KP; p->q = q;
   p->es = elem_size(a_type);
   p->max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
-  p->refine = (a_type == SORSVD_BF16 && o && o->refine) ? 1 : 0;
+  p->fmt = a_type == SORSVD_BF16 ? kFmtBF16 : (a_type == SORSVD_F16 ? kFmtF16 : -1);
+  p->cexp = (o && a_type == SORSVD_F16) ? (const int*)o->col_exp : nullptr;
+  p->refine = (h16 && o && o->refine) ? 1 : 0;
   p->residual = (o && o->residual) ? 1 : 0;
   p->pass_eff = (o && o->pass_efficient) ? 1 : 0;
-  if (p->pass_eff && a_type == SORSVD_BF16) return SORSVD_EUNSUPPORTED;
+  if (p->pass_eff && h16) return SORSVD_EUNSUPPORTED;
   p->ldt = round_up(std::max(m, n), 128) + 128;  // room for the last step's over-read
   const int forced = o ? o->split : 0;
   const int ks = skinny_step(a_type == SORSVD_DIAG ? SORSVD_F64 : a_type);
   const int acc = (a_type == SORSVD_F64 || a_type == SORSVD_DIAG) ? 8 : 4;
-  // BF16 tiles: wide workgroups amortise the re-read of the skinny operand
+  // 16-bit tiles: wide workgroups amortise the re-read of the skinny operand
   // (an opts override serves tuning sweeps)
   const int tile_opt = o ? o->tile : 0;
   p->rt_nn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
   p->rt_tn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
   p->rt_proj = tile_opt ? std::min(tile_opt, p->refine && LP > 32 ? 2 : 4) : (p->refine ? (LP <= 32 ? 4 : 2) : p->rt_nn);
   const int t64 = a_type == SORSVD_DIAG ? SORSVD_F64 : a_type;
-  const int rpb_m = a_type == SORSVD_BF16 ? 64 * p->rt_nn : skinny_rows_per_block(t64, m);
-  const int rpb_n = a_type == SORSVD_BF16 ? 64 * p->rt_tn : skinny_rows_per_block(t64, n);
-  const int ks_nn = a_type == SORSVD_BF16 ? bf16_step(false, p->rt_nn) : ks;
-  const int ks_tn = a_type == SORSVD_BF16 ? bf16_step(true, p->rt_tn) : ks;
+  const int rpb_m = h16 ? 64 * p->rt_nn : skinny_rows_per_block(t64, m);
+  const int rpb_n = h16 ? 64 * p->rt_tn : skinny_rows_per_block(t64, n);
+  const int ks_nn = h16 ? bf16_step(false, p->rt_nn) : ks;
+  const int ks_tn = h16 ? bf16_step(true, p->rt_tn) : ks;
   const bool skinny_pass = a_type == SORSVD_F32 || a_type == SORSVD_F64;
   const int tcode = a_type == SORSVD_F32 ? 1 : 0;
-  const bool bf16 = a_type == SORSVD_BF16;
   p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced, 8, 8,
                        skinny_pass ? skinny_slots(tcode, false, (int)LP)
-                                   : (bf16 ? bf16_slots(false, p->rt_nn, (int)LP) : 0));
+                                   : (h16 ? h16_slots(p->fmt, false, p->rt_nn, (int)LP) : 0));
   p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced, 8, 8,
                        skinny_pass ? skinny_slots(tcode, true, (int)LP)
-                                   : (bf16 ? bf16_slots(true, p->rt_tn, (int)LP) : 0));
+                                   : (h16 ? h16_slots(p->fmt, true, p->rt_tn, (int)LP) : 0));
   const int LPproj = (int)LP * (p->refine ? 2 : 1);
   p->projb = choose_split(m, n, 64 * p->rt_proj, 128, LPproj, p->es, acc, forced, 8, 8,
-                          bf16 ? bf16_slots(false, p->rt_proj, LPproj) : 0);
+                          h16 ? h16_slots(p->fmt, false, p->rt_proj, LPproj) : 0);
   // l x l products over a tall FP64 operand: many short splits (the partial
   // sums are small next to the operand)
   const int ks64 = skinny_step(SORSVD_F64);
@@ -239,12 +257,12 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->gram_n = choose_split(LP, n, rpbg, ks64, (int)LP, 8, 8, 0, 4, 2);
   p->proj = p->gram_m;
   p->nn_blocks = (int)(ceil_div(m, rpb_m) * p->nn.nsplit);
-  if (a_type == SORSVD_BF16 && p->rt_nn != 1 && p->rt_nn != 2 && p->rt_nn != 4) return SORSVD_EINVAL;
+  if (h16 && p->rt_nn != 1 && p->rt_nn != 2 && p->rt_nn != 4) return SORSVD_EINVAL;
 
   Layout L;
   p->off_info = L.take(256);
   const int64_t rows = std::max(m, n);
-  p->off_xc = a_type == SORSVD_BF16 ? L.take((size_t)2 * LP * p->ldt * 2) : L.take((size_t)rows * LP * p->es);
+  p->off_xc = h16 ? L.take((size_t)2 * LP * p->ldt * 2) : L.take((size_t)rows * LP * p->es);
   p->off_t1 = L.take((size_t)m * LP * 8);
   p->off_t2 = L.take((size_t)n * LP * 8);
   p->off_w = L.take((size_t)m * LP * 8);
@@ -270,6 +288,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->off_skip = L.take(64);
   p->off_res = p->residual ? L.take((size_t)2 * residual_parts(m, n) * 8) : 0;
   p->off_t2p = p->pass_eff ? L.take((size_t)n * LP * 8) : 0;
+  p->off_hsc = a_type == SORSVD_F16 ? L.take(sizeof(H16Scale)) : 0;
   p->total = L.total;
   return SORSVD_OK;
 }
@@ -361,17 +380,21 @@ int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, 
     if (e1) SORSVD_TRY(hipEventRecord(e1, st));
     if (sp.nsplit > 1) SORSVD_TRY(launch_reduce_f32(P, OUT, LP, sp.nsplit, T, LP, LP, st));
   } else {
-    // BF16: Xc is the transposed operand; `fold` = the refinement pass with
-    // [Q2 hi | Q2 lo] (2 LP columns) whose two halves are summed.
+    // 16-bit A: Xc is the transposed operand; `fold` = the refinement pass
+    // with [Q2 hi | Q2 lo] (2 LP columns) whose two halves are summed. FP16
+    // operands carry the scaling of the scale record, undone on T.
     float* P = at<float>(ws, p.off_p);
     const int LPw = fold ? 2 * LP : LP;
     const Split& spb = proj ? p.projb : sp;
     const int rt = proj ? p.rt_proj : (trans ? p.rt_tn : p.rt_nn);
-    SORSVD_TRY(launch_bf16_pass(trans, (const bf16_t*)A, lda, OUT, K, (const bf16_t*)Xc, p.ldt, LPw,
-                                spb.kchunk, spb.nsplit, P, normp, T, fold ? 1 : 0, rt, st));
+    const H16Scale* sc = p.fmt == kFmtF16 ? at<H16Scale>(ws, p.off_hsc) : nullptr;
+    SORSVD_TRY(launch_h16_pass(p.fmt, trans, (const uint16_t*)A, lda, OUT, K, (const uint16_t*)Xc, p.ldt, LPw,
+                               spb.kchunk, spb.nsplit, P, normp, T, fold ? 1 : 0, rt, sc, p.cexp, st));
     if (e1) SORSVD_TRY(hipEventRecord(e1, st));
     if (spb.nsplit > 1) {  // with one split the kernel wrote T itself
-      if (fold)
+      if (sc)
+        SORSVD_TRY(launch_reduce_h16(trans, P, OUT, LPw, spb.nsplit, T, LP, LP, fold ? 1 : 0, sc, p.cexp, st));
+      else if (fold)
         SORSVD_TRY(launch_reduce_fold(P, OUT, LPw, spb.nsplit, T, LP, LP, st));
       else
         SORSVD_TRY(launch_reduce_f32(P, OUT, LP, spb.nsplit, T, LP, LP, st));
@@ -381,21 +404,33 @@ int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, 
 }
 
 // Skinny operand of the next pass: Q (rows x LP, FP64) in A's compute type.
-// BF16: transposed, with the contraction permutation for the orbit (TN)
-// pass, and with the low part appended for the refinement pass.
+// 16-bit: transposed, with the contraction permutation for the orbit (TN)
+// pass, and with the low part appended for the refinement pass; FP16 also
+// scaled (H16Scale).
 const void* as_operand(const Plan& p, const double* Q, int64_t rows, void* ws, hipStream_t st, int* rc,
                        bool for_tn = false, bool with_lo = false) {
   *rc = SORSVD_OK;
   if (p.a_type == SORSVD_F64 || p.a_type == SORSVD_DIAG) return Q;
-  if (p.a_type == SORSVD_BF16) {
-    bf16_t* XT = at<bf16_t>(ws, p.off_xc);
-    if (launch_cast_bf16_t(Q, rows, (int)p.LP, p.ldt, for_tn ? 1 : 0, with_lo ? 1 : 0, XT, st) != hipSuccess)
+  if (p.fmt >= 0) {
+    uint16_t* XT = at<uint16_t>(ws, p.off_xc);
+    const H16Scale* sc = p.fmt == kFmtF16 ? at<H16Scale>(ws, p.off_hsc) : nullptr;
+    if (launch_cast_h16_t(p.fmt, Q, rows, (int)p.LP, p.ldt, for_tn ? 1 : 0, with_lo ? 1 : 0, XT, sc,
+                          for_tn ? nullptr : p.cexp, st) != hipSuccess)
       *rc = SORSVD_EHIP;
     return XT;
   }
   float* Xc = at<float>(ws, p.off_xc);
   if (launch_cast_f32(Q, rows * p.LP, Xc, st) != hipSuccess) *rc = SORSVD_EHIP;
   return Xc;
+}
+
+// FP16 A: the operand scale record of this run (min of the column exponents;
+// flags bit 3 of the result record when one lies outside +-kMaxColExp).
+int h16_setup(const Plan& p, void* ws, hipStream_t st) {
+  if (p.fmt != kFmtF16) return SORSVD_OK;
+  int* flags = reinterpret_cast<int*>(at<char>(ws, p.off_info) + offsetof(sorsvd_info, flags));
+  SORSVD_TRY(launch_h16_scale(p.cexp, p.n, kF16Shift, at<H16Scale>(ws, p.off_hsc), flags, st));
+  return SORSVD_OK;
 }
 
 // q1 != null: Q1 of the first sketch is given (q1, leading dimension ldq1, at
@@ -415,6 +450,7 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   double* normp = at<double>(ws, p.off_normp);
   int rc;
   SORSVD_TRY(launch_info_init(info, st));
+  if ((rc = h16_setup(p, ws, st))) return rc;
 
   // Omega, n x l (Alg. 3 / Alg. 4 step 1), straight into the compute-type operand.
   void* Xc = at<void>(ws, p.off_xc);
@@ -428,7 +464,10 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
     SORSVD_TRY(launch_omega_rowmajor_f32(seed, p.n, p.l, (float*)Xc, LP, st));
   } else {
     SORSVD_TRY(launch_fill((double*)Xc, LP * p.ldt * 2 / 8, 0.0, st));
-    SORSVD_TRY(launch_omega_bf16_t(seed, p.n, p.l, (bf16_t*)Xc, p.ldt, st));
+    if (p.fmt == kFmtF16)
+      SORSVD_TRY(launch_omega_f16_t(seed, p.n, p.l, (uint16_t*)Xc, p.ldt, at<H16Scale>(ws, p.off_hsc), p.cexp, st));
+    else
+      SORSVD_TRY(launch_omega_bf16_t(seed, p.n, p.l, (bf16_t*)Xc, p.ldt, st));
   }
 
   // T1 = A Omega (eq. T1), with ||A||_F^2 accumulated on the way; Q1 = qr(T1).
@@ -498,7 +537,7 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   // rounding of A to BF16).
   if (p.residual)
     SORSVD_TRY(launch_residual(p.a_type, A, lda, p.m, p.n, U, ldu, S, V, ldv, (int)p.k, (int)KP,
-                               at<double>(ws, p.off_res), info, st));
+                               at<double>(ws, p.off_res), info, st, p.cexp));
   return SORSVD_OK;
 }
 
@@ -609,7 +648,7 @@ size_t sorsvd_step_workspace_bytes(int64_t m, int64_t n, int64_t l, int32_t a_ty
   sorsvd_opts o;
   std::memset(&o, 0, sizeof(o));
   o.l = l;
-  o.refine = a_type == SORSVD_BF16 ? 1 : 0;
+  o.refine = (a_type == SORSVD_BF16 || a_type == SORSVD_F16) ? 1 : 0;
   Plan p;
   if (make_plan(m, n, l, 0, a_type, &o, &p) != SORSVD_OK) return 0;
   // room for packed FP64 copies of two skinny operands (QR input copy, projection)
@@ -620,7 +659,7 @@ static int step_plan(int64_t m, int64_t n, int64_t l, int32_t a_type, size_t ws_
   sorsvd_opts o;
   std::memset(&o, 0, sizeof(o));
   o.l = l;
-  o.refine = a_type == SORSVD_BF16 ? 1 : 0;  // the BF16 projection step uses the hi + lo split
+  o.refine = (a_type == SORSVD_BF16 || a_type == SORSVD_F16) ? 1 : 0;  // 16-bit projection: hi + lo split
   const int rc = make_plan(m, n, l, 0, a_type, &o, p);
   if (rc != SORSVD_OK) return rc;
   if (ws_bytes < sorsvd_step_workspace_bytes(m, n, l, a_type)) return SORSVD_EWORKSPACE;
@@ -629,7 +668,7 @@ static int step_plan(int64_t m, int64_t n, int64_t l, int32_t a_type, size_t ws_
 
 static int pack_operand(const Plan& p, const double* src, int64_t rows, int64_t l, void* ws,
                         hipStream_t st, const void** out, bool for_tn = false, bool with_lo = false) {
-  if (p.a_type == SORSVD_BF16) {
+  if (p.fmt >= 0) {
     double* tmp = at<double>(ws, p.total + round_up(std::max(p.m, p.n) * p.LP * 8, kAlign));
     SORSVD_TRY(launch_pack_f64(src, rows, (int)l, l, tmp, (int)p.LP, st));
     int rc;
@@ -655,6 +694,7 @@ int sorsvd_step_sketch(const void* A, int64_t lda, int32_t a_type, int64_t m, in
   if (rc) return rc;
   if (!A || !X || !T || lda < n) return SORSVD_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  if ((rc = h16_setup(p, ws, st))) return rc;
   const void* Xc;
   if ((rc = pack_operand(p, X, n, l, ws, st, &Xc))) return rc;
   double* Tp = at<double>(ws, p.off_t1);
@@ -670,6 +710,7 @@ int sorsvd_step_orbit(const void* A, int64_t lda, int32_t a_type, int64_t m, int
   if (rc) return rc;
   if (!A || !Y || !T || lda < n) return SORSVD_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  if ((rc = h16_setup(p, ws, st))) return rc;
   const void* Yc;
   if ((rc = pack_operand(p, Y, m, l, ws, st, &Yc, true))) return rc;
   double* Tp = at<double>(ws, p.off_t2);
@@ -713,8 +754,9 @@ int sorsvd_step_project(const void* A, int64_t lda, int32_t a_type, int64_t m, i
   if (!A || !Q1 || !Q2 || !M || lda < n) return SORSVD_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const int LP = (int)p.LP;
+  if ((rc = h16_setup(p, ws, st))) return rc;
   const void* Xc;
-  const bool fold = p.a_type == SORSVD_BF16;
+  const bool fold = p.fmt >= 0;
   if ((rc = pack_operand(p, Q2, n, l, ws, st, &Xc, false, fold))) return rc;
   double* W = at<double>(ws, p.off_w);
   if ((rc = pass(p, false, A, lda, Xc, W, nullptr, ws, st, fold, true))) return rc;
@@ -784,6 +826,7 @@ int sorsvd_pass_timing_read(double* total_ms, int64_t* launches, double* bytes, 
 // ------------------------------------------------------------------ learned (k, q)
 
 static int probe_plan(int64_t m, int64_t n, int32_t a_type, Plan* p) {
+  if (a_type == SORSVD_F16) return SORSVD_EUNSUPPORTED;
   const int64_t l = std::min<int64_t>(kMaxLP, std::min(m, n));
   sorsvd_opts o;
   std::memset(&o, 0, sizeof(o));
@@ -845,6 +888,7 @@ static constexpr int kAutoFallbackQ = 2;
 static constexpr double kNoiseShare = 4.0;   // BF16 judge: captured rounding-noise allowance / i.i.d. bound
 
 static int auto_plan(int64_t m, int64_t n, int32_t a_type, Plan* p) {
+  if (a_type == SORSVD_F16) return SORSVD_EUNSUPPORTED;
   const int64_t kcap = std::min<int64_t>(kMaxLP, std::min(m, n));
   sorsvd_opts o;
   std::memset(&o, 0, sizeof(o));

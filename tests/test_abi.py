@@ -45,6 +45,34 @@ def test_workspace_query_validates_shapes():
     assert P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, pass_efficient=1) == 0
 
 
+def test_fp16_workspace_and_unsupported_combinations(clib):
+    # FP16 A shares the 16-bit plan and adds the 256-byte operand scale record
+    assert (P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F16, refine=1)
+            == P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, refine=1) + 256)
+    assert P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F16, pass_efficient=1) == 0
+
+    def ws(t, col_exp):  # col_exp is only checked for null on the host
+        o = _lib.Opts(col_exp=col_exp)
+        return clib.sorsvd_workspace_bytes(3000, 2000, 32, 1, t, ctypes.byref(o))
+    assert ws(P.SORSVD_F16, 64) == ws(P.SORSVD_F16, None) > 0
+    for t in (P.SORSVD_F64, P.SORSVD_F32, P.SORSVD_BF16, P.SORSVD_DIAG):
+        assert ws(t, 64) == 0  # column exponents are an FP16 option
+    # no (k, q) predictor and no probe for FP16 A
+    assert clib.sorsvd_probe_workspace_bytes(3000, 2000, P.SORSVD_F16) == 0
+    assert clib.sorsvd_auto_workspace_bytes(3000, 2000, P.SORSVD_F16) == 0
+    assert clib.sorsvd_step_workspace_bytes(3000, 2000, 32, P.SORSVD_F16) > 0
+
+
+def test_pack_f16_rejects_bad_arguments_before_launch(clib):
+    vp = ctypes.c_void_p
+    assert clib.sorsvd_pack_f16(vp(1), 100, P.SORSVD_F64, 50, 101, vp(1), 101, vp(1), None) == EINVAL  # lda < n
+    assert clib.sorsvd_pack_f16(vp(1), 101, P.SORSVD_F64, 50, 101, vp(1), 100, vp(1), None) == EINVAL  # ldo < n
+    assert clib.sorsvd_pack_f16(vp(0), 101, P.SORSVD_F32, 50, 101, vp(1), 101, vp(1), None) == EINVAL  # null A
+    assert clib.sorsvd_pack_f16(vp(1), 101, P.SORSVD_F32, 50, 101, vp(1), 101, vp(0), None) == EINVAL  # null e
+    assert clib.sorsvd_pack_f16(vp(1), 101, P.SORSVD_BF16, 50, 101, vp(1), 101, vp(1), None) == EUNSUPPORTED
+    assert clib.sorsvd_pack_f16(vp(0), 0, P.SORSVD_F64, 0, 0, vp(0), 0, vp(0), None) == 0  # empty: nothing to do
+
+
 def _call(clib, A=1, lda=800, t=0, m=1000, n=800, k=20, q=0, U=1, ldu=20, S=1, V=1, ldv=20, ws=256, wsb=1 << 40,
           opts=None):
     vp = ctypes.c_void_p

@@ -141,9 +141,9 @@ def c2_torch(device="cuda", n=20000, seed=2):
     return spectral_torch(n, n, sigma_power(n, 2.0), seed, device, torch.float32)
 
 
-def c3_torch(device="cuda", m=200000, n=4000, seed=4, r=400):
+def c3_torch(device="cuda", m=200000, n=4000, seed=4, r=400, out_dtype=None):
     torch = _torch()
-    return spectral_torch(m, n, sigma_geometric(r, 0.9), seed, device, torch.bfloat16, noise_sd=1e-6)
+    return spectral_torch(m, n, sigma_geometric(r, 0.9), seed, device, out_dtype or torch.bfloat16, noise_sd=1e-6)
 
 
 def rpca_problem_torch(m, n, r, seed, device="cuda", frac=0.05, amp=10.0, dtype=None):
