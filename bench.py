@@ -414,6 +414,7 @@ def main():
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "err_fro": head["err_fro"],
+        "err_vs_fp64": head.get("err_vs_fp64"),
         "jacobi_sweeps": head["jacobi_sweeps"],
         "extra": extra,
     }
