@@ -45,10 +45,31 @@ __device__ inline int xcd_remap_b(int b, int nb) {
 
 union Frag {
   uint4 u;
+  u32x4_t w;
   bf16x8 v;
   f16x8 f;
   uint16_t h[8];
 };
+
+// 8 consecutive 16-bit values p[0..7] as one 16-byte word, with zeros where
+// ok_t is false: the path for unaligned rows and ragged ends. It builds whole
+// 32-bit words, so that the vector path beside it keeps its loaded registers
+// as they are (values assembled from 16-bit halves would make the compiler
+// unpack, and so wait for, every vector load at once).
+__device__ inline u32x4_t load8_slow(const uint16_t* p, int nvalid) {
+  uint32_t w[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const uint32_t lo = 2 * t < nvalid ? p[2 * t] : 0u;
+    const uint32_t hi = 2 * t + 1 < nvalid ? p[2 * t + 1] : 0u;
+    w[t] = lo | (hi << 16);
+  }
+  return u32x4_t{w[0], w[1], w[2], w[3]};
+}
+
+__device__ inline u32x4_t load16_nt(const uint16_t* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+}
 
 template <int FMT> __device__ inline f32x4 mfma16(const Frag& a, const Frag& b, f32x4 c) {
   if constexpr (FMT == kFmtBF16) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
@@ -111,21 +132,35 @@ __device__ inline void store_tiles(const f32x4 (&acc)[RT][CT], int64_t base, int
 
 // ---------------------------------------------------------------------------
 // NN: P_s[r][c] = sum_{k in split s} A[r][k] X[k][c]; X given as XT (LP x ldx).
-// No LDS and no barriers: each wave owns 16 RW rows and streams them in
-// steps of 32 contraction indices. Per step a lane loads one 16-byte A
-// fragment per row tile (row l % 16, indices 8 (l / 16) .. + 7) and one
-// 16-byte skinny fragment per column tile (column l % 16, same indices; an
-// L2 hit), exactly the MFMA operand layouts. A ring of D steps of fragments
-// keeps D - 1 steps of loads in flight behind the MFMAs. NRM: also the FP64
-// sum of squares of the A elements read (FP16: column j weighted by
-// 4^-e_j), one value per workgroup in normp.
-template <int FMT, int RW, int CT, int D, bool NRM>
+// Each wave owns 16 RW rows and streams them in steps of 32 contraction
+// indices: per step a lane loads one 16-byte A fragment per row tile (row
+// l % 16, indices 8 (l / 16) .. + 7, the MFMA operand layout) straight into
+// registers, and a ring of D steps keeps D - 1 steps of A loads in flight
+// behind the MFMAs. The skinny operand is shared by the four waves through
+// LDS: blocks of KB contraction indices of XT (LP x KB) are loaded by the
+// whole workgroup one block ahead and stored to the other of two LDS buffers
+// (one barrier per block); each wave then reads its 16-byte B fragments from
+// LDS (rows padded by 8 values, so the 16 rows of a read start 4 banks apart).
+// Loading them per wave from L2 instead doubles the vector-memory traffic at
+// l = 64 and triples it for the refinement pass. NRM: also the FP64 sum of
+// squares of the A elements read (FP16: column j weighted by 4^-e_j), one
+// value per workgroup in normp. kchunk must be a multiple of KB.
+template <int CT> constexpr int nn_kb() { return CT >= 10 ? 64 : 128; }
+
+template <int FMT, int RW, int CT, bool NRM>
 __global__ void __launch_bounds__(256, 2)
 k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
          const uint16_t* __restrict__ XT, int64_t ldx, int64_t kchunk, int tiles, int nsplit,
          int vec_ok, float* __restrict__ P, double* __restrict__ normp, double* __restrict__ Tout,
          int fold, const H16Scale* __restrict__ sc, const int* __restrict__ cexp) {
   constexpr int KS32 = 32;
+  constexpr int LP = CT * kTile;
+  constexpr int KB = nn_kb<CT>();        // contraction indices per skinny block
+  constexpr int D = KB / KS32;           // A ring depth = steps per block
+  constexpr int XS = KB + 8;             // LDS row stride of a skinny block
+  constexpr int XCH = LP * KB / 8 / 256; // 16-byte skinny chunks per thread per block
+  static_assert(XCH * 256 * 8 == LP * KB, "skinny block must split evenly over the workgroup");
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][LP * XS];
   __shared__ double red[4];
   const int nb = tiles * nsplit;
   const int v = xcd_remap_b((int)blockIdx.x, nb);
@@ -143,33 +178,54 @@ k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0, 0, 0, 0};
   double nrm = 0.0;
 
-  auto load = [&](Frag (&a)[RW], Frag (&x)[CT], int64_t kb) {
+  auto load_a = [&](Frag (&a)[RW], int64_t kb) {
     const int64_t kk = kb + 8 * g;
 #pragma unroll
     for (int rt = 0; rt < RW; ++rt) {
       const int64_t row = base + (int64_t)(w * RW + rt) * kTile + li;
-      if (row < OUT && kk + 8 <= k1 && vec_ok) {
-        a[rt].u = load_stream16(A + row * lda + kk);
-      } else {
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          a[rt].h[t] = (row < OUT && kk + t < k1) ? A[row * lda + kk + t] : (uint16_t)0;
-      }
+      const bool in = row < OUT && kk < k1;
+      if (vec_ok)  // rows 16-byte aligned and K % 8 == 0: whole chunks or none
+        a[rt].w = in ? load16_nt(A + row * lda + kk) : u32x4_t{0, 0, 0, 0};
+      else
+        a[rt].w = in ? load8_slow(A + row * lda + kk, (int)min<int64_t>(8, k1 - kk)) : u32x4_t{0, 0, 0, 0};
     }
+  };
+  // chunk q of a block: skinny row c = q / (KB / 8), values 8 (q % (KB / 8)) .. + 7
+  // (XT is zero-padded to ldx >= round_up(K, 128) + 128, so whole blocks are in bounds)
+  u32x4_t xr[XCH];
+  auto load_x = [&](int64_t kb) {
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)  // XT is zero-padded to ldx >= round_up(K, 128)
-      x[ct].u = *reinterpret_cast<const uint4*>(XT + (int64_t)(ct * kTile + li) * ldx + kk);
+    for (int i = 0; i < XCH; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      const int c = q / (KB / 8), o = 8 * (q % (KB / 8));
+      xr[i] = *reinterpret_cast<const u32x4_t*>(XT + (int64_t)c * ldx + kb + o);
+    }
+  };
+  auto store_x = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < XCH; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      const int c = q / (KB / 8), o = 8 * (q % (KB / 8));
+      *reinterpret_cast<u32x4_t*>(&Xs[b][c * XS + o]) = xr[i];
+    }
   };
 
-  Frag ab[D][RW], xb[D][CT];
+  Frag ab[D][RW];
+  if (k0 < k1) {
+    load_x(k0);
+    store_x(0);
 #pragma unroll
-  for (int d = 0; d < D - 1; ++d) load(ab[d], xb[d], k0 + (int64_t)d * KS32);
-  for (int64_t kb = k0; kb < k1; kb += (int64_t)D * KS32) {
+    for (int d = 0; d < D - 1; ++d) load_a(ab[d], k0 + (int64_t)d * KS32);
+    if (k0 + KB < k1) load_x(k0 + KB);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kb = k0; kb < k1; kb += KB) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int64_t knext = kb + (int64_t)(d + D - 1) * KS32;
-      if (knext < k1) load(ab[(d + D - 1) % D], xb[(d + D - 1) % D], knext);
-      if (kb + (int64_t)d * KS32 < k1) {
+    for (int j = 0; j < D; ++j) {
+      const int64_t knext = kb + (int64_t)(j + D - 1) * KS32;
+      if (knext < k1) load_a(ab[(j + D - 1) % D], knext);
+      if (kb + (int64_t)j * KS32 < k1) {
         if constexpr (NRM) {
           if constexpr (FMT == kFmtBF16) {
 #pragma unroll
@@ -177,7 +233,7 @@ k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
               float q = 0.f;  // 8 squares of BF16 values (exact in FP32): a short FP32 sum, then FP64
 #pragma unroll
               for (int t = 0; t < 8; ++t) {
-                const float x = bf16_to_f32(ab[d][rt].h[t]);
+                const float x = bf16_to_f32(ab[j][rt].h[t]);
                 q += x * x;
               }
               nrm += (double)q;
@@ -186,22 +242,32 @@ k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
             // squares of FP16 values are exact in FP64, and so is the weight
             // 4^-e_j: with or without column exponents the same sum results
             int ev[8];
-            load_exp8(cexp, kb + (int64_t)d * KS32 + 8 * g, k1, ev);
+            load_exp8(cexp, kb + (int64_t)j * KS32 + 8 * g, k1, ev);
 #pragma unroll
             for (int rt = 0; rt < RW; ++rt)
 #pragma unroll
               for (int t = 0; t < 8; ++t) {
-                const double x = (double)h16_to_f32<FMT>(ab[d][rt].h[t]);
+                const double x = (double)h16_to_f32<FMT>(ab[j][rt].h[t]);
                 nrm += ldexp(x * x, -2 * ev[t]);
               }
           }
         }
+        Frag bx[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          bx[ct].w = *reinterpret_cast<const u32x4_t*>(&Xs[buf][(ct * kTile + li) * XS + KS32 * j + 8 * g]);
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int rt = 0; rt < RW; ++rt) acc[rt][ct] = mfma16<FMT>(ab[d][rt], xb[d][ct], acc[rt][ct]);
+          for (int rt = 0; rt < RW; ++rt) acc[rt][ct] = mfma16<FMT>(ab[j][rt], bx[ct], acc[rt][ct]);
       }
     }
+    // the other buffer was last read in the previous block, which every wave
+    // finished before the barrier that ended it
+    if (kb + KB < k1) store_x(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    if (kb + 2 * KB < k1) load_x(kb + 2 * KB);
   }
 
   store_tiles<FMT, false, RW, CT>(acc, base, w, g, li, OUT, s, P, Tout, fold, sc, cexp);
@@ -249,34 +315,31 @@ k_h16_tn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0, 0, 0, 0};
 
-  // A chunk q: tile row r = q / (BN / 8), columns 8 * (q % (BN / 8)) .. + 7
-  auto load_a = [&](uint4 (&ar)[ACH], int64_t kb) {
+  // A chunk q: tile row r = q / (BN / 8), columns 8 * (q % (BN / 8)) .. + 7.
+  // vec_ok (rows 16-byte aligned, OUT % 8 == 0): whole chunks or none.
+  auto load_a = [&](u32x4_t (&ar)[ACH], int64_t kb) {
 #pragma unroll
     for (int i = 0; i < ACH; ++i) {
       const int q = threadIdx.x + 256 * i;
       const int r = q / (BN / 8), cc = 8 * (q % (BN / 8));
       const int64_t row = kb + r, col = base + cc;
-      Frag f;
-      if (row < k1 && col + 8 <= OUT && vec_ok) {
-        f.u = load_stream16(A + row * lda + col);
-      } else {
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          f.h[t] = (row < k1 && col + t < OUT) ? A[row * lda + col + t] : (uint16_t)0;
-      }
-      ar[i] = f.u;
+      const bool in = row < k1 && col < OUT;
+      if (vec_ok)
+        ar[i] = in ? load16_nt(A + row * lda + col) : u32x4_t{0, 0, 0, 0};
+      else
+        ar[i] = in ? load8_slow(A + row * lda + col, (int)min<int64_t>(8, OUT - col)) : u32x4_t{0, 0, 0, 0};
     }
   };
-  auto load_y = [&](uint4 (&yr)[YCH], int64_t kb) {
+  auto load_y = [&](u32x4_t (&yr)[YCH], int64_t kb) {
 #pragma unroll
     for (int i = 0; i < YCH; ++i) {
       const int q = threadIdx.x + 256 * i;
       const int c = q / (KST / 8), o = 8 * (q % (KST / 8));
-      if (q < YTOT) yr[i] = *reinterpret_cast<const uint4*>(YT + c * ldy + kb + o);  // YT zero-padded to ldy
+      if (q < YTOT) yr[i] = *reinterpret_cast<const u32x4_t*>(YT + c * ldy + kb + o);  // YT zero-padded to ldy
     }
   };
 
-  uint4 ar[ACH], yr[YCH];
+  u32x4_t ar[ACH], yr[YCH];
   if (k0 < k1) { load_a(ar, k0); load_y(yr, k0); }
   for (int64_t kb = k0; kb < k1; kb += KST) {
     __syncthreads();
@@ -284,13 +347,13 @@ k_h16_tn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
     for (int i = 0; i < ACH; ++i) {
       const int q = threadIdx.x + 256 * i;
       const int r = q / (BN / 8), cc = 8 * (q % (BN / 8));
-      *reinterpret_cast<uint4*>(As + r * AS + cc) = ar[i];
+      *reinterpret_cast<u32x4_t*>(As + r * AS + cc) = ar[i];
     }
 #pragma unroll
     for (int i = 0; i < YCH; ++i) {
       const int q = threadIdx.x + 256 * i;
       const int c = q / (KST / 8), o = 8 * (q % (KST / 8));
-      if (q < YTOT) *reinterpret_cast<uint4*>(Ys + c * YS + o) = yr[i];
+      if (q < YTOT) *reinterpret_cast<u32x4_t*>(Ys + c * YS + o) = yr[i];
     }
     __syncthreads();
     if (kb + KST < k1) { load_a(ar, kb + KST); load_y(yr, kb + KST); }
@@ -329,25 +392,29 @@ inline hipError_t launch_h16_rt(bool trans, const uint16_t* A, int64_t lda, int6
   const int tiles = (int)ceil_div(OUT, 64 * RT);
   if (tiles == 0 || nsplit == 0) return hipSuccess;
   if (trans && normp) return hipErrorInvalidValue;
-  const int vec_ok = ((lda * 2) % 16 == 0) && (((uintptr_t)A) % 16 == 0);
+  // whole 16-byte chunks: aligned rows, and no chunk straddling the end of a
+  // row (NN: K % 8 == 0; TN: OUT % 8 == 0)
+  const int vec_ok = ((lda * 2) % 16 == 0) && (((uintptr_t)A) % 16 == 0) && ((trans ? OUT : K) % 8 == 0);
   double* To = nsplit == 1 ? Tout : nullptr;
   constexpr int KST = RT >= 4 ? 64 : 128;
   dim3 grid((unsigned)(tiles * nsplit)), block(256);
-#define SORSVD_BF(C, D)                                                                            \
+#define SORSVD_BF(C)                                                                               \
   case C:                                                                                          \
     if (trans)                                                                                     \
       hipLaunchKernelGGL((k_h16_tn<FMT, RT, C, KST>), grid, block, 0, st, A, lda, OUT, K, XT, ldx, \
                          kchunk, tiles, nsplit, vec_ok, P, To, sc, cexp);                          \
+    else if (kchunk % nn_kb<C>() != 0)                                                             \
+      return hipErrorInvalidValue;                                                                 \
     else if (normp)                                                                                \
-      hipLaunchKernelGGL((k_h16_nn<FMT, RT, C, D, true>), grid, block, 0, st, A, lda, OUT, K, XT,  \
+      hipLaunchKernelGGL((k_h16_nn<FMT, RT, C, true>), grid, block, 0, st, A, lda, OUT, K, XT,     \
                          ldx, kchunk, tiles, nsplit, vec_ok, P, normp, To, fold, sc, cexp);        \
     else                                                                                           \
-      hipLaunchKernelGGL((k_h16_nn<FMT, RT, C, D, false>), grid, block, 0, st, A, lda, OUT, K, XT, \
+      hipLaunchKernelGGL((k_h16_nn<FMT, RT, C, false>), grid, block, 0, st, A, lda, OUT, K, XT,    \
                          ldx, kchunk, tiles, nsplit, vec_ok, P, normp, To, fold, sc, cexp);        \
     break;
   switch (LP / kTile) {
-    SORSVD_BF(1, 4) SORSVD_BF(2, 4) SORSVD_BF(3, 4) SORSVD_BF(4, 4) SORSVD_BF(5, 3) SORSVD_BF(6, 3)
-    SORSVD_BF(7, 3) SORSVD_BF(8, 3) SORSVD_BF(10, 2) SORSVD_BF(12, 2) SORSVD_BF(14, 2) SORSVD_BF(16, 2)
+    SORSVD_BF(1) SORSVD_BF(2) SORSVD_BF(3) SORSVD_BF(4) SORSVD_BF(5) SORSVD_BF(6)
+    SORSVD_BF(7) SORSVD_BF(8) SORSVD_BF(10) SORSVD_BF(12) SORSVD_BF(14) SORSVD_BF(16)
     default: return hipErrorInvalidValue;
   }
 #undef SORSVD_BF
@@ -374,16 +441,16 @@ inline int h16_blocks_per_cu(bool trans, int CT) {
   constexpr int KST = RT >= 4 ? 64 : 128;
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
-#define SORSVD_BF(C, D)                                                                                       \
+#define SORSVD_BF(C)                                                                                          \
   case C:                                                                                                     \
     e = trans ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                 \
                     &nb, reinterpret_cast<const void*>(&k_h16_tn<FMT, RT, C, KST>), 256, 0)                  \
               : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                 \
-                    &nb, reinterpret_cast<const void*>(&k_h16_nn<FMT, RT, C, D, false>), 256, 0);            \
+                    &nb, reinterpret_cast<const void*>(&k_h16_nn<FMT, RT, C, false>), 256, 0);               \
     break;
   switch (CT) {
-    SORSVD_BF(1, 4) SORSVD_BF(2, 4) SORSVD_BF(3, 4) SORSVD_BF(4, 4) SORSVD_BF(5, 3) SORSVD_BF(6, 3)
-    SORSVD_BF(7, 3) SORSVD_BF(8, 3) SORSVD_BF(10, 2) SORSVD_BF(12, 2) SORSVD_BF(14, 2) SORSVD_BF(16, 2)
+    SORSVD_BF(1) SORSVD_BF(2) SORSVD_BF(3) SORSVD_BF(4) SORSVD_BF(5) SORSVD_BF(6)
+    SORSVD_BF(7) SORSVD_BF(8) SORSVD_BF(10) SORSVD_BF(12) SORSVD_BF(14) SORSVD_BF(16)
     default: break;
   }
 #undef SORSVD_BF

@@ -119,20 +119,21 @@ struct Split {
   int nsplit = 1;
 };
 
-// Split of a contraction of length K for OUT output rows: enough workgroups
-// to fill 256 CUs several times over, each split at least `min_steps` steps
-// long, and partial sums no larger than 1/`part_div` of the bytes of the
-// streamed operand. slots > 0 (workgroups the device holds at once): among
+// Split of a contraction of length K for OUT output rows: about `target`
+// workgroups (enough to fill 256 CUs several times over by default), each
+// split at least `min_steps` steps long, and partial sums no larger than
+// 1/`part_div` of the bytes of the streamed operand. slots > 0 (workgroups the device holds at once): among
 // the splits from half of that count up to it, the one whose workgroups fill
 // whole waves of `slots` best (a last, mostly empty wave of workgroups costs
 // as much as a full one); never more splits than without it, so a workspace
 // sized without a device also fits.
 Split choose_split(int64_t OUT, int64_t K, int rows_per_block, int KS, int LP, int es_a,
-                   int acc_bytes, int forced, int min_steps = 8, int part_div = 8, int slots = 0) {
+                   int acc_bytes, int forced, int min_steps = 8, int part_div = 8, int slots = 0,
+                   int64_t target = 2048) {
   Split sp;
   if (K <= 0) { sp.kchunk = KS; sp.nsplit = 1; return sp; }
   const int64_t tiles = std::max<int64_t>(1, ceil_div(OUT, rows_per_block));
-  int64_t s = std::max<int64_t>(1, ceil_div(2048, tiles));
+  int64_t s = std::max<int64_t>(1, ceil_div(target, tiles));
   s = std::min<int64_t>(s, std::max<int64_t>(1, K / ((int64_t)min_steps * KS)));
   s = std::min<int64_t>(s, std::max<int64_t>(1, (K * es_a) / ((int64_t)part_div * LP * acc_bytes)));
   if (forced > 0) s = forced;
@@ -243,9 +244,15 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced, 8, 8,
                        skinny_pass ? skinny_slots(tcode, false, (int)LP)
                                    : (h16 ? h16_slots(p->fmt, false, p->rt_nn, (int)LP) : 0));
-  p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced, 8, 8,
-                       skinny_pass ? skinny_slots(tcode, true, (int)LP)
-                                   : (h16 ? h16_slots(p->fmt, true, p->rt_tn, (int)LP) : 0));
+  // 16-bit A^T Y: a workgroup streams 64 rt whole columns of A with its
+  // contraction rows staged through LDS, so one wave of resident workgroups
+  // already keeps HBM busy; more splits only add partial sums to write and
+  // reduce (measured at 200000 x 4000, l = 64: 6.2 TB/s at 512 workgroups,
+  // 5.0 TB/s at 2000)
+  const int tn_slots = skinny_pass ? skinny_slots(tcode, true, (int)LP)
+                                   : (h16 ? h16_slots(p->fmt, true, p->rt_tn, (int)LP) : 0);
+  p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced, 8, 8, tn_slots,
+                       (h16 && tn_slots > 0) ? tn_slots : 2048);
   const int LPproj = (int)LP * (p->refine ? 2 : 1);
   p->projb = choose_split(m, n, 64 * p->rt_proj, 128, LPproj, p->es, acc, forced, 8, 8,
                           h16 ? h16_slots(p->fmt, false, p->rt_proj, LPproj) : 0);
