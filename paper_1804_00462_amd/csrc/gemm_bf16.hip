@@ -202,8 +202,9 @@ int h16_slots(int fmt, bool trans, int rt, int LP) {
   return slots;
 }
 
-// contraction step of the 16-bit kernels for a given rt (splits are multiples of it)
-int bf16_step(bool trans, int rt) { return (trans && rt >= 4) ? 64 : 128; }
+// contraction step of the 16-bit kernels for a given rt and skinny width LP
+// (splits are multiples of it)
+int bf16_step(bool trans, int rt, int LP) { return trans ? (rt >= 4 ? 64 : 128) : nn_kb(rt, LP); }
 
 hipError_t launch_cast_h16_t(int fmt, const double* Q, int64_t rows, int LP, int64_t ldt, int permute,
                              int with_lo, uint16_t* QT, const H16Scale* sc, const int* cexp, hipStream_t st) {

@@ -132,35 +132,43 @@ __device__ inline void store_tiles(const f32x4 (&acc)[RT][CT], int64_t base, int
 
 // ---------------------------------------------------------------------------
 // NN: P_s[r][c] = sum_{k in split s} A[r][k] X[k][c]; X given as XT (LP x ldx).
-// Each wave owns 16 RW rows and streams them in steps of 32 contraction
-// indices: per step a lane loads one 16-byte A fragment per row tile (row
-// l % 16, indices 8 (l / 16) .. + 7, the MFMA operand layout) straight into
-// registers, and a ring of D steps keeps D - 1 steps of A loads in flight
-// behind the MFMAs. The skinny operand is shared by the four waves through
-// LDS: blocks of KB contraction indices of XT (LP x KB) are loaded by the
-// whole workgroup one block ahead and stored to the other of two LDS buffers
-// (one barrier per block); each wave then reads its 16-byte B fragments from
-// LDS (rows padded by 8 values, so the 16 rows of a read start 4 banks apart).
-// Loading them per wave from L2 instead doubles the vector-memory traffic at
-// l = 64 and triples it for the refinement pass. NRM: also the FP64 sum of
+// A workgroup owns 64 RT rows and walks its contraction range in blocks of KB
+// indices. Per block the tile of A (64 RT rows x KB) and the skinny block
+// (LP x KB of XT) are loaded by the whole workgroup into registers one block
+// ahead, then stored to LDS between two barriers: every wave instruction of
+// the A loads reads KB * 2 bytes of consecutive columns from each of 512 /
+// KB rows (256 B or more; HBM serves reads in such runs far better than in
+// the 64 B pieces of the MFMA operand layout). Each wave then reads its MFMA
+// operands from LDS with 16-byte reads: A fragments of its 16 RT rows (row
+// l % 16, contraction 8 (l / 16) .. + 7 of each step of 32) and B fragments
+// of the skinny block. LDS rows are padded by 8 values so the 16 rows of a
+// fragment read start 4 banks apart. KB is the largest of 256, 128, 64 whose
+// tiles fit 76 KB of LDS (two workgroups per CU). NRM: also the FP64 sum of
 // squares of the A elements read (FP16: column j weighted by 4^-e_j), one
 // value per workgroup in normp. kchunk must be a multiple of KB.
-template <int CT> constexpr int nn_kb() { return CT >= 10 ? 64 : 128; }
+constexpr int nn_lds_bytes(int RT, int LP, int KB) { return (64 * RT + LP) * (KB + 8) * 2; }
+constexpr int nn_kb(int RT, int LP) {
+  return nn_lds_bytes(RT, LP, 256) <= 76 * 1024 ? 256 : (nn_lds_bytes(RT, LP, 128) <= 76 * 1024 ? 128 : 64);
+}
 
-template <int FMT, int RW, int CT, bool NRM>
+template <int FMT, int RT, int CT, bool NRM>
 __global__ void __launch_bounds__(256, 2)
 k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
          const uint16_t* __restrict__ XT, int64_t ldx, int64_t kchunk, int tiles, int nsplit,
          int vec_ok, float* __restrict__ P, double* __restrict__ normp, double* __restrict__ Tout,
          int fold, const H16Scale* __restrict__ sc, const int* __restrict__ cexp) {
-  constexpr int KS32 = 32;
   constexpr int LP = CT * kTile;
-  constexpr int KB = nn_kb<CT>();        // contraction indices per skinny block
-  constexpr int D = KB / KS32;           // A ring depth = steps per block
-  constexpr int XS = KB + 8;             // LDS row stride of a skinny block
-  constexpr int XCH = LP * KB / 8 / 256; // 16-byte skinny chunks per thread per block
-  static_assert(XCH * 256 * 8 == LP * KB, "skinny block must split evenly over the workgroup");
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][LP * XS];
+  constexpr int BR = 64 * RT;                 // rows of A per workgroup
+  constexpr int KB = nn_kb(RT, LP);           // contraction indices per block
+  constexpr int KS = KB + 8;                  // LDS row stride (A tile and skinny block)
+  constexpr int CPR = KB / 8;                 // 16-byte chunks per row of a block
+  constexpr int ACH = BR * CPR / 256;         // A chunks per thread per block
+  constexpr int XTOT = LP * CPR;              // skinny chunks per block
+  constexpr int XCH = (XTOT + 255) / 256;     // ... per thread
+  constexpr int NJ = KB / 32;                 // MFMA steps per block
+  static_assert(ACH * 256 == BR * CPR && 256 % CPR == 0, "A tile must split evenly over the workgroup");
+  __shared__ __attribute__((aligned(16))) uint16_t As[BR * KS];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[LP * KS];
   __shared__ double red[4];
   const int nb = tiles * nsplit;
   const int v = xcd_remap_b((int)blockIdx.x, nb);
@@ -169,110 +177,106 @@ k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
   const int g = l / kTile, li = l % kTile;
   const int64_t k0 = (int64_t)s * kchunk;
   const int64_t k1 = min(K, k0 + kchunk);
-  const int64_t base = (int64_t)tile * (64 * RW);
+  const int64_t base = (int64_t)tile * BR;
 
-  f32x4 acc[RW][CT];
+  f32x4 acc[RT][CT];
 #pragma unroll
-  for (int rt = 0; rt < RW; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0, 0, 0, 0};
   double nrm = 0.0;
 
-  auto load_a = [&](Frag (&a)[RW], int64_t kb) {
-    const int64_t kk = kb + 8 * g;
+  // chunk q of a block: row q / CPR, contraction 8 (q % CPR) .. + 7. As 256
+  // is a multiple of CPR, a thread's chunks all cover the same 8 columns, so
+  // FP16 column exponents are loaded once per block, with the block.
+  u32x4_t ar[ACH], xr[XCH];
+  int evn[8];
+  auto load_block = [&](int64_t kb) {
+    if constexpr (NRM && FMT == kFmtF16) load_exp8(cexp, kb + 8 * (threadIdx.x % CPR), k1, evn);
 #pragma unroll
-    for (int rt = 0; rt < RW; ++rt) {
-      const int64_t row = base + (int64_t)(w * RW + rt) * kTile + li;
+    for (int i = 0; i < ACH; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      const int64_t row = base + q / CPR, kk = kb + 8 * (q % CPR);
       const bool in = row < OUT && kk < k1;
       if (vec_ok)  // rows 16-byte aligned and K % 8 == 0: whole chunks or none
-        a[rt].w = in ? load16_nt(A + row * lda + kk) : u32x4_t{0, 0, 0, 0};
+        ar[i] = in ? load16_nt(A + row * lda + kk) : u32x4_t{0, 0, 0, 0};
       else
-        a[rt].w = in ? load8_slow(A + row * lda + kk, (int)min<int64_t>(8, k1 - kk)) : u32x4_t{0, 0, 0, 0};
+        ar[i] = in ? load8_slow(A + row * lda + kk, (int)min<int64_t>(8, k1 - kk)) : u32x4_t{0, 0, 0, 0};
     }
-  };
-  // chunk q of a block: skinny row c = q / (KB / 8), values 8 (q % (KB / 8)) .. + 7
-  // (XT is zero-padded to ldx >= round_up(K, 128) + 128, so whole blocks are in bounds)
-  u32x4_t xr[XCH];
-  auto load_x = [&](int64_t kb) {
+    // XT is zero-padded to ldx >= round_up(K, 128) + 128: whole blocks are in bounds
 #pragma unroll
     for (int i = 0; i < XCH; ++i) {
       const int q = threadIdx.x + 256 * i;
-      const int c = q / (KB / 8), o = 8 * (q % (KB / 8));
-      xr[i] = *reinterpret_cast<const u32x4_t*>(XT + (int64_t)c * ldx + kb + o);
-    }
-  };
-  auto store_x = [&](int b) {
-#pragma unroll
-    for (int i = 0; i < XCH; ++i) {
-      const int q = threadIdx.x + 256 * i;
-      const int c = q / (KB / 8), o = 8 * (q % (KB / 8));
-      *reinterpret_cast<u32x4_t*>(&Xs[b][c * XS + o]) = xr[i];
+      if (q < XTOT) xr[i] = *reinterpret_cast<const u32x4_t*>(XT + (int64_t)(q / CPR) * ldx + kb + 8 * (q % CPR));
     }
   };
 
-  Frag ab[D][RW];
-  if (k0 < k1) {
-    load_x(k0);
-    store_x(0);
-#pragma unroll
-    for (int d = 0; d < D - 1; ++d) load_a(ab[d], k0 + (int64_t)d * KS32);
-    if (k0 + KB < k1) load_x(k0 + KB);
-  }
-  __syncthreads();
-  int buf = 0;
+  if (k0 < k1) load_block(k0);
   for (int64_t kb = k0; kb < k1; kb += KB) {
+    __syncthreads();  // the previous block's operands have been read
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const int64_t knext = kb + (int64_t)(j + D - 1) * KS32;
-      if (knext < k1) load_a(ab[(j + D - 1) % D], knext);
-      if (kb + (int64_t)j * KS32 < k1) {
-        if constexpr (NRM) {
-          if constexpr (FMT == kFmtBF16) {
+    for (int i = 0; i < ACH; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      *reinterpret_cast<u32x4_t*>(As + (q / CPR) * KS + 8 * (q % CPR)) = ar[i];
+    }
 #pragma unroll
-            for (int rt = 0; rt < RW; ++rt) {
-              float q = 0.f;  // 8 squares of BF16 values (exact in FP32): a short FP32 sum, then FP64
+    for (int i = 0; i < XCH; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      if (q < XTOT) *reinterpret_cast<u32x4_t*>(Xs + (q / CPR) * KS + 8 * (q % CPR)) = xr[i];
+    }
+    [[maybe_unused]] int ev[8];
+    if constexpr (NRM && FMT == kFmtF16)
 #pragma unroll
-              for (int t = 0; t < 8; ++t) {
-                const float x = bf16_to_f32(ab[j][rt].h[t]);
-                q += x * x;
-              }
-              nrm += (double)q;
-            }
-          } else {
-            // squares of FP16 values are exact in FP64, and so is the weight
-            // 4^-e_j: with or without column exponents the same sum results
-            int ev[8];
-            load_exp8(cexp, kb + (int64_t)j * KS32 + 8 * g, k1, ev);
+      for (int t = 0; t < 8; ++t) ev[t] = evn[t];
+    __syncthreads();
+    if (kb + KB < k1) load_block(kb + KB);
+    // the sum of squares of this thread's chunks, read back from LDS while
+    // the next block's loads are in flight
+    if constexpr (NRM) {
 #pragma unroll
-            for (int rt = 0; rt < RW; ++rt)
+      for (int i = 0; i < ACH; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        Frag f;
+        f.w = *reinterpret_cast<const u32x4_t*>(As + (q / CPR) * KS + 8 * (q % CPR));
+        if constexpr (FMT == kFmtBF16) {
+          float qs = 0.f;  // 8 squares of BF16 values (exact in FP32): a short FP32 sum, then FP64
 #pragma unroll
-              for (int t = 0; t < 8; ++t) {
-                const double x = (double)h16_to_f32<FMT>(ab[j][rt].h[t]);
-                nrm += ldexp(x * x, -2 * ev[t]);
-              }
+          for (int t = 0; t < 8; ++t) {
+            const float x = bf16_to_f32(f.h[t]);
+            qs += x * x;
+          }
+          nrm += (double)qs;
+        } else {
+          // squares of FP16 values are exact in FP64, and so is the weight
+          // 4^-e_j: with or without column exponents the same sum results
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const double x = (double)h16_to_f32<FMT>(f.h[t]);
+            nrm += ldexp(x * x, -2 * ev[t]);
           }
         }
-        Frag bx[CT];
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-          bx[ct].w = *reinterpret_cast<const u32x4_t*>(&Xs[buf][(ct * kTile + li) * XS + KS32 * j + 8 * g]);
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-          for (int rt = 0; rt < RW; ++rt) acc[rt][ct] = mfma16<FMT>(ab[j][rt], bx[ct], acc[rt][ct]);
       }
     }
-    // the other buffer was last read in the previous block, which every wave
-    // finished before the barrier that ended it
-    if (kb + KB < k1) store_x(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-    if (kb + 2 * KB < k1) load_x(kb + 2 * KB);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      Frag af[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        af[rt].w = *reinterpret_cast<const u32x4_t*>(As + ((w * RT + rt) * kTile + li) * KS + 32 * j + 8 * g);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        Frag bx;
+        bx.w = *reinterpret_cast<const u32x4_t*>(Xs + (ct * kTile + li) * KS + 32 * j + 8 * g);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = mfma16<FMT>(af[rt], bx, acc[rt][ct]);
+      }
+    }
   }
 
-  store_tiles<FMT, false, RW, CT>(acc, base, w, g, li, OUT, s, P, Tout, fold, sc, cexp);
+  store_tiles<FMT, false, RT, CT>(acc, base, w, g, li, OUT, s, P, Tout, fold, sc, cexp);
   if constexpr (NRM) {
     nrm = wave_sum(nrm);
+    __syncthreads();
     if (l == 0) red[w] = nrm;
     __syncthreads();
     if (threadIdx.x == 0) normp[v] = (red[0] + red[1]) + (red[2] + red[3]);
@@ -403,7 +407,7 @@ inline hipError_t launch_h16_rt(bool trans, const uint16_t* A, int64_t lda, int6
     if (trans)                                                                                     \
       hipLaunchKernelGGL((k_h16_tn<FMT, RT, C, KST>), grid, block, 0, st, A, lda, OUT, K, XT, ldx, \
                          kchunk, tiles, nsplit, vec_ok, P, To, sc, cexp);                          \
-    else if (kchunk % nn_kb<C>() != 0)                                                             \
+    else if (kchunk % nn_kb(RT, C * kTile) != 0)                                                   \
       return hipErrorInvalidValue;                                                                 \
     else if (normp)                                                                                \
       hipLaunchKernelGGL((k_h16_nn<FMT, RT, C, true>), grid, block, 0, st, A, lda, OUT, K, XT,     \

@@ -61,7 +61,7 @@ hipError_t launch_h16_pass(int fmt, bool trans, const uint16_t* A, int64_t lda, 
                            double* normp, double* Tout, int fold, int rt, const H16Scale* sc, const int* cexp,
                            hipStream_t st);
 int h16_slots(int fmt, bool trans, int rt, int LP);
-int bf16_step(bool trans, int rt);
+int bf16_step(bool trans, int rt, int LP);
 hipError_t launch_cast_h16_t(int fmt, const double* Q, int64_t rows, int LP, int64_t ldt, int permute,
                              int with_lo, uint16_t* QT, const H16Scale* sc, const int* cexp, hipStream_t st);
 hipError_t launch_reduce_fold(const float* P, int64_t OUT, int LP2, int nsplit, double* out,
@@ -228,22 +228,27 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   const int forced = o ? o->split : 0;
   const int ks = skinny_step(a_type == SORSVD_DIAG ? SORSVD_F64 : a_type);
   const int acc = (a_type == SORSVD_F64 || a_type == SORSVD_DIAG) ? 8 : 4;
-  // 16-bit tiles: wide workgroups amortise the re-read of the skinny operand
-  // (an opts override serves tuning sweeps)
+  // 16-bit tiles (an opts override serves tuning sweeps). A X: 128 rows per
+  // workgroup balances the row run each load reads against the re-read of
+  // the skinny block (measured at 200000 x 4000: 4.1 TB/s at 128 rows, 3.8 at
+  // 256, and the same order for the 2l-column refinement pass). A^T Y: 256
+  // columns when l <= 64.
   const int tile_opt = o ? o->tile : 0;
-  p->rt_nn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
+  p->rt_nn = tile_opt ? tile_opt : 2;
   p->rt_tn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
-  p->rt_proj = tile_opt ? std::min(tile_opt, p->refine && LP > 32 ? 2 : 4) : (p->refine ? (LP <= 32 ? 4 : 2) : p->rt_nn);
+  p->rt_proj = tile_opt ? std::min(tile_opt, p->refine && LP > 32 ? 2 : 4) : 2;
   const int t64 = a_type == SORSVD_DIAG ? SORSVD_F64 : a_type;
   const int rpb_m = h16 ? 64 * p->rt_nn : skinny_rows_per_block(t64, m);
   const int rpb_n = h16 ? 64 * p->rt_tn : skinny_rows_per_block(t64, n);
-  const int ks_nn = h16 ? bf16_step(false, p->rt_nn) : ks;
-  const int ks_tn = h16 ? bf16_step(true, p->rt_tn) : ks;
+  const int ks_nn = h16 ? bf16_step(false, p->rt_nn, (int)LP) : ks;
+  const int ks_tn = h16 ? bf16_step(true, p->rt_tn, (int)LP) : ks;
   const bool skinny_pass = a_type == SORSVD_F32 || a_type == SORSVD_F64;
   const int tcode = a_type == SORSVD_F32 ? 1 : 0;
-  p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced, 8, 8,
-                       skinny_pass ? skinny_slots(tcode, false, (int)LP)
-                                   : (h16 ? h16_slots(p->fmt, false, p->rt_nn, (int)LP) : 0));
+  // 16-bit passes aim at one wave of resident workgroups (see A^T Y below)
+  const int nn_slots = skinny_pass ? skinny_slots(tcode, false, (int)LP)
+                                   : (h16 ? h16_slots(p->fmt, false, p->rt_nn, (int)LP) : 0);
+  p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced, 8, 8, nn_slots,
+                       (h16 && nn_slots > 0) ? nn_slots : 2048);
   // 16-bit A^T Y: a workgroup streams 64 rt whole columns of A with its
   // contraction rows staged through LDS, so one wave of resident workgroups
   // already keeps HBM busy; more splits only add partial sums to write and
@@ -254,8 +259,9 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced, 8, 8, tn_slots,
                        (h16 && tn_slots > 0) ? tn_slots : 2048);
   const int LPproj = (int)LP * (p->refine ? 2 : 1);
-  p->projb = choose_split(m, n, 64 * p->rt_proj, 128, LPproj, p->es, acc, forced, 8, 8,
-                          h16 ? h16_slots(p->fmt, false, p->rt_proj, LPproj) : 0);
+  const int proj_slots = h16 ? h16_slots(p->fmt, false, p->rt_proj, LPproj) : 0;
+  p->projb = choose_split(m, n, 64 * p->rt_proj, h16 ? bf16_step(false, p->rt_proj, LPproj) : 128, LPproj, p->es,
+                          acc, forced, 8, 8, proj_slots, proj_slots > 0 ? proj_slots : 2048);
   // l x l products over a tall FP64 operand: many short splits (the partial
   // sums are small next to the operand)
   const int ks64 = skinny_step(SORSVD_F64);
