@@ -23,8 +23,9 @@ int h16_blocks_f16(bool trans, int rt, int CT);
 // QT[LP + c][.] = h16(Q' - hi) (the refinement split). With sc, row r is
 // scaled first, Q' = Q 2^s_r: s_r = tn_base for a TN operand (`permute`),
 // nn_base - e_r for an NN operand (rows of an NN operand are columns of A).
-// Rows rows..ldt-1 are written as zeros. Tiles of 64 rows go through LDS so
-// that both the reads of Q and the writes of QT are coalesced.
+// Rows rows..ldt-1 are written as zeros. A workgroup stages 64 rows in LDS
+// (coalesced reads of Q); each thread then forms 8 consecutive positions of
+// one output row (8 gathered tile rows) and writes them as one 16-byte store.
 template <int FMT>
 __global__ void __launch_bounds__(256)
 k_cast_h16_t(const double* __restrict__ Q, int64_t rows, int LP, int64_t ldt, int permute,
@@ -44,20 +45,31 @@ k_cast_h16_t(const double* __restrict__ Q, int64_t rows, int LP, int64_t ldt, in
   }
   __syncthreads();
   const int parts = with_lo ? 2 : 1;
-  for (int i = threadIdx.x; i < 64 * LP * parts; i += 256) {
-    const int rr = i % 64, cp = i / 64;
+  // item: (output row cp = part LP + c, group u of 8 positions); 8 consecutive
+  // threads cover 64 consecutive positions of one output row
+  for (int it = threadIdx.x; it < parts * LP * 8; it += 256) {
+    const int u = it % 8, cp = it / 8;
     const int c = cp % LP, part = cp / LP;
-    const int64_t r = r0 + rr;
-    if (r >= ldt) continue;
-    const double q = tile[rr][c];
-    const uint16_t hi = f64_to_h16<FMT>(q);
-    const uint16_t val = part == 0 ? hi : f64_to_h16<FMT>(q - (double)h16_to_f32<FMT>(hi));
-    int64_t pos = r;
-    if (permute) {  // row 32 J + 4 t + g -> position 32 J + 8 g + t
-      const int64_t J = r / 32, within = r % 32;
-      pos = 32 * J + 8 * (within % 4) + within / 4;
+    const int64_t pos0 = r0 + 8 * u;
+    if (pos0 >= ldt) continue;  // ldt is a multiple of 64
+    uint32_t wv[4];
+#pragma unroll
+    for (int t2 = 0; t2 < 4; ++t2) {
+      uint32_t pair = 0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = 2 * t2 + h;
+        // position 32 J + 8 g + t holds row 32 J + 4 t + g when permuted
+        const int pr = 8 * u + t;
+        const int rr = permute ? (pr / 32) * 32 + 4 * t + (pr % 32) / 8 : pr;
+        const double q = tile[rr][c];
+        const uint16_t hi = f64_to_h16<FMT>(q);
+        const uint16_t val = part == 0 ? hi : f64_to_h16<FMT>(q - (double)h16_to_f32<FMT>(hi));
+        pair |= (uint32_t)val << (16 * h);
+      }
+      wv[t2] = pair;
     }
-    QT[((int64_t)part * LP + c) * ldt + pos] = val;
+    *reinterpret_cast<u32x4_t*>(QT + ((int64_t)part * LP + c) * ldt + pos0) = u32x4_t{wv[0], wv[1], wv[2], wv[3]};
   }
 }
 
