@@ -23,17 +23,21 @@ int h16_blocks_f16(bool trans, int rt, int CT);
 // QT[LP + c][.] = h16(Q' - hi) (the refinement split). With sc, row r is
 // scaled first, Q' = Q 2^s_r: s_r = tn_base for a TN operand (`permute`),
 // nn_base - e_r for an NN operand (rows of an NN operand are columns of A).
-// Rows rows..ldt-1 are written as zeros. A workgroup stages 64 rows in LDS
-// (coalesced reads of Q); each thread then forms 8 consecutive positions of
-// one output row (8 gathered tile rows) and writes them as one 16-byte store.
+// Rows rows..ldt-1 are written as zeros. A workgroup stages kCastRows rows in
+// LDS (coalesced reads of Q); each thread then forms 8 consecutive positions
+// of one output row (8 gathered tile rows) and writes them as one 16-byte
+// store. 32-row tiles (33 KB of LDS) let four workgroups share a CU; the TN
+// permutation stays within aligned groups of 32 rows.
+constexpr int kCastRows = 32;
+
 template <int FMT>
 __global__ void __launch_bounds__(256)
 k_cast_h16_t(const double* __restrict__ Q, int64_t rows, int LP, int64_t ldt, int permute,
              int with_lo, uint16_t* __restrict__ QT, const H16Scale* __restrict__ sc,
              const int* __restrict__ cexp) {
-  __shared__ double tile[64][129];
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  for (int i = threadIdx.x; i < 64 * LP; i += 256) {
+  __shared__ double tile[kCastRows][129];
+  const int64_t r0 = (int64_t)blockIdx.x * kCastRows;
+  for (int i = threadIdx.x; i < kCastRows * LP; i += 256) {
     const int rr = i / LP, c = i % LP;
     const int64_t r = r0 + rr;
     double v = 0.0;
@@ -45,13 +49,14 @@ k_cast_h16_t(const double* __restrict__ Q, int64_t rows, int LP, int64_t ldt, in
   }
   __syncthreads();
   const int parts = with_lo ? 2 : 1;
-  // item: (output row cp = part LP + c, group u of 8 positions); 8 consecutive
-  // threads cover 64 consecutive positions of one output row
-  for (int it = threadIdx.x; it < parts * LP * 8; it += 256) {
-    const int u = it % 8, cp = it / 8;
+  // item: (output row cp = part LP + c, group u of 8 positions); consecutive
+  // threads cover consecutive positions of one output row
+  constexpr int NU = kCastRows / 8;
+  for (int it = threadIdx.x; it < parts * LP * NU; it += 256) {
+    const int u = it % NU, cp = it / NU;
     const int c = cp % LP, part = cp / LP;
     const int64_t pos0 = r0 + 8 * u;
-    if (pos0 >= ldt) continue;  // ldt is a multiple of 64
+    if (pos0 >= ldt) continue;  // ldt is a multiple of kCastRows
     uint32_t wv[4];
 #pragma unroll
     for (int t2 = 0; t2 < 4; ++t2) {
@@ -220,7 +225,8 @@ int bf16_step(bool trans, int rt, int LP) { return trans ? (rt >= 4 ? 64 : 128) 
 
 hipError_t launch_cast_h16_t(int fmt, const double* Q, int64_t rows, int LP, int64_t ldt, int permute,
                              int with_lo, uint16_t* QT, const H16Scale* sc, const int* cexp, hipStream_t st) {
-  const int64_t blocks = ceil_div(ldt, 64);
+  if (ldt % kCastRows) return hipErrorInvalidValue;
+  const int64_t blocks = ceil_div(ldt, kCastRows);
   if (blocks == 0) return hipSuccess;
   if (fmt == kFmtBF16)
     hipLaunchKernelGGL(k_cast_h16_t<kFmtBF16>, dim3((unsigned)blocks), dim3(256), 0, st, Q, rows, LP, ldt, permute,
