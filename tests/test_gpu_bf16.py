@@ -92,7 +92,8 @@ def test_bf16_projection_with_hi_lo_split(lib):
     assert err < 2.0**-14, err
 
 
-@pytest.mark.parametrize("m,n,k,q", [(3000, 1200, 64, 1), (1500, 2500, 32, 2), (1000, 333, 20, 0)])
+@pytest.mark.parametrize("m,n,k,q", [(3000, 1200, 64, 1), (1500, 2500, 32, 2), (1000, 333, 20, 0),
+                                     (2500, 1300, 128, 1)])
 def test_bf16_whole_method(lib, m, n, k, q):
     sigma = 0.9 ** np.arange(1, min(m, n) + 1)
     A, _, _ = W.spectral(m, n, sigma, 4)
