@@ -69,6 +69,22 @@ def test_f16_sketch_and_orbit(lib, m, n, l):
     assert np.abs(T2 - ref2).max() <= tol2
 
 
+def test_f16_unaligned_leading_dimension(lib):
+    """Rows that are not 16-byte aligned and a contraction that is not a
+    multiple of 8 take the kernels' element-wise load path."""
+    gen = W.rng(10)
+    big = to_f16(gen.standard_normal((300, 203)))
+    A = big[:, :197]
+    Ad = dev_f16(big)[:, :197]
+    assert Ad.stride(0) == 203
+    X = gen.standard_normal((197, 16))
+    Y = gen.standard_normal((300, 16))
+    T = host(lib.step_sketch(Ad, torch.as_tensor(X).cuda()))
+    assert np.abs(T - A @ operand(X)).max() < 1e-4
+    T2 = host(lib.step_orbit(Ad, torch.as_tensor(Y).cuda()))
+    assert np.abs(T2 - A.T @ operand(Y)).max() < 1e-4
+
+
 def test_f16_projection_with_hi_lo_split(lib):
     gen = W.rng(22)
     A = to_f16(gen.standard_normal((900, 700)))
