@@ -15,12 +15,14 @@
 // operand fragment is one 16-byte LDS read or global load:
 //   * skinny operands are stored TRANSPOSED in HBM (LP rows of length K),
 //     written that way by the library's own cast kernels;
-//   * NN (T = A X): lane l takes row l % 16 of A and 8 consecutive
-//     contraction indices starting at 8 * (l / 16) per step of 32 (a 16-byte
-//     load straight from HBM into registers), and the matching 16 bytes of
-//     the transposed skinny operand from L2; no LDS, no barriers;
+//   * NN (T = A X): a tile of 64 RT rows x KB contraction indices of A and
+//     the matching LP x KB block of the skinny operand are staged in LDS
+//     (row runs of 2 KB bytes per load); lane l then reads row l % 16 of a
+//     16-row tile and 8 consecutive contraction indices starting at
+//     8 * (l / 16) of each step of 32 as one 16-byte LDS read, and the same
+//     indices of a skinny column as another;
 //   * TN (T = A^T Y): the contraction runs over rows of A, so a tile of
-//     128 rows x (64 RT) columns of A is staged in LDS row-major (coalesced
+//     KST rows x (64 RT) columns of A is staged in LDS row-major (coalesced
 //     16-byte loads and writes) and each lane gathers its 8 rows with
 //     16-bit LDS reads. Inside every block of 32 contraction indices the
 //     k-slot of lane group g, element t is row 4 t + g: the four lane groups
@@ -37,7 +39,6 @@
 #include "half16.hpp"
 
 namespace sor {
-
 
 __device__ inline int xcd_remap_b(int b, int nb) {
   return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
