@@ -16,9 +16,130 @@ template <bool V_LDS, bool WANT_V, int NRB>
 __global__ void __launch_bounds__(kJacThreads)
 k_jacobi(const double* __restrict__ Min, int LP, int l, int k, int max_sweeps, double tol2,
          double* __restrict__ Ut, double* __restrict__ sv, double* __restrict__ Vt, int ldk,
-         double* __restrict__ Vg, DevInfo* __restrict__ info) {
+         double* __restrict__ Vg, DevInfo* __restrict__ info, double2* __restrict__ rlog,
+         int* __restrict__ vperm) {
   extern __shared__ double sm[];
-  jacobi_body<V_LDS, WANT_V, NRB>(Min, 1, 0, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, info, sm);
+  jacobi_body<V_LDS, WANT_V, NRB>(Min, 1, 0, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, info, sm, rlog,
+                                  vperm);
+}
+
+// V of the core SVD from the rotation log of jacobi_body (rlog, vperm): row r
+// of V starts as e_r and receives, step by step, the rotations of that step's
+// disjoint column pairs, (v_p, v_q) <- (c v_p - s v_q, s v_p + c v_q), p < q:
+// the sequence the columns of M received. Then Vt[r][j] = V[r][vperm[j]].
+// A wave owns one row, held in registers in round-robin position order: lane
+// pr holds positions pr and lp - 1 - pr, which are exactly the pair it
+// rotates at every step. Between steps position 0 stays and the others move
+// one place along the ring (the player at position x + 1 comes to x, the one
+// at 1 to lp - 1): one DPP wave shift per operand. After whole sweeps
+// positions and columns coincide again. The waves of a workgroup share the
+// coefficients, staged through LDS kVapChunk steps at a time: the next chunk
+// is loaded into registers while the current one is applied.
+constexpr int kVapWaves = 4;
+constexpr int kVapChunk = 32;
+constexpr int kVapLoads = kVapChunk * kWave / (kWave * kVapWaves);
+constexpr int kVapGroup = 8;
+
+// Whole-wave shifts by one lane (DPP wave_shl:1 / wave_shr:1): lane i
+// receives v of lane i + 1, resp. i - 1; the lane with no source keeps v.
+template <int CTRL> __device__ inline double wave_shift(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  const uint32_t slo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const uint32_t shi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)shi << 32) | slo));
+}
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+
+__global__ void __launch_bounds__(64 * kVapWaves)
+k_jacobi_vapply(const double2* __restrict__ rlog, const int* __restrict__ vperm, const DevInfo* __restrict__ info,
+                int l, int k, int max_sweeps, double* __restrict__ Vt, int ldk) {
+  __shared__ double2 cbuf[2][kVapChunk * kWave];
+  __shared__ double rows[kVapWaves][128];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int r = blockIdx.x * kVapWaves + w;
+  const int lp = (l + 1) & ~1, npairs = lp / 2, steps = lp - 1;
+  const int sweeps = min(info->sweeps, max_sweeps);
+  const int64_t T = (int64_t)sweeps * steps;
+  const bool act = lane < npairs;
+  double a = (act && r == lane) ? 1.0 : 0.0;            // position lane
+  double b = (act && r == lp - 1 - lane) ? 1.0 : 0.0;   // position lp - 1 - lane
+  if (T > 0) {  // uniform
+    // chunk entry e = s * kWave + pr: coefficients of pair pr at step t0 + s.
+    // Addresses are clamped so that every load is unconditional (entries past
+    // the log, and those of lanes beyond the pairs, are never used: a lane
+    // past the pairs never passes its registers to a lane of a pair)
+    const int64_t tlast = T - 1;
+    auto load_entry = [&](int64_t t0, int j) {
+      const int e = threadIdx.x + j * 64 * kVapWaves;
+      return rlog[min(t0 + e / kWave, tlast) * npairs + min(e % kWave, npairs - 1)];
+    };
+    int step = 0;
+    auto apply = [&](const double2 cs) {
+      // columns at this lane's positions (position 0 holds column 0)
+      int pa = 0;
+      if (lane > 0) {
+        pa = lane - 1 + step;
+        pa = 1 + (pa >= steps ? pa - steps : pa);
+      }
+      int pb = lp - 2 - lane + step;
+      pb = 1 + (pb >= steps ? pb - steps : pb);
+      const double c = cs.x, s = pa < pb ? cs.y : -cs.y;
+      const double x = a, y = b;
+      a = c * x - s * y;
+      b = s * x + c * y;
+      const double from_up = wave_shift<kDppWaveShl1>(a), from_down = wave_shift<kDppWaveShr1>(b);
+      const double na = lane == 0 ? a : (lane == npairs - 1 ? b : from_up);
+      const double nb = lane == 0 ? (npairs == 1 ? b : from_up) : from_down;
+      a = na;
+      b = nb;
+      if (++step == steps) step = 0;
+    };
+#pragma unroll
+    for (int j = 0; j < kVapLoads; ++j) cbuf[0][threadIdx.x + j * 64 * kVapWaves] = load_entry(0, j);
+    __syncthreads();
+    const int64_t nch = ceil_div(T, (int64_t)kVapChunk);
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      const int buf = (int)(ch & 1);
+      // the next chunk is loaded even after the last one (clamped, unused) so
+      // that the loads need no branch
+      double2 st[kVapLoads];
+#pragma unroll
+      for (int j = 0; j < kVapLoads; ++j) st[j] = load_entry((ch + 1) * kVapChunk, j);
+      const double2* cb = cbuf[buf] + lane;
+      if ((ch + 1) * kVapChunk <= T) {
+        // coefficients read from LDS a group of kVapGroup steps ahead of use
+        double2 cw[kVapGroup];
+#pragma unroll
+        for (int s = 0; s < kVapGroup; ++s) cw[s] = cb[s * kWave];
+#pragma unroll
+        for (int g = 0; g < kVapChunk; g += kVapGroup) {
+          double2 nx[kVapGroup];
+#pragma unroll
+          for (int s = 0; s < kVapGroup; ++s)
+            if (g + kVapGroup < kVapChunk) nx[s] = cb[(g + kVapGroup + s) * kWave];
+#pragma unroll
+          for (int s = 0; s < kVapGroup; ++s) apply(cw[s]);
+#pragma unroll
+          for (int s = 0; s < kVapGroup; ++s) cw[s] = nx[s];
+        }
+      } else {
+        const int ns = (int)(T - ch * kVapChunk);
+        for (int s = 0; s < ns; ++s) apply(cb[s * kWave]);
+      }
+#pragma unroll
+      for (int j = 0; j < kVapLoads; ++j) cbuf[buf ^ 1][threadIdx.x + j * 64 * kVapWaves] = st[j];
+      __syncthreads();
+    }
+  }
+  double* R = rows[w];
+  if (act) {
+    R[lane] = a;
+    R[lp - 1 - lane] = b;
+  }
+  __syncthreads();
+  if (r < l)
+    for (int j = lane; j < k; j += kWave) Vt[r * ldk + j] = R[vperm[j]];
 }
 
 // ---------------------------------------------------------------------------
@@ -165,11 +286,11 @@ hipError_t launch_chol_inv(const double* G, int LP, int l, int64_t rows, int mod
 template <bool V_LDS, bool WANT_V>
 static void launch_jacobi_nrb(int nrb, size_t shm, hipStream_t st, const double* M, int LP, int l, int k,
                               int max_sweeps, double tol2, double* Ut, double* sv, double* Vt, int ldk,
-                              double* Vg, DevInfo* info) {
+                              double* Vg, DevInfo* info, double2* rlog = nullptr, int* vperm = nullptr) {
 #define SOR_JAC(R)                                                                                       \
   case R:                                                                                                \
     hipLaunchKernelGGL((k_jacobi<V_LDS, WANT_V, R>), dim3(1), dim3(kJacThreads), shm, st, M, LP, l, k,  \
-                       max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, info);                                     \
+                       max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, info, rlog, vperm);                        \
     break;
   switch (nrb) {
     SOR_JAC(1) SOR_JAC(2) SOR_JAC(4) SOR_JAC(6) SOR_JAC(8) SOR_JAC(10) SOR_JAC(13) SOR_JAC(16)
@@ -178,16 +299,46 @@ static void launch_jacobi_nrb(int nrb, size_t shm, hipStream_t st, const double*
 #undef SOR_JAC
 }
 
-// tol <= 0 selects the default orthogonality threshold sqrt(l) 2^-52.
+// Bytes of the rotation log of a core SVD of width l with up to max_sweeps
+// sweeps, plus the permutation (see jacobi_body).
+size_t jacobi_log_bytes(int l, int max_sweeps) {
+  const int lp = (l + 1) & ~1;
+  return (size_t)max_sweeps * (lp - 1) * (lp / 2) * sizeof(double2) + 128 * sizeof(int);
+}
+
+// Whether the core SVD of width l rebuilds V from the rotation log: for
+// widths above 32, where moving V through LDS at every step of the Jacobi
+// kernel costs more than the replay (l = 100: 1.55 ms for the Jacobi kernel
+// with V, 0.96 ms without it plus 0.07 ms of replay; l = 64: 0.47 ms with V,
+// 0.39 ms without).
+bool jacobi_uses_log(int l) { return l > 32; }
+
+// tol <= 0 selects the default orthogonality threshold sqrt(l) 2^-52. rlog:
+// jacobi_log_bytes(l, max_sweeps) bytes of scratch, or null (V kept in the
+// Jacobi kernel).
 hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, double* Ut,
                          double* sv, double* Vt, int ldk, double* Vg, void* info, hipStream_t st,
-                         bool want_v, double tol) {
+                         bool want_v, double tol, void* rlog) {
   if (l < 1 || l > 128) return hipErrorInvalidValue;
-  bool v_lds = false;
-  const size_t shm = jacobi_lds(l, want_v, &v_lds);
   const double tol2 = tol > 0.0 ? tol * tol : (double)l * 0x1p-104;
   const int nrb = jac_nrb(l);
   DevInfo* di = (DevInfo*)info;
+  if (want_v && rlog && jacobi_uses_log(l)) {
+    bool v_lds = false;
+    const size_t shm = jacobi_lds(l, false, &v_lds);
+    const int lp = (l + 1) & ~1;
+    double2* lg = reinterpret_cast<double2*>(rlog);
+    int* perm = reinterpret_cast<int*>(lg + (size_t)max_sweeps * (lp - 1) * (lp / 2));
+    launch_jacobi_nrb<false, false>(nrb, shm, st, M, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, di, lg, perm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int blocks = (int)ceil_div(l, kVapWaves);
+    hipLaunchKernelGGL(k_jacobi_vapply, dim3(blocks), dim3(64 * kVapWaves), 0, st, lg, perm, di, l, k, max_sweeps,
+                       Vt, ldk);
+    return hipGetLastError();
+  }
+  bool v_lds = false;
+  const size_t shm = jacobi_lds(l, want_v, &v_lds);
   if (!want_v)
     launch_jacobi_nrb<false, false>(nrb, shm, st, M, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, di);
   else if (v_lds)

@@ -292,11 +292,21 @@ __host__ __device__ inline size_t jacobi_lds(int l, bool want_v, bool* v_lds) {
 
 // Min is given as nparts partial sums (stride pstride elements), added in
 // order. tol2 = tol^2 (the main path takes tol = sqrt(l) 2^-52).
+//
+// rlog != null (with WANT_V false): V is not kept here. Instead the (c, s)
+// of every pair of every step is written to rlog (double2, (1, 0) where the
+// pair was not rotated; entry (sweep (lp - 1) + step) npairs + pr), and the
+// column of rank j < k to vperm[j]: every row of V receives the same
+// sequence of column rotations, so k_jacobi_vapply rebuilds V afterwards, one
+// row per wave and many rows at once, instead of moving V through this one
+// CU's LDS at every step (which doubles its LDS traffic). rlog holds
+// max_sweeps (lp - 1) npairs entries.
 template <bool V_LDS, bool WANT_V, int NRB>
 __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, int64_t pstride, int LP,
                                    int l, int k, int max_sweeps, double tol2, double* __restrict__ Ut,
                                    double* __restrict__ sv, double* __restrict__ Vt, int ldk,
-                                   double* __restrict__ Vg, DevInfo* __restrict__ info, double* sm) {
+                                   double* __restrict__ Vg, DevInfo* __restrict__ info, double* sm,
+                                   double2* __restrict__ rlog = nullptr, int* __restrict__ vperm = nullptr) {
   static_assert(WANT_V || !V_LDS, "V in LDS only when wanted");
   constexpr int ldm = 8 * NRB;
   const bool vtail = V_LDS && !jac_vpad_fits(l);  // V columns unpadded (stride l)
@@ -340,8 +350,13 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
           if (x >= lp - 1) x -= lp - 1;
           return 1 + x;
         };
+        double2* lg = (!WANT_V && rlog && gl == 0)
+                          ? rlog + ((size_t)sweep * (lp - 1) + step) * npairs + pr : nullptr;
         int p = player(pr), q = player(lp - 1 - pr);
-        if (p >= l || q >= l) continue;
+        if (p >= l || q >= l) {
+          if (lg) *lg = double2{1.0, 0.0};
+          continue;
+        }
         if (p > q) { int t = p; p = q; q = t; }
         double* mp = Mc + p * ldm + gl;
         double* mq = Mc + q * ldm + gl;
@@ -352,7 +367,10 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
 #pragma unroll
         for (int i = 0; i < NRB; ++i) { al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i]; }
         al = sum8(al); be = sum8(be); ga = sum8(ga);
-        if (!(ga * ga > tol2 * (al * be))) continue;  // orthogonal enough (or zero column)
+        if (!(ga * ga > tol2 * (al * be))) {  // orthogonal enough (or zero column)
+          if (lg) *lg = double2{1.0, 0.0};
+          continue;
+        }
         // V: the row blocks before the last one are whole; in the last one
         // (registers vxl, vyl) rows past l go to the dummy word when V's
         // columns are not padded
@@ -377,6 +395,7 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t);
         const double s = c * t;
+        if (lg) *lg = double2{c, s};
 #pragma unroll
         for (int i = 0; i < NRB; ++i) {
           mp[8 * i] = c * x[i] - s * y[i];
@@ -424,6 +443,7 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
         if (WANT_V) Vt[r * ldk + rank] = Vc[c * vld + r];
       }
       if (gl == 0) sv[rank] = sc;
+      if (!WANT_V && vperm && gl == 0) vperm[rank] = c;
     }
   }
 }

@@ -85,7 +85,9 @@ hipError_t launch_chol_inv(const double* G, int LP, int l, int64_t rows, int mod
                            int* skip3, void* info, hipStream_t st);
 hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, double* Ut,
                          double* sv, double* Vt, int ldk, double* Vg, void* info, hipStream_t st,
-                         bool want_v = true, double tol = 0.0);
+                         bool want_v = true, double tol = 0.0, void* rlog = nullptr);
+size_t jacobi_log_bytes(int l, int max_sweeps);
+bool jacobi_uses_log(int l);
 hipError_t launch_signfix(const double* U64, int64_t m, const double* V64, int64_t n, int ld, int k,
                           double* pval, int64_t* pidx, int nblocks_max, double* sgn, double* U,
                           int64_t ldu, double* V, int64_t ldv, hipStream_t st);
@@ -187,6 +189,7 @@ struct Plan {
   size_t off_g, off_rinv, off_m, off_ut, off_vt, off_vg, off_pval, off_pidx, off_sgn, off_skip, off_res;
   size_t off_t2p;  // pass_eff: the last orbit product before its QR (n x LP FP64)
   size_t off_hsc;  // FP16 A: the operand scale record (H16Scale)
+  size_t off_rlog; // core SVD: rotation log from which V is rebuilt (0: V kept in the Jacobi kernel)
   size_t total;
 };
 
@@ -306,6 +309,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->off_res = p->residual ? L.take((size_t)2 * residual_parts(m, n) * 8) : 0;
   p->off_t2p = p->pass_eff ? L.take((size_t)n * LP * 8) : 0;
   p->off_hsc = a_type == SORSVD_F16 ? L.take(sizeof(H16Scale)) : 0;
+  p->off_rlog = jacobi_uses_log((int)l) ? L.take(jacobi_log_bytes((int)l, p->max_sweeps)) : 0;
   p->total = L.total;
   return SORSVD_OK;
 }
@@ -537,7 +541,8 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   SORSVD_TRY(launch_fill(Ut, (int64_t)LP * KP, 0.0, st));
   SORSVD_TRY(launch_fill(Vt, (int64_t)LP * KP, 0.0, st));
   SORSVD_TRY(launch_jacobi(M, LP, (int)p.l, (int)p.k, p.max_sweeps, Ut, S, Vt, KP,
-                           at<double>(ws, p.off_vg), info, st));
+                           at<double>(ws, p.off_vg), info, st, true, 0.0,
+                           p.off_rlog ? at<void>(ws, p.off_rlog) : nullptr));
 
   // Lift: U = Q1 U~_k, V = Q2 V~_k (Alg. 3 step 7), then the sign convention.
   double* U64 = at<double>(ws, p.off_u64);
@@ -798,8 +803,11 @@ int sorsvd_step_core_svd(const double* M, int64_t l, int64_t k, double* Ut, doub
   SORSVD_TRY(launch_info_init(at<void>(ws, p.off_info), st));
   SORSVD_TRY(launch_fill(Ut, l * k, 0.0, st));
   SORSVD_TRY(launch_fill(Vt, l * k, 0.0, st));
-  SORSVD_TRY(launch_jacobi(M, (int)l, (int)l, (int)k, max_sweeps > 0 ? max_sweeps : 40, Ut, s, Vt,
-                           (int)k, at<double>(ws, p.off_vg), at<void>(ws, p.off_info), st));
+  const int ms = max_sweeps > 0 ? max_sweeps : 40;
+  // the log in the workspace holds p.max_sweeps sweeps
+  void* rlog = (p.off_rlog && ms <= p.max_sweeps) ? at<void>(ws, p.off_rlog) : nullptr;
+  SORSVD_TRY(launch_jacobi(M, (int)l, (int)l, (int)k, ms, Ut, s, Vt, (int)k, at<double>(ws, p.off_vg),
+                           at<void>(ws, p.off_info), st, true, 0.0, rlog));
   return SORSVD_OK;
 }
 
