@@ -149,6 +149,42 @@ def test_core_svd_against_lapack(lib, l, k):
     assert np.abs(Ut.T @ Ut - np.eye(k)).max() < 1e-12
 
 
+@pytest.mark.parametrize("l", [33, 65, 99, 127])
+def test_core_svd_rotation_log_matches_v_in_kernel(lib, l):
+    """Above width 32 V is rebuilt from the logged rotations; a sweep cap above
+    the one the workspace log holds (40) keeps V in the Jacobi kernel. Both
+    apply the same rotations in the same order to the same start (the
+    identity), so they agree to rounding; odd widths add the padding column."""
+    gen = W.rng(l)
+    Mtx = gen.standard_normal((l, l)) @ np.diag(np.geomspace(1, 1e-3, l)) @ gen.standard_normal((l, l))
+    k = l - 3
+    Ua, sa, Va, ia = lib.step_core_svd(dev(Mtx), k)
+    Ub, sb, Vb, ib = lib.step_core_svd(dev(Mtx), k, max_sweeps=60)
+    assert ia["flags"] == ib["flags"] == 0
+    assert normwise(host(sa), host(sb)) <= 1e-14
+    assert np.abs(host(Ua) - host(Ub)).max() < 1e-11
+    assert np.abs(host(Va) - host(Vb)).max() < 1e-11
+    Vh = host(Va)
+    assert np.abs(Vh.T @ Vh - np.eye(k)).max() < 1e-13
+    # M V = U diag(s)
+    assert np.abs(Mtx @ Vh - host(Ua) * host(sa)[None, :]).max() < 1e-12 * np.abs(host(sa)).max()
+
+
+def test_core_svd_rotation_log_no_rotation_is_a_permutation(lib):
+    """A diagonal M (orthogonal columns) takes no rotation: every logged pair
+    is the identity and V is the permutation that sorts the values."""
+    l = 70
+    gen = W.rng(3)
+    d = gen.permutation(np.arange(1, l + 1)).astype(np.float64)
+    Ut, s, Vt, info = lib.step_core_svd(dev(np.diag(d)), l)
+    order = np.argsort(-d, kind="stable")
+    assert np.array_equal(host(s), d[order])
+    P = np.eye(l)[:, order]
+    assert np.array_equal(np.abs(host(Vt)), P)
+    # U = M V diag(1/s): a column of M times a reciprocal, exact to one rounding
+    assert np.abs(np.abs(host(Ut)) - P).max() <= 2.0 ** -52
+
+
 # ------------------------------------------------------------------ whole method
 
 def check_against_oracle(lib, A_np, A_dev, k, q, seed, l=None, tol_s=1e-10, tol_vec=1e-8, pass_efficient=0):
