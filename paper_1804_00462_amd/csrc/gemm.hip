@@ -43,25 +43,42 @@ k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
 }
 
 // out[r][c] = sum_{s = 0..nsplit-1} P[s][r][c] in FP64, for c < ncols, in a
-// fixed order: the 8 waves of a block take s = w, w + 8, ... for the same 64
-// consecutive outputs (coalesced), then the 8 wave sums are added in order.
+// fixed order: the kRedWaves waves of a block take s = w, w + kRedWaves, ...
+// for the same 64 consecutive outputs (coalesced), eight splits in flight per
+// wave, each with its own running sum (s = w + kRedWaves (u + 8 j) goes to
+// sum u); the sums are combined pairwise, then the wave sums are added in
+// order. skipflag as in the pass kernel (the sum is not needed).
+constexpr int kRedWaves = 16;
+
 template <typename Acc>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(64 * kRedWaves)
 k_reduce(const Acc* __restrict__ P, int64_t OUT, int LP, int nsplit, double* __restrict__ out,
-         int64_t ldo, int ncols) {
-  __shared__ double part[8][64];
+         int64_t ldo, int ncols, const int* __restrict__ skipflag) {
+  if (skipflag && *skipflag) return;
+  __shared__ double part[kRedWaves][64];
   const int64_t total = OUT * LP;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
   const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
   double acc = 0.0;
-  if (idx < total)
-    for (int s = wv; s < nsplit; s += 8) acc += (double)P[(int64_t)s * total + idx];
+  if (idx < total) {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int s = wv;
+    for (; s + 7 * kRedWaves < nsplit; s += 8 * kRedWaves) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (double)P[(int64_t)(s + kRedWaves * u) * total + idx];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += v[u];
+    }
+    for (int u = 0; s < nsplit; s += kRedWaves, ++u) a[u] += (double)P[(int64_t)s * total + idx];
+    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  }
   part[wv][lane] = acc;
   __syncthreads();
   if (wv == 0 && idx < total) {
     double t = part[0][lane];
 #pragma unroll
-    for (int i = 1; i < 8; ++i) t += part[i][lane];
+    for (int i = 1; i < kRedWaves; ++i) t += part[i][lane];
     const int64_t r = idx / LP;
     const int c = (int)(idx % LP);
     if (c < ncols) out[r * ldo + c] = t;
@@ -255,11 +272,11 @@ int skinny_slots(int a_type, bool trans, int LP) {
 int skinny_step(int a_type) { return a_type == 0 ? 32 : (a_type == 1 ? 32 : 128); }
 
 hipError_t launch_reduce_f64(const double* P, int64_t OUT, int LP, int nsplit, double* out,
-                             int64_t ldo, int ncols, hipStream_t st) {
+                             int64_t ldo, int ncols, hipStream_t st, const int* skipflag) {
   const int64_t total = OUT * LP;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_reduce<double>), dim3((unsigned)ceil_div(total, 64)), dim3(512), 0, st,
-                     P, OUT, LP, nsplit, out, ldo, ncols);
+  hipLaunchKernelGGL((k_reduce<double>), dim3((unsigned)ceil_div(total, 64)), dim3(64 * kRedWaves), 0, st,
+                     P, OUT, LP, nsplit, out, ldo, ncols, skipflag);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ int h16_blocks_f16(bool trans, int rt, int CT);
 // store. 32-row tiles (33 KB of LDS) let four workgroups share a CU; the TN
 // permutation stays within aligned groups of 32 rows.
 constexpr int kCastRows = 32;
+constexpr int kCastLoads = kCastRows * 128 / 2 / 256;  // 16-byte loads per thread at LP = 128
 
 template <int FMT>
 __global__ void __launch_bounds__(256)
@@ -37,15 +38,32 @@ k_cast_h16_t(const double* __restrict__ Q, int64_t rows, int LP, int64_t ldt, in
              const int* __restrict__ cexp) {
   __shared__ double tile[kCastRows][129];
   const int64_t r0 = (int64_t)blockIdx.x * kCastRows;
-  for (int i = threadIdx.x; i < kCastRows * LP; i += 256) {
-    const int rr = i / LP, c = i % LP;
+  // the tile as pairs of entries (LP is even): every thread issues all its
+  // 16-byte loads before the first LDS store
+  double2 v[kCastLoads];
+#pragma unroll
+  for (int j = 0; j < kCastLoads; ++j) {
+    const int e = 2 * (threadIdx.x + 256 * j);
+    const int rr = e / LP, c = e % LP;
     const int64_t r = r0 + rr;
-    double v = 0.0;
-    if (r < rows) {
-      v = Q[r * LP + c];
-      if (sc) v = ldexp(v, permute ? sc->tn_base : sc->nn_base - (cexp ? cexp[r] : 0));
+    v[j] = double2{0.0, 0.0};
+    if (e < kCastRows * LP && r < rows) v[j] = *reinterpret_cast<const double2*>(Q + r * LP + c);
+  }
+#pragma unroll
+  for (int j = 0; j < kCastLoads; ++j) {
+    const int e = 2 * (threadIdx.x + 256 * j);
+    if (e < kCastRows * LP) {
+      const int rr = e / LP, c = e % LP;
+      const int64_t r = r0 + rr;
+      double2 w = v[j];
+      if (sc && r < rows) {
+        const int sh = permute ? sc->tn_base : sc->nn_base - (cexp ? cexp[r] : 0);
+        w.x = ldexp(w.x, sh);
+        w.y = ldexp(w.y, sh);
+      }
+      tile[rr][c] = w.x;
+      tile[rr][c + 1] = w.y;
     }
-    tile[rr][c] = v;
   }
   __syncthreads();
   const int parts = with_lo ? 2 : 1;
@@ -225,7 +243,8 @@ int bf16_step(bool trans, int rt, int LP) { return trans ? (rt >= 4 ? 64 : 128) 
 
 hipError_t launch_cast_h16_t(int fmt, const double* Q, int64_t rows, int LP, int64_t ldt, int permute,
                              int with_lo, uint16_t* QT, const H16Scale* sc, const int* cexp, hipStream_t st) {
-  if (ldt % kCastRows) return hipErrorInvalidValue;
+  // the staging loads take Q 16-byte aligned, LP even and at most 128
+  if (ldt % kCastRows || LP % 2 || LP > 128 || ((uintptr_t)Q % 16)) return hipErrorInvalidValue;
   const int64_t blocks = ceil_div(ldt, kCastRows);
   if (blocks == 0) return hipSuccess;
   if (fmt == kFmtBF16)

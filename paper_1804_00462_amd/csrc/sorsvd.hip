@@ -29,7 +29,7 @@ hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OU
                              float* P, double* normp, const int* skipflag, hipStream_t st,
                              double* Tout = nullptr);
 hipError_t launch_reduce_f64(const double* P, int64_t OUT, int LP, int nsplit, double* out,
-                             int64_t ldo, int ncols, hipStream_t st);
+                             int64_t ldo, int ncols, hipStream_t st, const int* skipflag = nullptr);
 hipError_t launch_reduce_f32(const float* P, int64_t OUT, int LP, int nsplit, double* out,
                              int64_t ldo, int ncols, hipStream_t st);
 hipError_t launch_pack_f64(const double* src, int64_t rows, int cols, int64_t lds, double* dst,
@@ -343,7 +343,7 @@ int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void
     const int* skip = it == 2 ? skip3 : nullptr;
     SORSVD_TRY(launch_skinny_f64(true, T, LP, LP, rows, T, LP, LP, gram.kchunk, gram.nsplit, P,
                                  nullptr, skip, st));
-    SORSVD_TRY(launch_reduce_f64(P, LP, LP, gram.nsplit, G, LP, LP, st));
+    SORSVD_TRY(launch_reduce_f64(P, LP, LP, gram.nsplit, G, LP, LP, st, skip));
     SORSVD_TRY(launch_chol_inv(G, LP, (int)p.l, rows, it, Rinv, skip3, info, st));
     SORSVD_TRY(launch_skinny_f64(false, T, LP, rows, LP, Rinv, LP, LP, LP, 1, T, nullptr, skip, st));
   }
