@@ -87,17 +87,38 @@ __device__ inline void ldl_flow(const double* __restrict__ G, int nparts, int64_
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   bool bail = false;
   int known = 0;  // rows known to be published
+  // this wave's rows of G (upper part), the parts added in order: all loads of
+  // a part are issued before the first is used (entries outside the upper
+  // part read a valid address and are dropped)
 #pragma unroll
-  for (int i = 0; i < kCholRowsPerWave; ++i) {
-    const int a = w + kCholWaves * i;
+  for (int i = 0; i < kCholRowsPerWave; ++i)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) R.v[i][h] = 0.0;
+  for (int p = 0; p < nparts; ++p) {
+    double gv[kCholRowsPerWave][2];
+#pragma unroll
+    for (int i = 0; i < kCholRowsPerWave; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int a = w + kCholWaves * i, c = lane + 64 * h;
+        const bool in = a < l && c < l && c >= a;
+        gv[i][h] = G[p * pstride + (in ? a * LP + c : 0)];
+      }
+#pragma unroll
+    for (int i = 0; i < kCholRowsPerWave; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int a = w + kCholWaves * i, c = lane + 64 * h;
+        if (a < l && c < l && c >= a) R.v[i][h] += gv[i][h];
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < kCholRowsPerWave; ++i)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int c = lane + 64 * h;
-      double v = 0.0;
-      if (a < l && c < l && c >= a) v = chol_gval(G, nparts, pstride, LP, a, c) + (c == a ? shift : 0.0);
-      R.v[i][h] = v;
+      const int a = w + kCholWaves * i;
+      if (a < l && lane + 64 * h == a) R.v[i][h] += shift;
     }
-  }
 #pragma unroll
   for (int i = 0; i < kCholRowsPerWave; ++i) {
     const int a = w + kCholWaves * i;
@@ -321,12 +342,36 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
   const int grp = tid / 8, gl = tid % 8;
   constexpr int ngroups = kJacThreads / 8;
 
-  for (int i = tid; i < l * ldm; i += kJacThreads) {
-    const int c = i / ldm, r = i % ldm;
-    double mv = 0.0;
-    if (r < l)
-      for (int p = 0; p < nparts; ++p) mv += Min[p * pstride + r * LP + c];
-    Mc[i] = mv;
+  // M (row-major, ld LP, as nparts partial sums added in order) into LDS
+  // column-major with rows l .. ldm - 1 zero: read row-major (a wave reads
+  // consecutive columns), kMLoad entries per thread in flight at a time
+  {
+    constexpr int kMLoad = 8;
+    const int tot = ldm * l;
+    for (int i0 = 0; i0 < tot; i0 += kJacThreads * kMLoad) {
+      double mv[kMLoad];
+#pragma unroll
+      for (int u = 0; u < kMLoad; ++u) mv[u] = 0.0;
+      for (int p = 0; p < nparts; ++p) {
+        double t[kMLoad];
+#pragma unroll
+        for (int u = 0; u < kMLoad; ++u) {
+          const int i = i0 + tid + kJacThreads * u;
+          const int r = i / l, c = i % l;
+          t[u] = Min[p * pstride + ((i < tot && r < l) ? r * LP + c : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < kMLoad; ++u) {
+          const int i = i0 + tid + kJacThreads * u;
+          if (i < tot && i / l < l) mv[u] += t[u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kMLoad; ++u) {
+        const int i = i0 + tid + kJacThreads * u;
+        if (i < tot) Mc[(i % l) * ldm + i / l] = mv[u];
+      }
+    }
   }
   if (WANT_V)
     for (int i = tid; i < l * vld; i += kJacThreads) {
