@@ -267,7 +267,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
                           acc, forced, 8, 8, proj_slots, proj_slots > 0 ? proj_slots : 2048);
   // l x l products over a tall FP64 operand: many short splits, with partial
   // sums up to the size of the operand (at 20000 x 100 the Gram product then
-  // runs 316 workgroups instead of 158: 26 -> 21 us)
+  // runs 250 workgroups instead of 158: 26 -> 21 us)
   const int ks64 = skinny_step(SORSVD_F64);
   const int rpbg = skinny_rows_per_block(SORSVD_F64, LP);
   // one wave of resident workgroups: more splits only add partial sums
