@@ -206,7 +206,7 @@ k_bapply(const BProb* __restrict__ probs, const BItem* __restrict__ items, int n
     if (qr_step_skipped(P, step, qiter)) continue;
     double* T = which == 2 ? P.T2 : P.T1;
     skinny_tile<double, false, 1, CT>(T, P.LP, which == 2 ? P.n : P.m, 0, P.LP, P.Rinv, P.LP, I.base, 1,
-                                      nullptr, T, P.LP, nullptr, Xs, red);
+                                      nullptr, T, P.LP, nullptr, Xs, red, 1);  // R^{-1} is upper triangular
   }
 }
 

@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(256, 2)
 k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
          const T* __restrict__ X, int64_t ldx, int64_t kchunk, int tiles, int nsplit,
          int vec_ok, typename Traits<T>::acc_t* P, double* __restrict__ normp,
-         const int* __restrict__ skipflag, double* Tout) {
+         const int* __restrict__ skipflag, double* Tout, int tri) {
   if (skipflag && *skipflag) return;  // product not needed (see the Cholesky QR step)
   constexpr int LP = CT * kTile;
   constexpr int KS = 4 * Traits<T>::VK;
@@ -39,7 +39,7 @@ k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
   const int64_t base = (int64_t)tile * (64 * RT);
   skinny_tile<T, TRANS, RT, CT>(A, lda, OUT, k0, k1, X, ldx, base, vec_ok,
                                 Tout ? nullptr : P + (int64_t)s * OUT * LP, Tout, LP,
-                                normp ? normp + v : nullptr, Xs, red);
+                                normp ? normp + v : nullptr, Xs, red, tri);
 }
 
 // out[r][c] = sum_{s = 0..nsplit-1} P[s][r][c] in FP64, for c < ncols, in a
@@ -154,12 +154,12 @@ template <typename T, bool TRANS, int RT>
 static hipError_t launch_ct(int CT, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
                             int64_t ldx, int64_t kchunk, int tiles, int nsplit, int vec_ok,
                             typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
-                            double* Tout, hipStream_t st) {
+                            double* Tout, hipStream_t st, int tri) {
   dim3 grid((unsigned)(tiles * nsplit)), block(256);
 #define SORSVD_CASE(C)                                                                           \
   case C:                                                                                        \
     hipLaunchKernelGGL((k_skinny<T, TRANS, RT, C>), grid, block, 0, st, A, lda, OUT, K, X, ldx, \
-                       kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout);                 \
+                       kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout, tri);            \
     break;
   switch (CT) {
     SORSVD_CASE(1) SORSVD_CASE(2) SORSVD_CASE(3) SORSVD_CASE(4)
@@ -183,34 +183,35 @@ template <typename T, int RT>
 static hipError_t launch_rt(bool trans, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
                             int64_t ldx, int LP, int64_t kchunk, int nsplit,
                             typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
-                            double* Tout, hipStream_t st) {
+                            double* Tout, hipStream_t st, int tri) {
   const int tiles = (int)ceil_div(OUT, 64 * RT);
   if (tiles == 0 || nsplit == 0) return hipSuccess;
   const int vec_ok = ((lda * (int64_t)sizeof(T)) % 16 == 0) && (((uintptr_t)A) % 16 == 0);
   if (trans)
-    return launch_ct<T, true, RT>(LP / kTile, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout, st);
-  return launch_ct<T, false, RT>(LP / kTile, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout, st);
+    return launch_ct<T, true, RT>(LP / kTile, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout, st, tri);
+  return launch_ct<T, false, RT>(LP / kTile, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout, st, tri);
 }
 
 template <typename T>
 hipError_t launch_skinny(bool trans, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
                          int64_t ldx, int LP, int64_t kchunk, int nsplit,
                          typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
-                         double* Tout, hipStream_t st) {
+                         double* Tout, hipStream_t st, int tri = 0) {
   // must agree with skinny_rt: FP64 64-row tiles, FP32 128-row tiles
   if constexpr (has_rt1<T>())
-    return launch_rt<T, 1>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st);
+    return launch_rt<T, 1>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st, tri);
   else
-    return launch_rt<T, 2>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st);
+    return launch_rt<T, 2>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st, tri);
 }
 
 // With Tout != null and nsplit == 1 the kernel writes the FP64 result itself.
+// tri: X is upper triangular (see skinny_tile).
 hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
                              const double* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              double* P, double* normp, const int* skipflag, hipStream_t st,
-                             double* Tout) {
+                             double* Tout, bool tri) {
   return launch_skinny<double>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag,
-                               nsplit == 1 ? Tout : nullptr, st);
+                               nsplit == 1 ? Tout : nullptr, st, tri ? 1 : 0);
 }
 
 hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OUT, int64_t K,

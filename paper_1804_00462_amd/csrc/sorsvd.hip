@@ -23,7 +23,7 @@ namespace sor {
 hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
                              const double* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              double* P, double* normp, const int* skipflag, hipStream_t st,
-                             double* Tout = nullptr);
+                             double* Tout = nullptr, bool tri = false);
 hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OUT, int64_t K,
                              const float* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              float* P, double* normp, const int* skipflag, hipStream_t st,
@@ -346,7 +346,8 @@ int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void
                                  nullptr, skip, st));
     SORSVD_TRY(launch_reduce_f64(P, LP, LP, gram.nsplit, G, LP, LP, st, skip));
     SORSVD_TRY(launch_chol_inv(G, LP, (int)p.l, rows, it, Rinv, skip3, info, st));
-    SORSVD_TRY(launch_skinny_f64(false, T, LP, rows, LP, Rinv, LP, LP, LP, 1, T, nullptr, skip, st));
+    SORSVD_TRY(launch_skinny_f64(false, T, LP, rows, LP, Rinv, LP, LP, LP, 1, T, nullptr, skip, st, nullptr,
+                                 true));
   }
   return SORSVD_OK;
 }
