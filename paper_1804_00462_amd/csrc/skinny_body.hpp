@@ -82,7 +82,7 @@ constexpr int xs_elems() { return 2 * 4 * Traits<T>::VK * (CT * kTile + 2); }
 // output rows, after it has read all of its input rows. If nrm != null the
 // FP64 sum of squares of the A elements this workgroup read is stored there.
 // Xs: LDS of xs_elems<T, CT>() elements; red: LDS of 4 doubles.
-// PD: A fragments are loaded PD steps ahead (1 or 2). tri (FP64 only): X is
+// PD: A fragments are loaded PD steps ahead (1 or 2). tri (FP64 NN only): X is
 // upper triangular (X[k][c] = 0 for k > c, as R^{-1}), so the MFMAs of a step
 // whose contraction indices all lie below a 16-column output tile are skipped
 // (their products are exact zeros).
@@ -196,7 +196,7 @@ __device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
-        if constexpr (sizeof(T) == 8)
+        if constexpr (sizeof(T) == 8 && !TRANS)
           if (tri && kb >= (int64_t)(ct + 1) * kTile) continue;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Tr::mfma(a[rt][j], bq[j & 1][ct], acc[rt][ct]);
