@@ -43,8 +43,11 @@ WORKLOADS = {
     "c2pe": (20000, 20000, 100, 1, "float32", 0,
              "C2 with the pass-efficient core matrix (eq. M_approx, formed as T2^T Q2 from the last orbit "
              "product: 2q + 2 = 4 passes over A)"),
+    "c3pe": (200000, 4000, 64, 1, "bfloat16", 1,
+             "C3 with the pass-efficient core matrix (eq. M_approx as T2^T Q2; the last orbit product "
+             "takes Q1 split into BF16 hi + lo parts: 2q + 2 = 4 passes over A)"),
 }
-PASS_EFFICIENT = {"c2pe"}
+PASS_EFFICIENT = {"c2pe", "c3pe"}
 
 C4_DESC = ("batched SOR-SVD FP32: 512 RPCA-style problems L + S (L = X Y^T, N(0,1) factors of rank r, "
            "S = 5% outliers U[-10, 10]), m ~ U[256, 4096], n ~ U[128, 2048], r ~ U[4, 64] (seed 3), "
@@ -54,7 +57,7 @@ C4_DESC = ("batched SOR-SVD FP32: 512 RPCA-style problems L + S (L = X Y^T, N(0,
 PEAK = {"float32": ("mfma", 157.3, "TFLOP/s"), "float64": ("mfma", 78.6, "TFLOP/s"),
         "bfloat16": ("hbm", 8000.0, "GB/s"), "float16": ("hbm", 8000.0, "GB/s")}
 DTYPE_TAG = {"float32": "f32", "float64": "f64", "bfloat16": "bf16", "float16": "f16"}
-REDUCED = {"c3", "c3h"}  # 16-bit storage: also the error against the FP64 matrix
+REDUCED = {"c3", "c3h", "c3pe"}  # 16-bit storage: also the error against the FP64 matrix
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -98,9 +101,9 @@ def make_input(name, torch, P, quick=False):
         return A.to(getattr(torch, dname)), {}, None
     if name in ("c2", "c2pe"):
         return W.c2_torch("cuda"), {}, None
-    if name in ("c3", "c3h"):
+    if name in ("c3", "c3h", "c3pe"):
         A64 = W.c3_torch("cuda", out_dtype=torch.float64)
-        if name == "c3":
+        if name in ("c3", "c3pe"):
             return A64.to(torch.bfloat16), {}, A64
         Ah, e = P.pack_f16(A64)
         return Ah, {"col_exp": e}, A64
@@ -334,7 +337,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
-    ap.add_argument("--extra", default="c3,c3h,c1,c4,c5,c2pe,rpca",
+    ap.add_argument("--extra", default="c3,c3h,c1,c4,c5,c2pe,c3pe,rpca",
                     help="comma-separated extra workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick-input", action="store_true",

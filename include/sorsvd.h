@@ -77,7 +77,8 @@ typedef enum sorsvd_dtype {
 typedef struct sorsvd_opts {
   int64_t l;          /* sketch width l, k <= l <= min(m, n); 0 means l = k */
   int32_t max_sweeps; /* Jacobi sweep cap of the core SVD; 0 means 40 */
-  int32_t refine;     /* BF16 / FP16 A only: 1 = projection pass with Q2 split hi+lo */
+  int32_t refine;     /* BF16 / FP16 A only: 1 = projection pass with Q2 split hi+lo (with
+                         pass_efficient: the last orbit product with Q1 split hi+lo) */
   int32_t residual;   /* 1 = also compute ||A - U S V^T||_F explicitly (one more pass over A,
                          FP32 MFMA for FP32 / BF16 / FP16 A, FP64 for FP64 A, FP64 accumulation) */
   int32_t split;      /* split of the contraction in the passes; 0 = automatic */
@@ -88,9 +89,12 @@ typedef struct sorsvd_opts {
                              product, Q2 spans A^T Q1, so Q1^T A = R2^T Q2^T and M_approx equals
                              M = Q1^T A Q2 in exact arithmetic; it is formed as T2^T Q2 from the
                              last orbit product T2 = A^T Q1 kept before its QR (FP64, no
-                             pseudo-inverse, no pass over A). FP32 / FP64 / diagonal A only
-                             (SORSVD_EUNSUPPORTED for BF16 / FP16 A, whose core matrix needs
-                             the refinement pass). The error identity stays valid. */
+                             pseudo-inverse, no pass over A). BF16 / FP16 A with refine = 1:
+                             the last orbit product takes Q1 split into 16-bit hi + lo parts
+                             (2 LP columns in one pass over A, the halves added in FP64), so
+                             T2 carries Q1 as the refinement projection would carry Q2;
+                             without refine it takes Q1 in 16 bits (M then holds Q1's 16-bit
+                             rounding). The error identity stays valid. */
   const int32_t* col_exp; /* FP16 A only (else SORSVD_EUNSUPPORTED): DEVICE array of n column
                              exponents, A = A_stored diag(2^-e_j); NULL = no scaling. The
                              result (U, S, V, ||A||_F, errors) is that of A, not of A_stored.

@@ -183,6 +183,8 @@ struct Plan {
   int64_t ldt;    // 16-bit A: leading dimension of the transposed skinny operands
   int rt_nn, rt_tn, rt_proj;  // 16-bit A: rows (NN) / columns (TN) of A per workgroup = 64 rt
   Split projb;    // 16-bit A: split of the refinement projection pass
+  int rt_tnb;     // 16-bit A, pass_eff with refine: the last orbit product with Q1 = hi + lo
+  Split tnb;      // ... and its split
   Split nn, tn, gram_m, gram_n, proj;
   int nn_blocks;
   size_t off_info, off_xc, off_t1, off_t2, off_w, off_u64, off_v64, off_p, off_normp;
@@ -226,7 +228,6 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->refine = (h16 && o && o->refine) ? 1 : 0;
   p->residual = (o && o->residual) ? 1 : 0;
   p->pass_eff = (o && o->pass_efficient) ? 1 : 0;
-  if (p->pass_eff && h16) return SORSVD_EUNSUPPORTED;
   p->ldt = round_up(std::max(m, n), 128) + 128;  // room for the last step's over-read
   const int forced = o ? o->split : 0;
   const int ks = skinny_step(a_type == SORSVD_DIAG ? SORSVD_F64 : a_type);
@@ -261,6 +262,15 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
                                    : (h16 ? h16_slots(p->fmt, true, p->rt_tn, (int)LP) : 0);
   p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced, 8, 8, tn_slots,
                        (h16 && tn_slots > 0) ? tn_slots : 2048);
+  // pass-efficient core matrix on 16-bit A with refinement: the last orbit
+  // product takes [Q1 hi | Q1 lo] (2 LP columns), so that T2 = A^T Q1, from
+  // which M is formed, carries Q1 to ~2^-17 as the projection pass would
+  p->rt_tnb = tile_opt ? tile_opt : 2;
+  if (h16 && p->pass_eff && p->refine) {
+    const int tnb_slots = h16_slots(p->fmt, true, p->rt_tnb, 2 * (int)LP);
+    p->tnb = choose_split(n, m, 64 * p->rt_tnb, bf16_step(true, p->rt_tnb, 2 * (int)LP), 2 * (int)LP, p->es, acc,
+                          forced, 8, 8, tnb_slots, tnb_slots > 0 ? tnb_slots : 2048);
+  }
   const int LPproj = (int)LP * (p->refine ? 2 : 1);
   const int proj_slots = h16 ? h16_slots(p->fmt, false, p->rt_proj, LPproj) : 0;
   p->projb = choose_split(m, n, 64 * p->rt_proj, h16 ? bf16_step(false, p->rt_proj, LPproj) : 128, LPproj, p->es,
@@ -293,6 +303,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   pb = std::max(pb, partial_bytes(m, LP, p->nn, acc));
   pb = std::max(pb, partial_bytes(m, (p->refine ? 2 : 1) * LP, p->projb, acc));
   pb = std::max(pb, partial_bytes(n, LP, p->tn, acc));
+  if (h16 && p->pass_eff && p->refine) pb = std::max(pb, partial_bytes(n, 2 * LP, p->tnb, acc));
   pb = std::max(pb, partial_bytes(LP, LP, p->gram_m, 8));
   pb = std::max(pb, partial_bytes(LP, LP, p->gram_n, 8));
   p->off_p = L.take(pb);
@@ -370,6 +381,8 @@ PassTimer& timer() {
 //                    = A^T Y (trans = true,  Y in compute type, K = m)
 int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, double* T,
          double* normp, void* ws, hipStream_t st, bool fold = false, bool proj = false) {
+  // (trans with fold: the last orbit product of the pass-efficient form, with
+  // [Q1 hi | Q1 lo]; its halves are always added by the reduction)
   const int LP = (int)p.LP;
   const int64_t OUT = trans ? p.n : p.m;
   const int64_t K = trans ? p.m : p.n;
@@ -408,13 +421,15 @@ int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, 
     // operands carry the scaling of the scale record, undone on T.
     float* P = at<float>(ws, p.off_p);
     const int LPw = fold ? 2 * LP : LP;
-    const Split& spb = proj ? p.projb : sp;
-    const int rt = proj ? p.rt_proj : (trans ? p.rt_tn : p.rt_nn);
+    const bool tfold = trans && fold;
+    const Split& spb = proj ? p.projb : (tfold ? p.tnb : sp);
+    const int rt = proj ? p.rt_proj : (tfold ? p.rt_tnb : (trans ? p.rt_tn : p.rt_nn));
     const H16Scale* sc = p.fmt == kFmtF16 ? at<H16Scale>(ws, p.off_hsc) : nullptr;
     SORSVD_TRY(launch_h16_pass(p.fmt, trans, (const uint16_t*)A, lda, OUT, K, (const uint16_t*)Xc, p.ldt, LPw,
-                               spb.kchunk, spb.nsplit, P, normp, T, fold ? 1 : 0, rt, sc, p.cexp, st));
+                               spb.kchunk, spb.nsplit, P, normp, tfold ? nullptr : T, fold ? 1 : 0, rt, sc,
+                               p.cexp, st));
     if (e1) SORSVD_TRY(hipEventRecord(e1, st));
-    if (spb.nsplit > 1) {  // with one split the kernel wrote T itself
+    if (spb.nsplit > 1 || tfold) {  // with one split the kernel wrote T itself (not the A^T Y kernel with fold)
       if (sc)
         SORSVD_TRY(launch_reduce_h16(trans, P, OUT, LPw, spb.nsplit, T, LP, LP, fold ? 1 : 0, sc, p.cexp, st));
       else if (fold)
@@ -501,9 +516,12 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
     if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st, p.q == 0))) return rc;
   }
   // T2 = A^T Q1 (eq. AT1; the span of A^T T1 by Lemma 1); Q2 = qr(T2).
-  const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true);
+  // (the pass-efficient form with refinement splits Q1 into hi + lo for the
+  // orbit product that M is formed from)
+  const bool pe_lo = p.pass_eff && p.refine;
+  const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true, pe_lo && p.q == 0);
   if (rc) return rc;
-  if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
+  if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st, pe_lo && p.q == 0))) return rc;
   if (p.pass_eff && p.q == 0) SORSVD_TRY(launch_pack_f64(T2, p.n, LP, LP, T2P, LP, st));
   if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st, p.q == 0))) return rc;
   // Power method (Alg. 4 loop), orthonormalising after each product.
@@ -513,9 +531,9 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
     if (rc) return rc;
     if ((rc = pass(p, false, A, lda, X, T1, nullptr, ws, st))) return rc;
     if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st, last))) return rc;
-    Y = as_operand(p, T1, p.m, ws, st, &rc, true);
+    Y = as_operand(p, T1, p.m, ws, st, &rc, true, pe_lo && last);
     if (rc) return rc;
-    if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
+    if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st, pe_lo && last))) return rc;
     if (p.pass_eff && last) SORSVD_TRY(launch_pack_f64(T2, p.n, LP, LP, T2P, LP, st));
     if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st, last))) return rc;
   }

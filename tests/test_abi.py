@@ -39,17 +39,23 @@ def test_workspace_query_validates_shapes():
     assert P.workspace_bytes(10, 8, 3, 0, 9) == 0                   # unknown dtype
     # workspace grows with the sketch width
     assert P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F32) > P.workspace_bytes(5000, 4000, 16, 1, P.SORSVD_F32)
-    # the pass-efficient core matrix keeps the last orbit product (n x LP FP64); not for BF16 A
+    # the pass-efficient core matrix keeps the last orbit product (n x LP FP64)
     assert (P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F32, pass_efficient=1)
             == P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F32) + 4000 * 64 * 8)
-    assert P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, pass_efficient=1) == 0
+    # 16-bit A: the same, and with refinement the partial sums of the 2 LP-column
+    # orbit product (without a device the split is the device-independent one)
+    assert (P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, pass_efficient=1)
+            == P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16) + 4000 * 64 * 8)
+    assert (P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, pass_efficient=1, refine=1)
+            >= P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, refine=1) + 4000 * 64 * 8)
 
 
 def test_fp16_workspace_and_unsupported_combinations(clib):
     # FP16 A shares the 16-bit plan and adds the 256-byte operand scale record
     assert (P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F16, refine=1)
             == P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, refine=1) + 256)
-    assert P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F16, pass_efficient=1) == 0
+    assert (P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_F16, pass_efficient=1, refine=1)
+            == P.workspace_bytes(5000, 4000, 64, 1, P.SORSVD_BF16, pass_efficient=1, refine=1) + 256)
 
     def ws(t, col_exp):  # col_exp is only checked for null on the host
         o = _lib.Opts(col_exp=col_exp)

@@ -160,6 +160,47 @@ def test_16bit_forced_splits_agree(lib, fmt, split):
     assert dsig < (1e-3 if fmt == "bf16" else 1e-4)
 
 
+@pytest.mark.parametrize("fmt,m,n,k,q", [("bf16", 3000, 1200, 64, 1), ("bf16", 1500, 900, 32, 0),
+                                         ("f16", 3000, 1200, 64, 1), ("f16", 1100, 1300, 48, 2)])
+def test_16bit_pass_efficient_against_oracle(lib, fmt, m, n, k, q):
+    """Pass-efficient core matrix on 16-bit A (eq. M_approx, formed from the
+    last orbit product T2 = A^T Q1, whose Q1 is split into hi + lo parts):
+    against the oracle's M_approx form on the stored values, and against the
+    same method with the refinement projection pass."""
+    sigma = 0.9 ** np.arange(1, min(m, n) + 1)
+    A, _, _ = W.spectral(m, n, sigma, 4)
+    if fmt == "bf16":
+        A = to_bf16(A)
+        Ad, opts = dev_bf16(A), {}
+    else:
+        Ad, e = lib.pack_f16(torch.as_tensor(A).cuda())
+        opts = {"col_exp": e}
+        A = host(Ad) * np.exp2(-host(e))[None, :]
+    sig_stored = np.linalg.svd(A, compute_uv=False)
+    U, S, V, info = lib.sorsvd(Ad, k, q=q, seed=3, refine=1, pass_efficient=1, **opts)
+    U, S, V = host(U), host(S), host(V)
+    assert info["flags"] == 0
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-11
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-11
+    assert np.all(np.diff(S) <= 0)
+    assert np.all(S <= sig_stored[:k] * (1 + 1e-4))
+    R = A - (U * S) @ V.T
+    e_ex = np.linalg.norm(R) / np.linalg.norm(A)
+    assert e_ex >= bounds.ey_floor(sig_stored, k) / np.linalg.norm(A) * (1 - 1e-6)
+    Uo, So, Vo, io = osvd.sorsvd(A, k, q=q, seed=3, m_form="approx")
+    dsig = np.max(np.abs(S - So)) / So[0]
+    de = abs(e_ex - io["err_fro"]) / io["err_fro"]
+    _, Sx, _, _ = lib.sorsvd(Ad, k, q=q, seed=3, refine=1, **opts)
+    dx = np.max(np.abs(S - host(Sx))) / S[0]
+    print(f"{fmt} pass-efficient m={m} n={n} k={k} q={q}: sigma vs oracle {dsig:.2e}, err rel {de:.2e}, "
+          f"vs projection pass {dx:.2e}, identity {info['err_fro']:.4e} explicit {e_ex:.4e}")
+    # measured margins as for the projection form (the orbit operand is split
+    # like the projection operand there)
+    assert dsig < (1e-3 if fmt == "bf16" else 1e-4)
+    assert de < 5e-3
+    assert dx < 1e-3
+
+
 def test_bf16_explicit_residual_and_rounding_noise(lib):
     """The residual pass measures the error against the stored BF16 matrix and
     the rounding noise of storing it; their difference of squares estimates the
