@@ -74,10 +74,12 @@ def test_c2_full_size_fp32(lib):
     assert abs(info["a_fro"] - io["a_fro"]) <= 1e-6 * io["a_fro"]
 
 
-@pytest.mark.parametrize("fmt", ["bf16", "f16"])
-def test_c3_full_size_16bit(lib, fmt):
+@pytest.mark.parametrize("fmt,pe", [("bf16", 0), ("f16", 0), ("bf16", 1)])
+def test_c3_full_size_16bit(lib, fmt, pe):
     """200000 x 4000, U diag(0.9^j) V^T + N(0, (1e-6)^2), k = l = 64, q = 1,
-    refinement pass; stored in BF16, or in FP16 with column exponents."""
+    refinement; stored in BF16, or in FP16 with column exponents; pe: the
+    pass-efficient core matrix (eq. M_approx, compared with the oracle's
+    M_approx form)."""
     A64 = W.c3_torch("cuda", out_dtype=torch.float64)
     m, n = A64.shape
     k = 64
@@ -90,7 +92,7 @@ def test_c3_full_size_16bit(lib, fmt):
         opts = {"col_exp": e}
         stored = A.double() * torch.exp2(-e.double())[None, :]
     del A64
-    plan = lib.Plan(m, n, k, 1, A.dtype, refine=1, **opts)
+    plan = lib.Plan(m, n, k, 1, A.dtype, refine=1, pass_efficient=pe, **opts)
     U, S, V = plan.run(A, 1)
     info = plan.info()
     assert info["flags"] == 0
@@ -100,10 +102,10 @@ def test_c3_full_size_16bit(lib, fmt):
     Ah = host(stored)
     del stored
     torch.cuda.empty_cache()
-    _, So, _, io = osvd.sorsvd(Ah, k, q=1, seed=1)
+    _, So, _, io = osvd.sorsvd(Ah, k, q=1, seed=1, m_form="approx" if pe else "exact")
     dsig = np.max(np.abs(Sh - So)) / So[0]
     de = abs(e_st - io["err_fro"]) / io["err_fro"]
-    print(f"C3 {fmt} full size: sigma normwise {dsig:.2e}, err {e_st:.6e} vs oracle {io['err_fro']:.6e} "
+    print(f"C3 {fmt} pe={pe} full size: sigma normwise {dsig:.2e}, err {e_st:.6e} vs oracle {io['err_fro']:.6e} "
           f"(rel {de:.2e}), identity {info['err_fro']:.6e}", flush=True)
     # 16-bit skinny operands (BF16 8 bits, FP16 11 bits) with FP32 accumulation
     # over 4000 / 200000 terms; the error of this matrix is dominated by its
