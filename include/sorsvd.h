@@ -337,8 +337,10 @@ void sorsvd_batch_destroy(sorsvd_batch* b);
  * sorsvd_auto: probe -> network -> (k, q) -> SOR-SVD -> judge -> fallback.
  *   For each q the network's width is taken with 25% head-room, rounded up to
  *   a multiple of 8, and kept if it fits min(128, m, n); among those the (k, q)
- *   with the least modelled pass time (2q + 3) max(1, k / k_ridge) wins
- *   (k_ridge 312 for BF16, 39 otherwise). Judge: the error identity
+ *   with the least modelled pass time P max(1, k / k_ridge) wins (k_ridge 312
+ *   for BF16, 39 otherwise; P = 2q + 3 passes, 2q + 2 for BF16 A, whose runs
+ *   take the refinement split and the pass-efficient core matrix, as with
+ *   opts.refine = opts.pass_efficient = 1). Judge: the error identity
  *   (FP32/FP64), or for BF16 the explicit residual corrected for the rounding
  *   of A to BF16: sqrt(err_fro_explicit^2 - (1 - 2 rho) a_noise_rel^2) with
  *   rho = min(1, 4 k (m^-1/2 + n^-1/2)^2), an allowance for the share of the
