@@ -127,13 +127,16 @@ def test_bf16_whole_method(lib, m, n, k, q):
     assert abs(info["a_fro"] - io["a_fro"]) <= 1e-7 * io["a_fro"]
 
 
-@pytest.mark.parametrize("fmt,split", [("bf16", 3), ("bf16", 7), ("f16", 3)])
-def test_16bit_forced_splits_agree(lib, fmt, split):
+@pytest.mark.parametrize("fmt,split,pe", [("bf16", 3, 0), ("bf16", 7, 0), ("f16", 3, 0), ("bf16", 3, 1),
+                                          ("f16", 7, 1)])
+def test_16bit_forced_splits_agree(lib, fmt, split, pe):
     """Contraction splits of the 16-bit passes whose ranges hold an odd number
     of the A X kernel's 128-index blocks (1100 in 3: ranges of 384, the last
     332) or end in a short range (in 7: 4 ranges of 256, the last 76): the
     result equals the unsplit run up to the FP32 rounding of the per-split
-    partial sums, and both stay within the oracle's tolerance."""
+    partial sums, and both stay within the oracle's tolerance. pe: the
+    pass-efficient form, whose last orbit product (2 LP columns, hi + lo)
+    takes the forced split too, against the oracle's M_approx."""
     m, n, k = 1500, 1100, 64
     sigma = 0.9 ** np.arange(1, n + 1)
     A, _, _ = W.spectral(m, n, sigma, 5)
@@ -144,8 +147,8 @@ def test_16bit_forced_splits_agree(lib, fmt, split):
         Ad, e = lib.pack_f16(torch.as_tensor(A).cuda())
         opts = {"col_exp": e}
         A = host(Ad) * np.exp2(-host(e))[None, :]
-    _, S0, _, i0 = lib.sorsvd(Ad, k, q=1, seed=3, refine=1, split=1, **opts)
-    U1, S1, V1, i1 = lib.sorsvd(Ad, k, q=1, seed=3, refine=1, split=split, **opts)
+    _, S0, _, i0 = lib.sorsvd(Ad, k, q=1, seed=3, refine=1, split=1, pass_efficient=pe, **opts)
+    U1, S1, V1, i1 = lib.sorsvd(Ad, k, q=1, seed=3, refine=1, split=split, pass_efficient=pe, **opts)
     S0, S1, U1, V1 = host(S0), host(S1), host(U1), host(V1)
     assert i0["flags"] == 0 and i1["flags"] == 0
     assert np.abs(U1.T @ U1 - np.eye(k)).max() < 1e-11
@@ -153,9 +156,9 @@ def test_16bit_forced_splits_agree(lib, fmt, split):
     # ||A||_F: the same 8-value squares, grouped differently in FP64
     assert abs(i1["a_fro"] - i0["a_fro"]) <= 1e-13 * i0["a_fro"]
     d01 = np.max(np.abs(S1 - S0)) / S0[0]
-    _, So, _, io = osvd.sorsvd(A, k, q=1, seed=3)
+    _, So, _, io = osvd.sorsvd(A, k, q=1, seed=3, m_form="approx" if pe else "exact")
     dsig = np.max(np.abs(S1 - So)) / So[0]
-    print(f"{fmt} split {split}: sigma vs unsplit {d01:.2e}, vs oracle {dsig:.2e}")
+    print(f"{fmt} split {split} pe {pe}: sigma vs unsplit {d01:.2e}, vs oracle {dsig:.2e}")
     assert d01 < 1e-4
     assert dsig < (1e-3 if fmt == "bf16" else 1e-4)
 
