@@ -434,7 +434,7 @@ def auto(A, tol, params=None, seed=0):
     lib = _lib.load()
     _check_matrix(A)
     code, (m, n) = dtype_code(A.dtype), A.shape
-    kcap = min(128, m, n)
+    kcap = min(1024, m, n)
     nbytes = int(lib.sorsvd_auto_workspace_bytes(m, n, code))
     if nbytes == 0:
         raise _lib.SorsvdError(-1, "sorsvd_auto_workspace_bytes")

@@ -24,6 +24,7 @@ SOURCES = {
     "gemm_f16.hip": [],
     "batched.hip": [],
     "small.hip": [],
+    "wide.hip": [],
     "philox.hip": ["-ffp-contract=off"],
     "gemm.hip": [],
     "sorsvd.hip": [],

@@ -20,26 +20,54 @@
 
 namespace sor {
 
+// The skinny operand and the output may be wider than one workgroup's
+// columns: they are then cut into ncb column blocks of CT tiles (the output
+// and the partial sums have ncb CT 16 columns). The ncb workgroups of one
+// (split, row tile) read the same rows of A and get neighbouring logical
+// indices, so they run on one XCD at about the same time and A comes from
+// HBM about once. The sums of squares of A (normp) are taken by column
+// block 0, one slot per (split, row tile).
 template <typename T, bool TRANS, int RT, int CT>
 __global__ void __launch_bounds__(256, 2)
 k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
-         const T* __restrict__ X, int64_t ldx, int64_t kchunk, int tiles, int nsplit,
+         const T* __restrict__ X, int64_t ldx, int64_t kchunk, int tiles, int nsplit, int ncb,
          int vec_ok, typename Traits<T>::acc_t* P, double* __restrict__ normp,
          const int* __restrict__ skipflag, double* Tout, int tri) {
   if (skipflag && *skipflag) return;  // product not needed (see the Cholesky QR step)
-  constexpr int LP = CT * kTile;
-  constexpr int KS = 4 * Traits<T>::VK;
+  constexpr int CB = CT * kTile;
   __shared__ T Xs[xs_elems<T, CT>()];
   __shared__ double red[4];
-  const int nb = tiles * nsplit;
-  const int v = xcd_remap((int)blockIdx.x, nb);
-  const int s = v / tiles, tile = v % tiles;
+  const int nb = tiles * nsplit * ncb;
+  const int v = ncb > 1 ? xcd_remap_any((int)blockIdx.x, nb) : xcd_remap((int)blockIdx.x, nb);
+  const int cb = v % ncb, u = v / ncb;
+  const int s = u / tiles, tile = u % tiles;
+  const int64_t ldp = (int64_t)ncb * CB, c0 = (int64_t)cb * CB;
   const int64_t k0 = (int64_t)s * kchunk;
   const int64_t k1 = min(K, k0 + kchunk);
   const int64_t base = (int64_t)tile * (64 * RT);
-  skinny_tile<T, TRANS, RT, CT>(A, lda, OUT, k0, k1, X, ldx, base, vec_ok,
-                                Tout ? nullptr : P + (int64_t)s * OUT * LP, Tout, LP,
-                                normp ? normp + v : nullptr, Xs, red, tri);
+  skinny_tile<T, TRANS, RT, CT>(A, lda, OUT, k0, k1, X + c0, ldx, base, vec_ok,
+                                Tout ? nullptr : P + (int64_t)s * OUT * ldp + c0, Tout ? Tout + c0 : nullptr, ldp,
+                                (normp && cb == 0) ? normp + u : nullptr, Xs, red, tri, ldp, c0);
+}
+
+// Column block cb of T <- T Z in place, for an upper triangular Z (LP x LP,
+// LP = ncb CT 16): block cb needs columns [0, c0 + CB) of T (Z is zero below
+// its diagonal) and overwrites columns [c0, c0 + CB). The blocks are formed
+// from the last to the first (one launch each), so no block reads columns an
+// earlier launch has overwritten. (P and nrm are null; taken as arguments,
+// since constant null pointers there crash this compiler.)
+template <int CT>
+__global__ void __launch_bounds__(256, 2)
+k_apply_tri_block(double* T, int64_t rows, int64_t LP, const double* __restrict__ Z, int cb, int vec_ok,
+                  const int* __restrict__ skipflag, double* P, double* nrm) {
+  if (skipflag && *skipflag) return;
+  constexpr int CB = CT * kTile;
+  __shared__ double Xs[xs_elems<double, CT>()];
+  __shared__ double red[4];
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  const int64_t c0 = (int64_t)cb * CB;
+  skinny_tile<double, false, 1, CT>(T, LP, rows, 0, min(LP, c0 + CB), Z + c0, LP, base, vec_ok, P, T + c0,
+                                    LP, nrm, Xs, red, 1, LP, c0);
 }
 
 // out[r][c] = sum_{s = 0..nsplit-1} P[s][r][c] in FP64, for c < ncols, in a
@@ -152,14 +180,14 @@ hipError_t launch_zero_lower(double* R, int l, hipStream_t st) {
 
 template <typename T, bool TRANS, int RT>
 static hipError_t launch_ct(int CT, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
-                            int64_t ldx, int64_t kchunk, int tiles, int nsplit, int vec_ok,
+                            int64_t ldx, int64_t kchunk, int tiles, int nsplit, int ncb, int vec_ok,
                             typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
                             double* Tout, hipStream_t st, int tri) {
-  dim3 grid((unsigned)(tiles * nsplit)), block(256);
+  dim3 grid((unsigned)(tiles * nsplit * ncb)), block(256);
 #define SORSVD_CASE(C)                                                                           \
   case C:                                                                                        \
     hipLaunchKernelGGL((k_skinny<T, TRANS, RT, C>), grid, block, 0, st, A, lda, OUT, K, X, ldx, \
-                       kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout, tri);            \
+                       kchunk, tiles, nsplit, ncb, vec_ok, P, normp, skipflag, Tout, tri);       \
     break;
   switch (CT) {
     SORSVD_CASE(1) SORSVD_CASE(2) SORSVD_CASE(3) SORSVD_CASE(4)
@@ -181,45 +209,76 @@ int skinny_rt(int a_type, int64_t OUT) { return a_type == 1 ? 2 : 1; }
 
 template <typename T, int RT>
 static hipError_t launch_rt(bool trans, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
-                            int64_t ldx, int LP, int64_t kchunk, int nsplit,
+                            int64_t ldx, int LP, int64_t kchunk, int nsplit, int ncb,
                             typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
                             double* Tout, hipStream_t st, int tri) {
   const int tiles = (int)ceil_div(OUT, 64 * RT);
   if (tiles == 0 || nsplit == 0) return hipSuccess;
+  if (ncb < 1 || LP % (ncb * kTile)) return hipErrorInvalidValue;
   const int vec_ok = ((lda * (int64_t)sizeof(T)) % 16 == 0) && (((uintptr_t)A) % 16 == 0);
+  const int CT = LP / ncb / kTile;
   if (trans)
-    return launch_ct<T, true, RT>(LP / kTile, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout, st, tri);
-  return launch_ct<T, false, RT>(LP / kTile, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, vec_ok, P, normp, skipflag, Tout, st, tri);
+    return launch_ct<T, true, RT>(CT, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, ncb, vec_ok, P, normp, skipflag, Tout, st, tri);
+  return launch_ct<T, false, RT>(CT, A, lda, OUT, K, X, ldx, kchunk, tiles, nsplit, ncb, vec_ok, P, normp, skipflag, Tout, st, tri);
 }
 
 template <typename T>
 hipError_t launch_skinny(bool trans, const T* A, int64_t lda, int64_t OUT, int64_t K, const T* X,
                          int64_t ldx, int LP, int64_t kchunk, int nsplit,
                          typename Traits<T>::acc_t* P, double* normp, const int* skipflag,
-                         double* Tout, hipStream_t st, int tri = 0) {
+                         double* Tout, hipStream_t st, int tri = 0, int ncb = 1) {
   // must agree with skinny_rt: FP64 64-row tiles, FP32 128-row tiles
   if constexpr (has_rt1<T>())
-    return launch_rt<T, 1>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st, tri);
+    return launch_rt<T, 1>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, ncb, P, normp, skipflag, Tout, st, tri);
   else
-    return launch_rt<T, 2>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag, Tout, st, tri);
+    return launch_rt<T, 2>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, ncb, P, normp, skipflag, Tout, st, tri);
 }
 
 // With Tout != null and nsplit == 1 the kernel writes the FP64 result itself.
-// tri: X is upper triangular (see skinny_tile).
+// tri: X is upper triangular (see skinny_tile); not with ncb > 1 in place
+// (launch_apply_tri_blocks). ncb: column blocks of X and of the output (LP is
+// their total width).
 hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
                              const double* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              double* P, double* normp, const int* skipflag, hipStream_t st,
-                             double* Tout, bool tri) {
+                             double* Tout, bool tri, int ncb) {
+  if (tri && ncb > 1 && Tout == A) return hipErrorInvalidValue;
   return launch_skinny<double>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag,
-                               nsplit == 1 ? Tout : nullptr, st, tri ? 1 : 0);
+                               nsplit == 1 ? Tout : nullptr, st, tri ? 1 : 0, ncb);
 }
 
 hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OUT, int64_t K,
                              const float* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              float* P, double* normp, const int* skipflag, hipStream_t st,
-                             double* Tout) {
+                             double* Tout, int ncb) {
   return launch_skinny<float>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag,
-                              nsplit == 1 ? Tout : nullptr, st);
+                              nsplit == 1 ? Tout : nullptr, st, 0, ncb);
+}
+
+// T (rows x LP, ld LP) <- T Z in place, Z upper triangular LP x LP, LP = ncb
+// column blocks of equal width (at most 128).
+hipError_t launch_apply_tri_blocks(double* T, int64_t rows, int LP, const double* Z, int ncb,
+                                   const int* skipflag, hipStream_t st) {
+  if (ncb < 1 || LP % (ncb * kTile)) return hipErrorInvalidValue;
+  const int CT = LP / ncb / kTile;
+  const int64_t tiles = ceil_div(rows, 64);
+  if (tiles == 0) return hipSuccess;
+  const int vec_ok = ((LP * 8) % 16 == 0) && (((uintptr_t)T) % 16 == 0);
+  dim3 grid((unsigned)tiles), block(256);
+  for (int cb = ncb - 1; cb >= 0; --cb) {
+#define SORSVD_CASE(C)                                                                                         \
+  case C:                                                                                                      \
+    hipLaunchKernelGGL((k_apply_tri_block<C>), grid, block, 0, st, T, rows, (int64_t)LP, Z, cb, vec_ok, skipflag, \
+                       nullptr, nullptr);                                                                            \
+    break;
+    switch (CT) {
+      SORSVD_CASE(1) SORSVD_CASE(2) SORSVD_CASE(3) SORSVD_CASE(4)
+      SORSVD_CASE(5) SORSVD_CASE(6) SORSVD_CASE(7) SORSVD_CASE(8)
+      default: return hipErrorInvalidValue;
+    }
+#undef SORSVD_CASE
+  }
+  return hipGetLastError();
 }
 
 int skinny_rows_per_block(int a_type, int64_t OUT) { return 64 * skinny_rt(a_type, OUT); }
@@ -246,6 +305,7 @@ static int skinny_blocks_per_cu(int CT) {
   return e == hipSuccess ? nb : 0;
 }
 
+// LP: the width of one column block.
 int skinny_slots(int a_type, bool trans, int LP) {
   static std::mutex mu;
   static std::map<std::tuple<int, int, bool, int>, int> cache;

@@ -44,6 +44,13 @@ __device__ inline int xcd_remap_b(int b, int nb) {
   return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
 }
 
+// Contiguous logical ranges per XCD for any workgroup count (see xcd_remap_any
+// of the FP32 / FP64 passes).
+__device__ inline int xcd_remap_any(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 union Frag {
   uint4 u;
   u32x4_t w;
@@ -91,15 +98,16 @@ __device__ inline int out_shift(const H16Scale* sc, const int* cexp, int64_t oro
 }
 
 // Epilogue: with a single contraction split the tiles go straight to the
-// FP64 output T (OUT x LP, or OUT x LP/2 with `fold`, where the products with
-// the high and low parts of the skinny operand, held by the same lane, are
-// added in FP64), with the operand scaling undone for FP16 (BF16 operands are
-// never scaled); otherwise to the FP32 partials P[s].
+// FP64 output T (row stride ldo; CT 16 columns, or CT 8 with `fold`, where
+// the products with the high and low parts of the skinny operand, held by the
+// same lane, are added in FP64), with the operand scaling undone for FP16
+// (BF16 operands are never scaled); otherwise to the FP32 partials P (this
+// split's and column block's, row stride ldp). Both pointers are already
+// offset to the workgroup's column block.
 template <int FMT, bool TRANS, int RT, int CT>
 __device__ inline void store_tiles(const f32x4 (&acc)[RT][CT], int64_t base, int w, int g, int li,
-                                   int64_t OUT, int s, float* P, double* Tout, int fold,
+                                   int64_t OUT, float* P, int64_t ldp, double* Tout, int64_t ldo, int fold,
                                    const H16Scale* sc, const int* cexp) {
-  constexpr int LP = CT * kTile;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -113,21 +121,40 @@ __device__ inline void store_tiles(const f32x4 (&acc)[RT][CT], int64_t base, int
 #pragma unroll
           for (int ct = 0; ct < CT / 2; ++ct) {
             const double v = (double)acc[rt][ct][r] + (double)acc[rt][ct + CT / 2][r];
-            Tout[orow * (LP / 2) + ct * kTile + li] = FMT == kFmtF16 ? ldexp(v, sh) : v;
+            Tout[orow * ldo + ct * kTile + li] = FMT == kFmtF16 ? ldexp(v, sh) : v;
           }
         } else {
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             const double v = (double)acc[rt][ct][r];
-            Tout[orow * LP + ct * kTile + li] = FMT == kFmtF16 ? ldexp(v, sh) : v;
+            Tout[orow * ldo + ct * kTile + li] = FMT == kFmtF16 ? ldexp(v, sh) : v;
           }
         }
       } else {
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-          P[((int64_t)s * OUT + orow) * LP + ct * kTile + li] = acc[rt][ct][r];
+        for (int ct = 0; ct < CT; ++ct) P[orow * ldp + ct * kTile + li] = acc[rt][ct][r];
       }
     }
+}
+
+// Column blocks (ncb > 1): the skinny operand is cut into blocks of CT 16
+// operand rows (its transposed layout holds block cb at rows cb CT 16 ..;
+// with `fold` each block holds its high part followed by its low part), the
+// workgroups of one (split, tile) take neighbouring logical indices (one XCD,
+// A from HBM about once), and block cb writes output columns cb CT 16 .. (cb
+// CT 8 .. with `fold`) of outputs and partial sums ncb blocks wide.
+struct H16Block {
+  int s, tile, cb, u;
+};
+__device__ inline H16Block h16_block(int tiles, int nsplit, int ncb) {
+  const int nb = tiles * nsplit * ncb;
+  const int v = ncb > 1 ? xcd_remap_any((int)blockIdx.x, nb) : xcd_remap_b((int)blockIdx.x, nb);
+  H16Block b;
+  b.cb = v % ncb;
+  b.u = v / ncb;
+  b.s = b.u / tiles;
+  b.tile = b.u % tiles;
+  return b;
 }
 
 
@@ -155,7 +182,7 @@ constexpr int nn_kb(int RT, int LP) {
 template <int FMT, int RT, int CT, bool NRM>
 __global__ void __launch_bounds__(256, 2)
 k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
-         const uint16_t* __restrict__ XT, int64_t ldx, int64_t kchunk, int tiles, int nsplit,
+         const uint16_t* __restrict__ XT, int64_t ldx, int64_t kchunk, int tiles, int nsplit, int ncb,
          int vec_ok, float* __restrict__ P, double* __restrict__ normp, double* __restrict__ Tout,
          int fold, const H16Scale* __restrict__ sc, const int* __restrict__ cexp) {
   constexpr int LP = CT * kTile;
@@ -171,9 +198,10 @@ k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
   __shared__ __attribute__((aligned(16))) uint16_t As[BR * KS];
   __shared__ __attribute__((aligned(16))) uint16_t Xs[LP * KS];
   __shared__ double red[4];
-  const int nb = tiles * nsplit;
-  const int v = xcd_remap_b((int)blockIdx.x, nb);
-  const int s = v / tiles, tile = v % tiles;
+  const H16Block bk = h16_block(tiles, nsplit, ncb);
+  const int s = bk.s, tile = bk.tile;
+  const bool nrm_on = NRM && bk.cb == 0;  // uniform over the workgroup
+  XT += (int64_t)bk.cb * LP * ldx;
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
   const int g = l / kTile, li = l % kTile;
   const int64_t k0 = (int64_t)s * kchunk;
@@ -233,7 +261,7 @@ k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
     if (kb + KB < k1) load_block(kb + KB);
     // the sum of squares of this thread's chunks, read back from LDS while
     // the next block's loads are in flight
-    if constexpr (NRM) {
+    if (nrm_on) {
 #pragma unroll
       for (int i = 0; i < ACH; ++i) {
         const int q = threadIdx.x + 256 * i;
@@ -274,13 +302,15 @@ k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
     }
   }
 
-  store_tiles<FMT, false, RT, CT>(acc, base, w, g, li, OUT, s, P, Tout, fold, sc, cexp);
-  if constexpr (NRM) {
+  const int64_t ldp = (int64_t)ncb * LP, ldo = fold ? ldp / 2 : ldp;
+  store_tiles<FMT, false, RT, CT>(acc, base, w, g, li, OUT, P + (int64_t)s * OUT * ldp + (int64_t)bk.cb * LP, ldp,
+                                  Tout ? Tout + (int64_t)bk.cb * (fold ? LP / 2 : LP) : nullptr, ldo, fold, sc, cexp);
+  if (nrm_on) {
     nrm = wave_sum(nrm);
     __syncthreads();
     if (l == 0) red[w] = nrm;
     __syncthreads();
-    if (threadIdx.x == 0) normp[v] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) normp[bk.u] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
 
@@ -291,7 +321,7 @@ k_h16_nn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
 template <int FMT, int RT, int CT, int KST>
 __global__ void __launch_bounds__(256, 2)
 k_h16_tn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
-         const uint16_t* __restrict__ YT, int64_t ldy, int64_t kchunk, int tiles, int nsplit,
+         const uint16_t* __restrict__ YT, int64_t ldy, int64_t kchunk, int tiles, int nsplit, int ncb,
          int vec_ok, float* __restrict__ P, double* __restrict__ Tout,
          const H16Scale* __restrict__ sc, const int* __restrict__ cexp) {
   constexpr int LP = CT * kTile;
@@ -305,9 +335,9 @@ k_h16_tn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
   __shared__ __attribute__((aligned(16))) uint16_t As[KST * AS];
   __shared__ __attribute__((aligned(16))) uint16_t Ys[LP * YS];
 
-  const int nb = tiles * nsplit;
-  const int v = xcd_remap_b((int)blockIdx.x, nb);
-  const int s = v / tiles, tile = v % tiles;
+  const H16Block bk = h16_block(tiles, nsplit, ncb);
+  const int s = bk.s, tile = bk.tile;
+  YT += (int64_t)bk.cb * LP * ldy;
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
   const int g = l / kTile, li = l % kTile;
   const int64_t k0 = (int64_t)s * kchunk;
@@ -381,7 +411,9 @@ k_h16_tn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
     }
   }
 
-  store_tiles<FMT, true, RT, CT>(acc, base, w, g, li, OUT, s, P, Tout, 0, sc, cexp);
+  const int64_t ldp = (int64_t)ncb * LP;
+  store_tiles<FMT, true, RT, CT>(acc, base, w, g, li, OUT, P + (int64_t)s * OUT * ldp + (int64_t)bk.cb * LP, ldp,
+                                 Tout ? Tout + (int64_t)bk.cb * LP : nullptr, ldp, 0, sc, cexp);
 }
 
 // ------------------------------------------------------------ launch templates
@@ -389,35 +421,38 @@ k_h16_tn(const uint16_t* __restrict__ A, int64_t lda, int64_t OUT, int64_t K,
 // Rows (NN) or columns (TN) of A per workgroup = 64 rt, rt in {1, 2, 4}.
 // With nsplit == 1 the result goes straight to Tout (FP64). normp (NN only):
 // the sums of squares of A, one per workgroup.
+// LP: total operand width (ncb column blocks of LP / ncb).
 template <int FMT, int RT>
 inline hipError_t launch_h16_rt(bool trans, const uint16_t* A, int64_t lda, int64_t OUT, int64_t K,
-                                const uint16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit,
+                                const uint16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit, int ncb,
                                 float* P, double* normp, double* Tout, int fold, const H16Scale* sc,
                                 const int* cexp, hipStream_t st) {
   const int tiles = (int)ceil_div(OUT, 64 * RT);
   if (tiles == 0 || nsplit == 0) return hipSuccess;
   if (trans && normp) return hipErrorInvalidValue;
+  if (ncb < 1 || LP % (ncb * kTile) || (fold && (LP / ncb) % (2 * kTile))) return hipErrorInvalidValue;
+  const int CTB = LP / ncb / kTile;
   // whole 16-byte chunks: aligned rows, and no chunk straddling the end of a
   // row (NN: K % 8 == 0; TN: OUT % 8 == 0)
   const int vec_ok = ((lda * 2) % 16 == 0) && (((uintptr_t)A) % 16 == 0) && ((trans ? OUT : K) % 8 == 0);
   double* To = nsplit == 1 ? Tout : nullptr;
   constexpr int KST = RT >= 4 ? 64 : 128;
-  dim3 grid((unsigned)(tiles * nsplit)), block(256);
+  dim3 grid((unsigned)(tiles * nsplit * ncb)), block(256);
 #define SORSVD_BF(C)                                                                               \
   case C:                                                                                          \
     if (trans)                                                                                     \
       hipLaunchKernelGGL((k_h16_tn<FMT, RT, C, KST>), grid, block, 0, st, A, lda, OUT, K, XT, ldx, \
-                         kchunk, tiles, nsplit, vec_ok, P, To, sc, cexp);                          \
+                         kchunk, tiles, nsplit, ncb, vec_ok, P, To, sc, cexp);                     \
     else if (kchunk % nn_kb(RT, C * kTile) != 0)                                                   \
       return hipErrorInvalidValue;                                                                 \
     else if (normp)                                                                                \
       hipLaunchKernelGGL((k_h16_nn<FMT, RT, C, true>), grid, block, 0, st, A, lda, OUT, K, XT,     \
-                         ldx, kchunk, tiles, nsplit, vec_ok, P, normp, To, fold, sc, cexp);        \
+                         ldx, kchunk, tiles, nsplit, ncb, vec_ok, P, normp, To, fold, sc, cexp);   \
     else                                                                                           \
       hipLaunchKernelGGL((k_h16_nn<FMT, RT, C, false>), grid, block, 0, st, A, lda, OUT, K, XT,    \
-                         ldx, kchunk, tiles, nsplit, vec_ok, P, normp, To, fold, sc, cexp);        \
+                         ldx, kchunk, tiles, nsplit, ncb, vec_ok, P, normp, To, fold, sc, cexp);   \
     break;
-  switch (LP / kTile) {
+  switch (CTB) {
     SORSVD_BF(1) SORSVD_BF(2) SORSVD_BF(3) SORSVD_BF(4) SORSVD_BF(5) SORSVD_BF(6)
     SORSVD_BF(7) SORSVD_BF(8) SORSVD_BF(10) SORSVD_BF(12) SORSVD_BF(14) SORSVD_BF(16)
     default: return hipErrorInvalidValue;
@@ -428,13 +463,13 @@ inline hipError_t launch_h16_rt(bool trans, const uint16_t* A, int64_t lda, int6
 
 template <int FMT>
 inline hipError_t launch_h16_fmt(bool trans, const uint16_t* A, int64_t lda, int64_t OUT, int64_t K,
-                                 const uint16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit, float* P,
-                                 double* normp, double* Tout, int fold, int rt, const H16Scale* sc,
+                                 const uint16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit, int ncb,
+                                 float* P, double* normp, double* Tout, int fold, int rt, const H16Scale* sc,
                                  const int* cexp, hipStream_t st) {
   switch (rt) {
-    case 1: return launch_h16_rt<FMT, 1>(trans, A, lda, OUT, K, XT, ldx, LP, kchunk, nsplit, P, normp, Tout, fold, sc, cexp, st);
-    case 2: return launch_h16_rt<FMT, 2>(trans, A, lda, OUT, K, XT, ldx, LP, kchunk, nsplit, P, normp, Tout, fold, sc, cexp, st);
-    case 4: return launch_h16_rt<FMT, 4>(trans, A, lda, OUT, K, XT, ldx, LP, kchunk, nsplit, P, normp, Tout, fold, sc, cexp, st);
+    case 1: return launch_h16_rt<FMT, 1>(trans, A, lda, OUT, K, XT, ldx, LP, kchunk, nsplit, ncb, P, normp, Tout, fold, sc, cexp, st);
+    case 2: return launch_h16_rt<FMT, 2>(trans, A, lda, OUT, K, XT, ldx, LP, kchunk, nsplit, ncb, P, normp, Tout, fold, sc, cexp, st);
+    case 4: return launch_h16_rt<FMT, 4>(trans, A, lda, OUT, K, XT, ldx, LP, kchunk, nsplit, ncb, P, normp, Tout, fold, sc, cexp, st);
     default: return hipErrorInvalidValue;
   }
 }

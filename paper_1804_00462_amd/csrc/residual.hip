@@ -17,9 +17,18 @@
 // approximation error is then estimated as sqrt(e_stored^2 - that sum / ||A||^2):
 // the rounding error is spread over all n singular directions, so only a
 // fraction (k / n)^2 of it is captured by the rank-k approximation.
+//
+// For k > 128 (W no longer fits LDS) the pass is a tiled product instead: U
+// (m x KP) and W^T = S V^T (KP x n, columns padded to a multiple of 128) are
+// first cast to the MFMA type, then each workgroup forms a 128 x 128 tile
+// (64 x 128 for FP64) of U W^T with the streaming tile body of the passes
+// (U in place of A, W^T as the skinny operand, one column block) and takes
+// the same sums from it in its epilogue.
+#include <algorithm>
 #include <type_traits>
 
 #include "half16.hpp"
+#include "skinny_body.hpp"
 
 namespace sor {
 
@@ -141,6 +150,96 @@ k_residual(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, const do
   }
 }
 
+// ---------------------------------------------------------------------------
+// k > 128.
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_res_cast_u(const double* __restrict__ U, int64_t ldu, int64_t m, int k, int KP, T* __restrict__ Uc) {
+  const int64_t tot = m * KP;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t r = e / KP;
+    const int c = (int)(e % KP);
+    Uc[e] = c < k ? (T)U[r * ldu + c] : T(0);
+  }
+}
+
+// Wt[c][j] = S_c V[j][c] (times 2^e_j with column exponents), zero for c >= k or j >= n.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_res_cast_w(const double* __restrict__ S, const double* __restrict__ V, int64_t ldv, int64_t n, int k, int KP,
+             int64_t npad, const int* __restrict__ cexp, T* __restrict__ Wt) {
+  const int64_t tot = (int64_t)KP * npad;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int c = (int)(e / npad);
+    const int64_t j = e % npad;
+    T w = T(0);
+    if (c < k && j < n) {
+      double x = S[c] * V[j * ldv + c];
+      if (cexp) x = ldexp(x, cexp[j]);
+      w = (T)x;
+    }
+    Wt[e] = w;
+  }
+}
+
+// Epilogue of the tiled residual: (a - a_hat)^2 and the rounding noise of a.
+template <typename TA>
+struct ResEpi {
+  const TA* A;
+  int64_t lda, n, c0;
+  const int* cexp;
+  double res, noise;
+  __device__ void operator()(int64_t row, int c, double v) {
+    const int64_t col = c0 + c;
+    if (col >= n) return;
+    const TA* p = A + row * lda + col;
+    if constexpr (std::is_same<TA, f16_word>::value) {
+      const int e = cexp ? cexp[col] : 0;
+      const double d = load_a<TA>(p) - v;
+      res += ldexp(d * d, -2 * e);
+      noise += ldexp(f16_noise(p->bits), -2 * e);
+    } else {
+      const double d = load_a<TA>(p) - v;
+      res += d * d;
+      if constexpr (sizeof(TA) == 2) noise += bf16_noise(*p);
+    }
+  }
+};
+
+template <typename TA, typename T>
+__global__ void __launch_bounds__(256, 2)
+k_residual_wide(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, const T* __restrict__ Uc, int KP,
+                const T* __restrict__ Wt, int64_t npad, int tiles, int ncb, double* __restrict__ part,
+                const int* __restrict__ cexp, typename Traits<T>::acc_t* pnull, double* dnull) {
+  constexpr int RT = sizeof(T) == 8 ? 1 : 2;
+  constexpr int CT = 8;
+  __shared__ T Xs[xs_elems<T, CT>()];
+  __shared__ double red[2][4];
+  const int nb = tiles * ncb;
+  const int v = xcd_remap_any((int)blockIdx.x, nb);
+  const int cb = v % ncb, tile = v / ncb;
+  const int64_t c0 = (int64_t)cb * CT * kTile;
+  ResEpi<TA> epi{A, lda, n, c0, cexp, 0.0, 0.0};
+  const int vec_ok = ((KP * (int64_t)sizeof(T)) % 16 == 0) && (((uintptr_t)Uc) % 16 == 0);
+  // (pnull, dnull: null pointers taken as arguments; constant nulls there crash this compiler)
+  skinny_tile<T, false, RT, CT, sizeof(T) == 4 ? 2 : 1, ResEpi<TA>>(Uc, KP, m, 0, KP, Wt + c0, npad,
+                                                                     (int64_t)tile * 64 * RT, vec_ok, pnull,
+                                                                     dnull, 0, dnull, Xs, &red[0][0], 0,
+                                                                     CT * kTile, 0, &epi);
+  const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const double res = wave_sum(epi.res), noise = wave_sum(epi.noise);
+  if (l == 0) {
+    red[0][wv] = res;
+    red[1][wv] = noise;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * (int64_t)v] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    part[2 * (int64_t)v + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
 struct ResInfo {  // the leading fields of the result record
   double a_fro;
   double err_fro;
@@ -190,11 +289,61 @@ int64_t residual_row_groups(int64_t m, int64_t n) {
 
 int64_t residual_parts(int64_t m, int64_t n) { return ceil_div(n, kResCols) * residual_row_groups(m, n); }
 
+static int64_t res_wide_tiles(int a_type, int64_t m) { return ceil_div(m, a_type == 0 ? 64 : 128); }
+
+// Scratch of launch_residual: the partial sums, and for KP > 128 the cast
+// operands.
+size_t residual_ws_bytes(int a_type, int64_t m, int64_t n, int KP) {
+  if (KP <= kResCols) return (size_t)2 * residual_parts(m, n) * 8;
+  const int64_t npad = round_up(n, kResCols);
+  const size_t es = a_type == 0 ? 8 : 4;
+  const int64_t parts = res_wide_tiles(a_type, m) * (npad / kResCols);
+  return round_up((int64_t)2 * parts * 8, 256) + round_up(m * KP * (int64_t)es, 256) +
+         round_up((int64_t)KP * npad * (int64_t)es, 256);
+}
+
+template <typename TA, typename T>
+static hipError_t launch_residual_wide(const TA* A, int64_t lda, int64_t m, int64_t n, const double* U, int64_t ldu,
+                                       const double* S, const double* V, int64_t ldv, int k, int KP, void* ws,
+                                       int64_t tiles, void* info, hipStream_t st, const int* cexp) {
+  const int64_t npad = round_up(n, kResCols);
+  const int ncb = (int)(npad / kResCols);
+  const int64_t parts = tiles * ncb;
+  double* part = reinterpret_cast<double*>(ws);
+  T* Uc = reinterpret_cast<T*>((char*)ws + round_up(2 * parts * 8, 256));
+  T* Wt = reinterpret_cast<T*>((char*)Uc + round_up(m * KP * (int64_t)sizeof(T), 256));
+  hipLaunchKernelGGL((k_res_cast_u<T>), dim3((unsigned)std::min<int64_t>(4096, ceil_div(m * KP, 256))), dim3(256), 0,
+                     st, U, ldu, m, k, KP, Uc);
+  hipLaunchKernelGGL((k_res_cast_w<T>), dim3((unsigned)std::min<int64_t>(4096, ceil_div((int64_t)KP * npad, 256))),
+                     dim3(256), 0, st, S, V, ldv, n, k, KP, npad, cexp, Wt);
+  hipLaunchKernelGGL((k_residual_wide<TA, T>), dim3((unsigned)parts), dim3(256), 0, st, A, lda, m, n, Uc, KP, Wt,
+                     npad, (int)tiles, ncb, part, cexp, nullptr, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, st, part, parts, (ResInfo*)info);
+  return hipGetLastError();
+}
+
 // a_type: 0 FP64, 1 FP32, 2 BF16, 4 FP16 (cexp: its column exponents, or
-// null). part: 2 residual_parts(m, n) doubles.
+// null). part: residual_ws_bytes(a_type, m, n, KP) bytes of scratch.
 hipError_t launch_residual(int a_type, const void* A, int64_t lda, int64_t m, int64_t n, const double* U,
                            int64_t ldu, const double* S, const double* V, int64_t ldv, int k, int KP, double* part,
                            void* info, hipStream_t st, const int* cexp) {
+  if (KP > kResCols) {
+    if (KP % kTile) return hipErrorInvalidValue;
+    const int64_t tiles = res_wide_tiles(a_type, m);
+    if (a_type == 0)
+      return launch_residual_wide<double, double>((const double*)A, lda, m, n, U, ldu, S, V, ldv, k, KP, part, tiles,
+                                                  info, st, nullptr);
+    if (a_type == 1)
+      return launch_residual_wide<float, float>((const float*)A, lda, m, n, U, ldu, S, V, ldv, k, KP, part, tiles,
+                                                info, st, nullptr);
+    if (a_type == 4)
+      return launch_residual_wide<f16_word, float>((const f16_word*)A, lda, m, n, U, ldu, S, V, ldv, k, KP, part,
+                                                   tiles, info, st, cexp);
+    return launch_residual_wide<bf16_t, float>((const bf16_t*)A, lda, m, n, U, ldu, S, V, ldv, k, KP, part, tiles,
+                                               info, st, nullptr);
+  }
   const dim3 grid((unsigned)ceil_div(n, kResCols), (unsigned)residual_row_groups(m, n));
   if (a_type == 0) {
     const size_t shm = (size_t)KP * kResLd * sizeof(double);

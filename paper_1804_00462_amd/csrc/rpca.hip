@@ -8,16 +8,20 @@
 //   W' = X - S + Y / mu'   (the next SOR-SVD input, mu' the next penalty)
 // k_rpca_step does all of it in one pass over the m x n arrays: a workgroup
 // owns a 32 x 32 tile, stages U's 32 rows (times the thresholded z) and V's
-// 32 rows transposed in LDS, forms its L tile with FP64 FMAs (l <= 128
-// terms) and applies the updates; the squares of R are summed per workgroup
-// in FP64 (fixed order) for the stopping test.
+// 32 rows transposed in LDS, kRpcaChunk terms at a time, forms its L tile
+// with FP64 FMAs (the l terms added in order) and applies the updates; the
+// squares of R are summed per workgroup in FP64 (fixed order) for the
+// stopping test.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace sor {
 
 namespace {
 
-constexpr int kRT = 32;  // tile rows and columns
+constexpr int kRT = 32;          // tile rows and columns
+constexpr int kRpcaChunk = 128;  // terms of L staged in LDS at a time
 
 // Per-block partial sums of x^2 and maxima of |x| over an m x n array.
 __global__ void __launch_bounds__(256) k_rpca_stats(const double* __restrict__ X, int64_t ldx, int64_t m,
@@ -74,23 +78,28 @@ __global__ void __launch_bounds__(256) k_rpca_step(const double* __restrict__ X,
                                                    double* __restrict__ S, int64_t ld, double* __restrict__ Y,
                                                    double* __restrict__ W, double* __restrict__ rpart) {
   extern __shared__ double sm[];
-  double* Us = sm;              // l x 32: Us[t][r] = U[r0 + r][t] shrink(z_t)
-  double* Vs = sm + l * kRT;    // l x 32: Vs[t][c] = V[c0 + c][t]
+  const int lc = min(l, kRpcaChunk);
+  double* Us = sm;              // lc x 32: Us[t][r] = U[r0 + r][t0 + t] shrink(z_{t0 + t})
+  double* Vs = sm + lc * kRT;   // lc x 32: Vs[t][c] = V[c0 + c][t0 + t]
   __shared__ double red[4];
   const int64_t r0 = (int64_t)blockIdx.y * kRT, c0 = (int64_t)blockIdx.x * kRT;
   const int tx = threadIdx.x % kRT, ty = threadIdx.x / kRT;
-  for (int i = threadIdx.x; i < l * kRT; i += 256) {
-    const int t = i % l, r = i / l;  // consecutive threads read consecutive t of one row
-    const double zt = fmax(z[t] - inv_mu, 0.0);
-    Us[t * kRT + r] = r0 + r < m ? U[(r0 + r) * l + t] * zt : 0.0;
-    Vs[t * kRT + r] = c0 + r < n ? V[(c0 + r) * l + t] : 0.0;
-  }
-  __syncthreads();
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int t = 0; t < l; ++t) {
-    const double v = Vs[t * kRT + tx];
+  for (int t0 = 0; t0 < l; t0 += lc) {
+    const int nt = min(lc, l - t0);
+    if (t0 > 0) __syncthreads();  // the previous chunk has been read
+    for (int i = threadIdx.x; i < nt * kRT; i += 256) {
+      const int t = i % nt, r = i / nt;  // consecutive threads read consecutive t of one row
+      const double zt = fmax(z[t0 + t] - inv_mu, 0.0);
+      Us[t * kRT + r] = r0 + r < m ? U[(r0 + r) * l + t0 + t] * zt : 0.0;
+      Vs[t * kRT + r] = c0 + r < n ? V[(c0 + r) * l + t0 + t] : 0.0;
+    }
+    __syncthreads();
+    for (int t = 0; t < nt; ++t) {
+      const double v = Vs[t * kRT + tx];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] += Us[t * kRT + ty + 8 * i] * v;
+      for (int i = 0; i < 4; ++i) acc[i] += Us[t * kRT + ty + 8 * i] * v;
+    }
   }
   double rsq = 0.0;
   const int64_t c = c0 + tx;
@@ -156,7 +165,7 @@ hipError_t launch_rpca_step(const double* X, int64_t ldx, int64_t m, int64_t n, 
                             double* L, double* S, int64_t ld, double* Y, double* W, double* rpart,
                             hipStream_t st) {
   const dim3 grid((unsigned)ceil_div(n, kRT), (unsigned)ceil_div(m, kRT));
-  const size_t shm = (size_t)2 * l * kRT * sizeof(double);
+  const size_t shm = (size_t)2 * std::min(l, kRpcaChunk) * kRT * sizeof(double);
   hipLaunchKernelGGL(k_rpca_step, grid, dim3(256), shm, st, X, ldx, m, n, U, V, z, l, inv_mu, thr_s, mu,
                      inv_mu_next, L, S, ld, Y, W, rpart);
   return hipGetLastError();

@@ -14,6 +14,8 @@
 // map, so any permutation of the contraction inside a step is harmless.
 // Loads for later steps are issued before the MFMAs of the current one.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace sor {
@@ -67,6 +69,15 @@ __device__ inline int xcd_remap(int b, int nb) {
   return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
 }
 
+// Workgroup b of nb, dispatched to XCD b % 8, takes logical index v from a
+// contiguous range per XCD (any nb): XCD x receives nb / 8 workgroups, plus
+// one when x < nb % 8, and numbers them in dispatch order. Logical neighbours
+// therefore run on the same XCD at about the same time and share its L2.
+__device__ inline int xcd_remap_any(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 
 // LDS of the staged skinny operand: two buffers (the next step's rows are
 // stored while the current ones feed the MFMAs) of KS rows, row stride LP + 2.
@@ -77,20 +88,29 @@ template <typename T, int CT>
 constexpr int xs_elems() { return 2 * 4 * Traits<T>::VK * (CT * kTile + 2); }
 
 // Output: if Tout != null, out[r][c] -> Tout[r * ldo + c] in FP64 (c < LP);
-// else -> P[r * LP + c] in the accumulator type (a partial sum). Tout may
+// else -> P[r * ldp + c] in the accumulator type (a partial sum). Tout may
 // alias A (the in-place T <- T R^{-1}): the workgroup writes only its own
 // output rows, after it has read all of its input rows. If nrm != null the
 // FP64 sum of squares of the A elements this workgroup read is stored there.
 // Xs: LDS of xs_elems<T, CT>() elements; red: LDS of 4 doubles.
 // PD: A fragments are loaded PD steps ahead (1 or 2). tri (FP64 NN only): X is
-// upper triangular (X[k][c] = 0 for k > c, as R^{-1}), so the MFMAs of a step
-// whose contraction indices all lie below a 16-column output tile are skipped
-// (their products are exact zeros).
-template <typename T, bool TRANS, int RT, int CT, int PD = (sizeof(T) == 4 ? 2 : 1)>
-__device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t k0, int64_t k1,
+// upper triangular (X[k][c0 + c] = 0 for k > c0 + c, as R^{-1}, where X is
+// the column block starting at column c0 of the whole operand), so the MFMAs
+// of a step whose contraction indices all lie below a 16-column output tile
+// are skipped (their products are exact zeros). ldp: row stride of the
+// partial sums P (the width of the whole output when X is one column block).
+// Epi (optional): called as epi(orow, c, value) for every output row orow <
+// OUT and column c of the tile instead of storing it (Tout and P unused).
+struct NoEpi {
+  __device__ void operator()(int64_t, int, double) const {}
+};
+
+template <typename T, bool TRANS, int RT, int CT, int PD = (sizeof(T) == 4 ? 2 : 1), typename Epi = NoEpi>
+__device__ __attribute__((always_inline)) inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t k0, int64_t k1,
                                    const T* __restrict__ X, int64_t ldx, int64_t base, int vec_ok,
                                    typename Traits<T>::acc_t* P, double* Tout, int64_t ldo,
-                                   double* nrm_out, T* Xs, double* red, int tri = 0) {
+                                   double* nrm_out, T* Xs, double* red, int tri = 0,
+                                   int64_t ldp = CT * kTile, int64_t c0 = 0, Epi* epi = nullptr) {
   using Tr = Traits<T>;
   using accv = typename Tr::accv;
   constexpr int LP = CT * kTile;
@@ -197,7 +217,7 @@ __device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         if constexpr (sizeof(T) == 8 && !TRANS)
-          if (tri && kb >= (int64_t)(ct + 1) * kTile) continue;
+          if (tri && kb - c0 >= (int64_t)(ct + 1) * kTile) continue;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Tr::mfma(a[rt][j], bq[j & 1][ct], acc[rt][ct]);
       }
@@ -229,8 +249,9 @@ __device__ inline void skinny_tile(const T* A, int64_t lda, int64_t OUT, int64_t
       for (int r = 0; r < 4; ++r) {
         const int64_t orow = base + (int64_t)(w * RT + rt) * kTile + Tr::out_row(l, r);
         if (orow < OUT) {
-          if (Tout) Tout[orow * ldo + ct * kTile + li] = (double)acc[rt][ct][r];
-          else P[orow * LP + ct * kTile + li] = acc[rt][ct][r];
+          if constexpr (!std::is_same<Epi, NoEpi>::value) (*epi)(orow, ct * kTile + li, (double)acc[rt][ct][r]);
+          else if (Tout) Tout[orow * ldo + ct * kTile + li] = (double)acc[rt][ct][r];
+          else P[orow * ldp + ct * kTile + li] = acc[rt][ct][r];
         }
       }
     }

@@ -23,11 +23,13 @@ namespace sor {
 hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
                              const double* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              double* P, double* normp, const int* skipflag, hipStream_t st,
-                             double* Tout = nullptr, bool tri = false);
+                             double* Tout = nullptr, bool tri = false, int ncb = 1);
 hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OUT, int64_t K,
                              const float* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              float* P, double* normp, const int* skipflag, hipStream_t st,
-                             double* Tout = nullptr);
+                             double* Tout = nullptr, int ncb = 1);
+hipError_t launch_apply_tri_blocks(double* T, int64_t rows, int LP, const double* Z, int ncb,
+                                   const int* skipflag, hipStream_t st);
 hipError_t launch_reduce_f64(const double* P, int64_t OUT, int LP, int nsplit, double* out,
                              int64_t ldo, int ncols, hipStream_t st, const int* skipflag = nullptr);
 hipError_t launch_reduce_f32(const float* P, int64_t OUT, int LP, int nsplit, double* out,
@@ -57,17 +59,17 @@ hipError_t launch_rpca_nnz(const double* S, int64_t ld, int64_t m, int64_t n, do
 int skinny_step(int a_type);
 // gemm_bf16.hip (16-bit passes; FP16 instantiations in gemm_f16.hip)
 hipError_t launch_h16_pass(int fmt, bool trans, const uint16_t* A, int64_t lda, int64_t OUT, int64_t K,
-                           const uint16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit, float* P,
+                           const uint16_t* XT, int64_t ldx, int LP, int64_t kchunk, int nsplit, int ncb, float* P,
                            double* normp, double* Tout, int fold, int rt, const H16Scale* sc, const int* cexp,
                            hipStream_t st);
 int h16_slots(int fmt, bool trans, int rt, int LP);
 int bf16_step(bool trans, int rt, int LP);
-hipError_t launch_cast_h16_t(int fmt, const double* Q, int64_t rows, int LP, int64_t ldt, int permute,
+hipError_t launch_cast_h16_t(int fmt, const double* Q, int64_t rows, int LP, int ncb, int64_t ldt, int permute,
                              int with_lo, uint16_t* QT, const H16Scale* sc, const int* cexp, hipStream_t st);
 hipError_t launch_reduce_fold(const float* P, int64_t OUT, int LP2, int nsplit, double* out,
-                              int64_t ldo, int ncols, hipStream_t st);
+                              int64_t ldo, int ncols, int cbw, hipStream_t st);
 hipError_t launch_reduce_h16(bool trans, const float* P, int64_t OUT, int LP2, int nsplit, double* out, int64_t ldo,
-                             int ncols, int fold, const H16Scale* sc, const int* cexp, hipStream_t st);
+                             int ncols, int fold, int cbw, const H16Scale* sc, const int* cexp, hipStream_t st);
 hipError_t launch_h16_scale(const int* cexp, int64_t n, int shift, H16Scale* sc, int* flags, hipStream_t st);
 // philox.hip
 hipError_t launch_omega_bf16_t(uint64_t seed, int64_t rows, int64_t cols, bf16_t* out,
@@ -105,16 +107,45 @@ hipError_t launch_mlp_adam(float* P, const float* G, float* M, float* V, int64_t
 hipError_t launch_features(const double* sv, int l, float* feat, hipStream_t st);
 // residual.hip
 int64_t residual_parts(int64_t m, int64_t n);
+size_t residual_ws_bytes(int a_type, int64_t m, int64_t n, int KP);
 hipError_t launch_residual(int a_type, const void* A, int64_t lda, int64_t m, int64_t n, const double* U,
                            int64_t ldu, const double* S, const double* V, int64_t ldv, int k, int KP, double* part,
                            void* info, hipStream_t st, const int* cexp);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+// wide.hip (l > 128)
+size_t chol_wide_bytes(int LP);
+hipError_t launch_chol_wide(double* G, int LP, int l, int64_t rows, int mode, double* Z, int* skip3, void* info,
+                            void* scratch, hipStream_t st);
+size_t jacobi_wide_bytes(int l);
+hipError_t launch_jacobi_wide(const double* M, int LPm, int l, int k, int max_sweeps, double* Ut, double* sv,
+                              double* Vt, int ldk, void* scratch, void* info, hipStream_t st, double tol);
 
 namespace {
 
-constexpr int kMaxLP = 128;        // widest sketch handled by the pass kernels
+constexpr int kMaxLP = 1024;       // widest sketch
+constexpr int kNarrowLP = 128;     // widest sketch of the one-workgroup QR factor and core SVD
+constexpr int kBlk = 128;          // widest column block of the pass kernels
+constexpr int kProbeL = 128;       // sketch width of the (k, q) predictor's probe
+constexpr int kWideSweeps = 16;    // default sweep cap of the core SVD of the method for l > 128
+constexpr int kWideMaxSweeps = 64; // largest sweep cap for l > 128
 constexpr int kSignBlocks = 1024;  // max row blocks of the sign search
 constexpr size_t kAlign = 256;
+
+// Padded width of a skinny operand of w columns and its column blocks: up to
+// 128 columns one block (w rounded up to 16); wider operands ncb blocks of
+// equal width, a multiple of 16 up to 128 (the padding columns are zero).
+void width_blocks(int64_t w, int64_t* WP, int* ncb) {
+  const int64_t w16 = round_up(w, kTile);
+  if (w16 <= kBlk) {
+    *WP = w16;
+    *ncb = 1;
+    return;
+  }
+  const int64_t nb = ceil_div(w16, kBlk);
+  const int64_t ct = ceil_div(w16 / kTile, nb);
+  *WP = nb * ct * kTile;
+  *ncb = (int)nb;
+}
 
 struct Split {
   int64_t kchunk = 0;
@@ -131,10 +162,11 @@ struct Split {
 // sized without a device also fits.
 Split choose_split(int64_t OUT, int64_t K, int rows_per_block, int KS, int LP, int es_a,
                    int acc_bytes, int forced, int min_steps = 8, int part_div = 8, int slots = 0,
-                   int64_t target = 2048) {
+                   int64_t target = 2048, int ncb = 1) {
   Split sp;
   if (K <= 0) { sp.kchunk = KS; sp.nsplit = 1; return sp; }
-  const int64_t tiles = std::max<int64_t>(1, ceil_div(OUT, rows_per_block));
+  // (ncb column blocks: workgroups per split = row tiles x ncb)
+  const int64_t tiles = std::max<int64_t>(1, ceil_div(OUT, rows_per_block)) * ncb;
   int64_t s = std::max<int64_t>(1, ceil_div(target, tiles));
   s = std::min<int64_t>(s, std::max<int64_t>(1, K / ((int64_t)min_steps * KS)));
   s = std::min<int64_t>(s, std::max<int64_t>(1, (K * es_a) / ((int64_t)part_div * LP * acc_bytes)));
@@ -172,6 +204,9 @@ struct Layout {
 struct Plan {
   int a_type;
   int64_t m, n, k, l, LP, KP;
+  int ncb, ncbk;  // column blocks of the LP-wide and KP-wide operands (1 up to 128 columns)
+  int64_t CB;     // width of one LP column block
+  bool wide;      // l > 128: blocked QR factor and core SVD (wide.hip)
   int q;
   int es;
   int max_sweeps;
@@ -192,6 +227,7 @@ struct Plan {
   size_t off_t2p;  // pass_eff: the last orbit product before its QR (n x LP FP64)
   size_t off_hsc;  // FP16 A: the operand scale record (H16Scale)
   size_t off_rlog; // core SVD: rotation log from which V is rebuilt (0: V kept in the Jacobi kernel)
+  size_t off_wchol, off_wjac;  // wide: scratch of the blocked factor and of the blocked Jacobi
   size_t total;
 };
 
@@ -218,11 +254,18 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   if (a_type == SORSVD_DIAG && o && o->residual) return SORSVD_EUNSUPPORTED;
   const int64_t l = (o && o->l > 0) ? o->l : k;
   if (k > l || l > std::min(m, n)) return SORSVD_EINVAL;
-  const int64_t LP = round_up(l, kTile), KP = round_up(k, kTile);
-  if (LP > kMaxLP) return SORSVD_EUNSUPPORTED;
+  if (l > kMaxLP) return SORSVD_EUNSUPPORTED;
+  int64_t LP, KP;
+  int ncb, ncbk;
+  width_blocks(l, &LP, &ncb);
+  width_blocks(k, &KP, &ncbk);
   p->a_type = a_type; p->m = m; p->n = n; p->k = k; p->l = l; p->LP = LP; p->KP = KP; p->q = q;
+  p->ncb = ncb; p->ncbk = ncbk; p->CB = LP / ncb;
+  p->wide = l > kNarrowLP;
   p->es = elem_size(a_type);
-  p->max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
+  p->max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : (p->wide ? kWideSweeps : 40);
+  if (p->wide && p->max_sweeps > kWideMaxSweeps) return SORSVD_EINVAL;
+  const int CB = (int)p->CB;
   p->fmt = a_type == SORSVD_BF16 ? kFmtBF16 : (a_type == SORSVD_F16 ? kFmtF16 : -1);
   p->cexp = (o && a_type == SORSVD_F16) ? (const int*)o->col_exp : nullptr;
   p->refine = (h16 && o && o->refine) ? 1 : 0;
@@ -239,42 +282,43 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   // columns when l <= 64.
   const int tile_opt = o ? o->tile : 0;
   p->rt_nn = tile_opt ? tile_opt : 2;
-  p->rt_tn = tile_opt ? tile_opt : (LP <= 64 ? 4 : 2);
-  p->rt_proj = tile_opt ? std::min(tile_opt, p->refine && LP > 32 ? 2 : 4) : 2;
+  p->rt_tn = tile_opt ? tile_opt : (CB <= 64 ? 4 : 2);
+  p->rt_proj = tile_opt ? std::min(tile_opt, p->refine && CB > 32 ? 2 : 4) : 2;
   const int t64 = a_type == SORSVD_DIAG ? SORSVD_F64 : a_type;
   const int rpb_m = h16 ? 64 * p->rt_nn : skinny_rows_per_block(t64, m);
   const int rpb_n = h16 ? 64 * p->rt_tn : skinny_rows_per_block(t64, n);
-  const int ks_nn = h16 ? bf16_step(false, p->rt_nn, (int)LP) : ks;
-  const int ks_tn = h16 ? bf16_step(true, p->rt_tn, (int)LP) : ks;
+  const int ks_nn = h16 ? bf16_step(false, p->rt_nn, CB) : ks;
+  const int ks_tn = h16 ? bf16_step(true, p->rt_tn, CB) : ks;
   const bool skinny_pass = a_type == SORSVD_F32 || a_type == SORSVD_F64;
   const int tcode = a_type == SORSVD_F32 ? 1 : 0;
   // 16-bit passes aim at one wave of resident workgroups (see A^T Y below)
-  const int nn_slots = skinny_pass ? skinny_slots(tcode, false, (int)LP)
-                                   : (h16 ? h16_slots(p->fmt, false, p->rt_nn, (int)LP) : 0);
+  const int nn_slots = skinny_pass ? skinny_slots(tcode, false, CB)
+                                   : (h16 ? h16_slots(p->fmt, false, p->rt_nn, CB) : 0);
   p->nn = choose_split(m, n, rpb_m, ks_nn, (int)LP, p->es, acc, forced, 8, 8, nn_slots,
-                       (h16 && nn_slots > 0) ? nn_slots : 2048);
+                       (h16 && nn_slots > 0) ? nn_slots : 2048, ncb);
   // 16-bit A^T Y: a workgroup streams 64 rt whole columns of A with its
   // contraction rows staged through LDS, so one wave of resident workgroups
   // already keeps HBM busy; more splits only add partial sums to write and
   // reduce (measured at 200000 x 4000, l = 64: 6.2 TB/s at 512 workgroups,
   // 5.0 TB/s at 2000)
-  const int tn_slots = skinny_pass ? skinny_slots(tcode, true, (int)LP)
-                                   : (h16 ? h16_slots(p->fmt, true, p->rt_tn, (int)LP) : 0);
+  const int tn_slots = skinny_pass ? skinny_slots(tcode, true, CB)
+                                   : (h16 ? h16_slots(p->fmt, true, p->rt_tn, CB) : 0);
   p->tn = choose_split(n, m, rpb_n, ks_tn, (int)LP, p->es, acc, forced, 8, 8, tn_slots,
-                       (h16 && tn_slots > 0) ? tn_slots : 2048);
+                       (h16 && tn_slots > 0) ? tn_slots : 2048, ncb);
   // pass-efficient core matrix on 16-bit A with refinement: the last orbit
   // product takes [Q1 hi | Q1 lo] (2 LP columns), so that T2 = A^T Q1, from
   // which M is formed, carries Q1 to ~2^-17 as the projection pass would
   p->rt_tnb = tile_opt ? tile_opt : 2;
   if (h16 && p->pass_eff && p->refine) {
-    const int tnb_slots = h16_slots(p->fmt, true, p->rt_tnb, 2 * (int)LP);
-    p->tnb = choose_split(n, m, 64 * p->rt_tnb, bf16_step(true, p->rt_tnb, 2 * (int)LP), 2 * (int)LP, p->es, acc,
-                          forced, 8, 8, tnb_slots, tnb_slots > 0 ? tnb_slots : 2048);
+    const int tnb_slots = h16_slots(p->fmt, true, p->rt_tnb, 2 * CB);
+    p->tnb = choose_split(n, m, 64 * p->rt_tnb, bf16_step(true, p->rt_tnb, 2 * CB), 2 * (int)LP, p->es, acc,
+                          forced, 8, 8, tnb_slots, tnb_slots > 0 ? tnb_slots : 2048, ncb);
   }
   const int LPproj = (int)LP * (p->refine ? 2 : 1);
-  const int proj_slots = h16 ? h16_slots(p->fmt, false, p->rt_proj, LPproj) : 0;
-  p->projb = choose_split(m, n, 64 * p->rt_proj, h16 ? bf16_step(false, p->rt_proj, LPproj) : 128, LPproj, p->es,
-                          acc, forced, 8, 8, proj_slots, proj_slots > 0 ? proj_slots : 2048);
+  const int CBproj = CB * (p->refine ? 2 : 1);
+  const int proj_slots = h16 ? h16_slots(p->fmt, false, p->rt_proj, CBproj) : 0;
+  p->projb = choose_split(m, n, 64 * p->rt_proj, h16 ? bf16_step(false, p->rt_proj, CBproj) : 128, LPproj, p->es,
+                          acc, forced, 8, 8, proj_slots, proj_slots > 0 ? proj_slots : 2048, ncb);
   // l x l products over a tall FP64 operand: many short splits, with partial
   // sums up to the size of the operand (at 20000 x 100 the Gram product then
   // runs 250 workgroups instead of 158: 26 -> 21 us)
@@ -282,10 +326,10 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   const int rpbg = skinny_rows_per_block(SORSVD_F64, LP);
   // one wave of resident workgroups: more splits only add partial sums
   // (l x l FP64 each) to write and reduce
-  const int gslots = skinny_slots(SORSVD_F64, true, (int)LP);
+  const int gslots = skinny_slots(SORSVD_F64, true, CB);
   const int64_t gtarget = gslots > 0 ? gslots : 2048;
-  p->gram_m = choose_split(LP, m, rpbg, ks64, (int)LP, 8, 8, 0, 4, 1, gslots, gtarget);
-  p->gram_n = choose_split(LP, n, rpbg, ks64, (int)LP, 8, 8, 0, 4, 1, gslots, gtarget);
+  p->gram_m = choose_split(LP, m, rpbg, ks64, (int)LP, 8, 8, 0, 4, 1, gslots, gtarget, ncb);
+  p->gram_n = choose_split(LP, n, rpbg, ks64, (int)LP, 8, 8, 0, 4, 1, gslots, gtarget, ncb);
   p->proj = p->gram_m;
   p->nn_blocks = (int)(ceil_div(m, rpb_m) * p->nn.nsplit);
   if (h16 && p->rt_nn != 1 && p->rt_nn != 2 && p->rt_nn != 4) return SORSVD_EINVAL;
@@ -313,15 +357,17 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->off_m = L.take((size_t)LP * LP * 8);
   p->off_ut = L.take((size_t)LP * KP * 8);
   p->off_vt = L.take((size_t)LP * KP * 8);
-  p->off_vg = L.take((size_t)LP * kMaxLP * 8);  // Jacobi's V: l columns of up to kMaxLP padded rows
+  p->off_vg = L.take(p->wide ? 0 : (size_t)LP * kNarrowLP * 8);  // Jacobi's V: l columns of up to 128 padded rows
   p->off_pval = L.take((size_t)kSignBlocks * KP * 8);
   p->off_pidx = L.take((size_t)kSignBlocks * KP * 8);
   p->off_sgn = L.take((size_t)KP * 8);
   p->off_skip = L.take(64);
-  p->off_res = p->residual ? L.take((size_t)2 * residual_parts(m, n) * 8) : 0;
+  p->off_res = p->residual ? L.take(residual_ws_bytes(a_type == SORSVD_F64 ? 0 : (a_type == SORSVD_F32 ? 1 : (a_type == SORSVD_F16 ? 4 : 2)), m, n, (int)KP)) : 0;
   p->off_t2p = p->pass_eff ? L.take((size_t)n * LP * 8) : 0;
   p->off_hsc = a_type == SORSVD_F16 ? L.take(sizeof(H16Scale)) : 0;
-  p->off_rlog = jacobi_uses_log((int)l) ? L.take(jacobi_log_bytes((int)l, p->max_sweeps)) : 0;
+  p->off_rlog = (!p->wide && jacobi_uses_log((int)l)) ? L.take(jacobi_log_bytes((int)l, p->max_sweeps)) : 0;
+  p->off_wchol = p->wide ? L.take(chol_wide_bytes((int)LP)) : 0;
+  p->off_wjac = p->wide ? L.take(jacobi_wide_bytes((int)l)) : 0;
   p->total = L.total;
   return SORSVD_OK;
 }
@@ -342,6 +388,8 @@ template <typename T> T* at(void* ws, size_t off) { return reinterpret_cast<T*>(
 // shift: its columns are then orthonormal to ~cond(T)^2 u, which is a
 // well-conditioned basis of the same span, and only the span enters the next
 // product. The bases that form M and the lifted factors take both steps.
+// For l > 128 the factor is the blocked one of wide.hip and T R^{-1} is formed
+// column block by column block (launch_apply_tri_blocks); the steps are the same.
 int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void* ws, hipStream_t st,
                  bool final = true) {
   double* P = at<double>(ws, p.off_p);
@@ -354,11 +402,30 @@ int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void
     if (!final && it == 1) continue;
     const int* skip = it == 2 ? skip3 : nullptr;
     SORSVD_TRY(launch_skinny_f64(true, T, LP, LP, rows, T, LP, LP, gram.kchunk, gram.nsplit, P,
-                                 nullptr, skip, st));
+                                 nullptr, skip, st, nullptr, false, p.ncb));
     SORSVD_TRY(launch_reduce_f64(P, LP, LP, gram.nsplit, G, LP, LP, st, skip));
-    SORSVD_TRY(launch_chol_inv(G, LP, (int)p.l, rows, it, Rinv, skip3, info, st));
-    SORSVD_TRY(launch_skinny_f64(false, T, LP, rows, LP, Rinv, LP, LP, LP, 1, T, nullptr, skip, st, nullptr,
-                                 true));
+    if (p.wide) {
+      SORSVD_TRY(launch_chol_wide(G, LP, (int)p.l, rows, it, Rinv, skip3, info, at<void>(ws, p.off_wchol), st));
+      SORSVD_TRY(launch_apply_tri_blocks(T, rows, LP, Rinv, p.ncb, skip, st));
+    } else {
+      SORSVD_TRY(launch_chol_inv(G, LP, (int)p.l, rows, it, Rinv, skip3, info, st));
+      SORSVD_TRY(launch_skinny_f64(false, T, LP, rows, LP, Rinv, LP, LP, LP, 1, T, nullptr, skip, st, nullptr,
+                                   true));
+    }
+  }
+  return SORSVD_OK;
+}
+
+// Core SVD of M (l x l in an LP-wide buffer) into Ut, S, Vt (l x k, ld KP).
+int core_svd(const Plan& p, const double* M, double* Ut, double* S, double* Vt, void* ws, hipStream_t st) {
+  void* info = at<void>(ws, p.off_info);
+  if (p.wide) {
+    SORSVD_TRY(launch_jacobi_wide(M, (int)p.LP, (int)p.l, (int)p.k, p.max_sweeps, Ut, S, Vt, (int)p.KP,
+                                  at<void>(ws, p.off_wjac), info, st, 0.0));
+  } else {
+    SORSVD_TRY(launch_jacobi(M, (int)p.LP, (int)p.l, (int)p.k, p.max_sweeps, Ut, S, Vt, (int)p.KP,
+                             at<double>(ws, p.off_vg), info, st, true, 0.0,
+                             p.off_rlog ? at<void>(ws, p.off_rlog) : nullptr));
   }
   return SORSVD_OK;
 }
@@ -406,13 +473,13 @@ int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, 
   } else if (p.a_type == SORSVD_F64) {
     double* P = at<double>(ws, p.off_p);
     SORSVD_TRY(launch_skinny_f64(trans, (const double*)A, lda, OUT, K, (const double*)Xc, LP, LP,
-                                 sp.kchunk, sp.nsplit, P, normp, nullptr, st, T));
+                                 sp.kchunk, sp.nsplit, P, normp, nullptr, st, T, false, p.ncb));
     if (e1) SORSVD_TRY(hipEventRecord(e1, st));
     if (sp.nsplit > 1) SORSVD_TRY(launch_reduce_f64(P, OUT, LP, sp.nsplit, T, LP, LP, st));
   } else if (p.a_type == SORSVD_F32) {
     float* P = at<float>(ws, p.off_p);
     SORSVD_TRY(launch_skinny_f32(trans, (const float*)A, lda, OUT, K, (const float*)Xc, LP, LP,
-                                 sp.kchunk, sp.nsplit, P, normp, nullptr, st, T));
+                                 sp.kchunk, sp.nsplit, P, normp, nullptr, st, T, p.ncb));
     if (e1) SORSVD_TRY(hipEventRecord(e1, st));
     if (sp.nsplit > 1) SORSVD_TRY(launch_reduce_f32(P, OUT, LP, sp.nsplit, T, LP, LP, st));
   } else {
@@ -426,14 +493,15 @@ int pass(const Plan& p, bool trans, const void* A, int64_t lda, const void* Xc, 
     const int rt = proj ? p.rt_proj : (tfold ? p.rt_tnb : (trans ? p.rt_tn : p.rt_nn));
     const H16Scale* sc = p.fmt == kFmtF16 ? at<H16Scale>(ws, p.off_hsc) : nullptr;
     SORSVD_TRY(launch_h16_pass(p.fmt, trans, (const uint16_t*)A, lda, OUT, K, (const uint16_t*)Xc, p.ldt, LPw,
-                               spb.kchunk, spb.nsplit, P, normp, tfold ? nullptr : T, fold ? 1 : 0, rt, sc,
+                               spb.kchunk, spb.nsplit, p.ncb, P, normp, tfold ? nullptr : T, fold ? 1 : 0, rt, sc,
                                p.cexp, st));
     if (e1) SORSVD_TRY(hipEventRecord(e1, st));
     if (spb.nsplit > 1 || tfold) {  // with one split the kernel wrote T itself (not the A^T Y kernel with fold)
       if (sc)
-        SORSVD_TRY(launch_reduce_h16(trans, P, OUT, LPw, spb.nsplit, T, LP, LP, fold ? 1 : 0, sc, p.cexp, st));
+        SORSVD_TRY(launch_reduce_h16(trans, P, OUT, LPw, spb.nsplit, T, LP, LP, fold ? 1 : 0, (int)p.CB, sc, p.cexp,
+                                     st));
       else if (fold)
-        SORSVD_TRY(launch_reduce_fold(P, OUT, LPw, spb.nsplit, T, LP, LP, st));
+        SORSVD_TRY(launch_reduce_fold(P, OUT, LPw, spb.nsplit, T, LP, LP, (int)p.CB, st));
       else
         SORSVD_TRY(launch_reduce_f32(P, OUT, LP, spb.nsplit, T, LP, LP, st));
     }
@@ -452,7 +520,7 @@ const void* as_operand(const Plan& p, const double* Q, int64_t rows, void* ws, h
   if (p.fmt >= 0) {
     uint16_t* XT = at<uint16_t>(ws, p.off_xc);
     const H16Scale* sc = p.fmt == kFmtF16 ? at<H16Scale>(ws, p.off_hsc) : nullptr;
-    if (launch_cast_h16_t(p.fmt, Q, rows, (int)p.LP, p.ldt, for_tn ? 1 : 0, with_lo ? 1 : 0, XT, sc,
+    if (launch_cast_h16_t(p.fmt, Q, rows, (int)p.CB, p.ncb, p.ldt, for_tn ? 1 : 0, with_lo ? 1 : 0, XT, sc,
                           for_tn ? nullptr : p.cexp, st) != hipSuccess)
       *rc = SORSVD_EHIP;
     return XT;
@@ -543,7 +611,7 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
     // pass-efficient core matrix (eq. M_approx): Q1^T A = T2^T for the kept
     // T2 = A^T Q1, so Q1^T A Q2 = T2^T Q2 (an FP64 l x l product over n rows)
     SORSVD_TRY(launch_skinny_f64(true, T2P, LP, LP, p.n, T2, LP, LP, p.gram_n.kchunk, p.gram_n.nsplit, P,
-                                 nullptr, nullptr, st));
+                                 nullptr, nullptr, st, nullptr, false, p.ncb));
     SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.gram_n.nsplit, M, LP, LP, st));
   } else {
     // M = Q1^T (A Q2) (eq. M): W = A Q2 in the pass kernel, then the FP64 Q1^T W.
@@ -551,7 +619,7 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
     if (rc) return rc;
     if ((rc = pass(p, false, A, lda, X, W, nullptr, ws, st, p.refine != 0, true))) return rc;
     SORSVD_TRY(launch_skinny_f64(true, T1, LP, LP, p.m, W, LP, LP, p.proj.kchunk, p.proj.nsplit, P,
-                                 nullptr, nullptr, st));
+                                 nullptr, nullptr, st, nullptr, false, p.ncb));
     SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.proj.nsplit, M, LP, LP, st));
   }
 
@@ -560,15 +628,15 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   double* Vt = at<double>(ws, p.off_vt);
   SORSVD_TRY(launch_fill(Ut, (int64_t)LP * KP, 0.0, st));
   SORSVD_TRY(launch_fill(Vt, (int64_t)LP * KP, 0.0, st));
-  SORSVD_TRY(launch_jacobi(M, LP, (int)p.l, (int)p.k, p.max_sweeps, Ut, S, Vt, KP,
-                           at<double>(ws, p.off_vg), info, st, true, 0.0,
-                           p.off_rlog ? at<void>(ws, p.off_rlog) : nullptr));
+  if ((rc = core_svd(p, M, Ut, S, Vt, ws, st))) return rc;
 
   // Lift: U = Q1 U~_k, V = Q2 V~_k (Alg. 3 step 7), then the sign convention.
   double* U64 = at<double>(ws, p.off_u64);
   double* V64 = at<double>(ws, p.off_v64);
-  SORSVD_TRY(launch_skinny_f64(false, T1, LP, p.m, LP, Ut, KP, KP, LP, 1, U64, nullptr, nullptr, st));
-  SORSVD_TRY(launch_skinny_f64(false, T2, LP, p.n, LP, Vt, KP, KP, LP, 1, V64, nullptr, nullptr, st));
+  SORSVD_TRY(launch_skinny_f64(false, T1, LP, p.m, LP, Ut, KP, KP, LP, 1, U64, nullptr, nullptr, st, nullptr, false,
+                               p.ncbk));
+  SORSVD_TRY(launch_skinny_f64(false, T2, LP, p.n, LP, Vt, KP, KP, LP, 1, V64, nullptr, nullptr, st, nullptr, false,
+                               p.ncbk));
   SORSVD_TRY(launch_signfix(U64, p.m, V64, p.n, KP, (int)p.k, at<double>(ws, p.off_pval),
                             at<int64_t>(ws, p.off_pidx), kSignBlocks, at<double>(ws, p.off_sgn), U, ldu,
                             V, ldv, st));
@@ -779,7 +847,7 @@ int sorsvd_step_qr(const double* T, int64_t rows, int64_t l, double* Q, double* 
   double* P = at<double>(ws, p.off_p);
   double* G = at<double>(ws, p.off_g);
   SORSVD_TRY(launch_skinny_f64(true, Tq, LP, LP, rows, Tc, LP, LP, p.gram_m.kchunk, p.gram_m.nsplit,
-                                   P, nullptr, nullptr, st));
+                                   P, nullptr, nullptr, st, nullptr, false, p.ncb));
   SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.gram_m.nsplit, G, LP, LP, st));
   SORSVD_TRY(launch_pack_f64(Tq, rows, (int)l, LP, Q, (int)l, st));
   SORSVD_TRY(launch_pack_f64(G, l, (int)l, LP, R, (int)l, st));
@@ -807,7 +875,7 @@ int sorsvd_step_project(const void* A, int64_t lda, int32_t a_type, int64_t m, i
   double* P = at<double>(ws, p.off_p);
   double* Mp = at<double>(ws, p.off_m);
   SORSVD_TRY(launch_skinny_f64(true, Q1p, LP, LP, m, W, LP, LP, p.proj.kchunk, p.proj.nsplit, P,
-                                   nullptr, nullptr, st));
+                                   nullptr, nullptr, st, nullptr, false, p.ncb));
   SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.proj.nsplit, Mp, LP, LP, st));
   SORSVD_TRY(launch_pack_f64(Mp, l, (int)l, LP, M, (int)l, st));
   return SORSVD_OK;
@@ -823,6 +891,15 @@ int sorsvd_step_core_svd(const double* M, int64_t l, int64_t k, double* Ut, doub
   SORSVD_TRY(launch_info_init(at<void>(ws, p.off_info), st));
   SORSVD_TRY(launch_fill(Ut, l * k, 0.0, st));
   SORSVD_TRY(launch_fill(Vt, l * k, 0.0, st));
+  if (p.wide) {
+    // a general M (not the near-triangular core matrix of the method) can
+    // take as many sweeps as the one-workgroup kernel's default allows
+    if (max_sweeps > kWideMaxSweeps) return SORSVD_EINVAL;
+    const int ms = max_sweeps > 0 ? max_sweeps : 40;
+    SORSVD_TRY(launch_jacobi_wide(M, (int)l, (int)l, (int)k, ms, Ut, s, Vt, (int)k, at<void>(ws, p.off_wjac),
+                                  at<void>(ws, p.off_info), st, 0.0));
+    return SORSVD_OK;
+  }
   const int ms = max_sweeps > 0 ? max_sweeps : 40;
   // the log in the workspace holds p.max_sweeps sweeps
   void* rlog = (p.off_rlog && ms <= p.max_sweeps) ? at<void>(ws, p.off_rlog) : nullptr;
@@ -872,7 +949,7 @@ int sorsvd_pass_timing_read(double* total_ms, int64_t* launches, double* bytes, 
 
 static int probe_plan(int64_t m, int64_t n, int32_t a_type, Plan* p) {
   if (a_type == SORSVD_F16) return SORSVD_EUNSUPPORTED;
-  const int64_t l = std::min<int64_t>(kMaxLP, std::min(m, n));
+  const int64_t l = std::min<int64_t>(kProbeL, std::min(m, n));
   sorsvd_opts o;
   std::memset(&o, 0, sizeof(o));
   o.l = l;
@@ -929,6 +1006,7 @@ int sorsvd_mlp_train_step(float* params, float* m, float* v, const float* X, con
 }
 
 static constexpr double kAutoMargin = 1.25;  // head-room on the predicted width
+static constexpr int64_t kAutoFallbackK = 256;  // first rung of the fixed ladder
 static constexpr int kAutoFallbackQ = 2;
 static constexpr double kNoiseShare = 4.0;   // BF16 judge: captured rounding-noise allowance / i.i.d. bound
 
@@ -1010,7 +1088,7 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
   int64_t keep_ld = 0;
   int keep_parts = 0;
   const double ridge = a_type == SORSVD_BF16 ? 312.0 : 39.0;  // width where a pass turns MFMA-bound
-  int64_t k = kcap;
+  int64_t k = std::min(kAutoFallbackK, kcap);
   int q = kAutoFallbackQ;
   bool predicted = false;
   if (params) {
@@ -1049,7 +1127,17 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
       }
     }
   }
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  // the predicted (k, q), then the fixed ladder: (256, 2), (512, 2), ... up
+  // to the cap, until the judge accepts
+  std::vector<std::pair<int64_t, int>> runs;
+  if (predicted) runs.emplace_back(k, q);
+  for (int64_t kf = std::min(kAutoFallbackK, kcap);; kf = std::min(2 * kf, kcap)) {
+    if (!(predicted && kf == k && q == kAutoFallbackQ)) runs.emplace_back(kf, kAutoFallbackQ);
+    if (kf == kcap) break;
+  }
+  for (size_t attempt = 0; attempt < runs.size(); ++attempt) {
+    k = runs[attempt].first;
+    q = runs[attempt].second;
     sorsvd_opts o;
     auto_opts(a_type, &o);
     o.residual = a_type == SORSVD_BF16 ? 1 : 0;  // BF16: the identity cannot resolve 1e-3
@@ -1082,9 +1170,6 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     out->used_fallback = (attempt > 0 || !predicted) ? 1 : 0;
     out->flags = info.flags;
     if (e <= tol) return SORSVD_OK;
-    if (!predicted || (k == kcap && q >= kAutoFallbackQ)) break;
-    k = kcap;  // fallback
-    q = kAutoFallbackQ;
   }
   return SORSVD_ETOL;
 }

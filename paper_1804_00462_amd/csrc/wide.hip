@@ -1,0 +1,600 @@
+// The l x l steps of the method for sketch widths l > 128, spread over many
+// workgroups (the one-workgroup kernels of small.hip hold l <= 128):
+//
+//   * the Cholesky factor of the Gram matrix G = T^T T of a sketch (the QR
+//     step of Alg. 3 / Alg. 4 as Cholesky QR, T = Q R with R^T R = G) and
+//     Z = R^{-1}, blocked in 64 x 64 blocks, with the same shift rule as the
+//     one-workgroup factor;
+//   * the core SVD of M = Q1^T A Q2 (Alg. 3 step 6) by one-sided Jacobi
+//     rotations, with the columns grouped in blocks that meet in pairs.
+//
+// Matrices are FP64, row-major l x l inside LP x LP buffers (ld LP); entries
+// at indices >= l are zero on input and stay zero.
+#include <algorithm>
+
+#include "small_body.hpp"
+
+namespace sor {
+
+namespace {
+
+constexpr int kWB = 64;        // Cholesky block edge
+constexpr int kWLd = kWB + 2;  // LDS row stride of a 64 x 64 block
+
+__device__ inline bool gate_off(const int* skip, const int* need) {
+  return (skip && *skip) || (need && !*need);
+}
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// A 64 x 64 block (rows r0.., columns c0..) of an LP x LP matrix into LDS
+// (row stride kWLd), zero outside the buffer.
+__device__ inline void load_block64(const double* __restrict__ M, int LP, int r0, int c0, double* S) {
+  for (int i = threadIdx.x; i < kWB * kWB; i += 256) {
+    const int r = i / kWB, c = i % kWB;
+    const int gr = r0 + r, gc = c0 + c;
+    S[r * kWLd + c] = (gr < LP && gc < LP) ? M[(int64_t)gr * LP + gc] : 0.0;
+  }
+}
+
+// acc[ct] += sum_{k in [k0, k1)} A(16 w + i, k) B(k, 16 ct + j) for the 16-row
+// strip of wave w, on FP64 MFMA (16 x 16 x 4); A(i, k) = As[k][i] when TA,
+// else As[i][k]; both operands in LDS with row stride kWLd. Result layout:
+// acc[ct][r] holds C(16 w + 4 r + l / 16, 16 ct + l % 16) for lane l.
+template <bool TA>
+__device__ inline void mm64(const double* As, const double* Bs, int k0, int k1, f64x4 (&acc)[4]) {
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const int li = l % 16, g = l / 16;
+  const int i = 16 * w + li;
+  for (int kb = k0; kb < k1; kb += 4) {
+    const int k = kb + g;
+    const double a = TA ? As[k * kWLd + i] : As[i * kWLd + k];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[k * kWLd + 16 * ct + li], acc[ct], 0, 0, 0);
+  }
+}
+
+__device__ inline void store_acc64(const f64x4 (&acc)[4], double* S) {
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const int li = l % 16, g = l / 16;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[(16 * w + 4 * r + g) * kWLd + 16 * ct + li] = acc[ct][r];
+}
+
+}  // namespace
+
+// Small state of a blocked factorization (in the workspace).
+struct WideChol {
+  int32_t retry;  // a pivot of the unshifted factor failed the check
+  int32_t pad_;
+  double tr;      // trace of G
+};
+
+// ---------------------------------------------------------------------------
+// Blocked Cholesky factor. With S the current Schur complement, panel p
+// (rows / columns J = [64 p, 64 p + 64)) factors S_JJ = R_JJ^T R_JJ and forms
+// R_JI = R_JJ^{-T} S_JI for the trailing blocks I and S_IK <- S_IK - R_JI^T R_JK
+// (right-looking; one launch per panel, one workgroup per trailing block
+// (I, K), I <= K, each forming the diagonal factor itself). The pivot rule is
+// the one-workgroup factor's: an unshifted factor whose pivot d_j falls below
+// 1e-13 G_jj (column j nearly in the span of the earlier ones) raises
+// `retry`, and the factor is taken again from G + c u tr(G) I (c = 11 (rows
+// l + l (l + 1)), u = 2^-53); a pivot that is still not positive then drops
+// its column (zero row of R, zero row and column of Z; flag bit 2).
+// Z = R^{-1} is then formed by doubling: with Z known on diagonal blocks of
+// edge s, the block above the diagonal of each pair is
+// Z_12 = -Z_11 R_12 Z_22 (two launches per level).
+
+// Copies G to G0, clears R and Z, takes the diagonal and trace of G (block 0).
+__global__ void __launch_bounds__(256)
+k_wchol_prep(const double* __restrict__ G, int LP, int l, double* __restrict__ G0, double* __restrict__ Rb,
+             double* __restrict__ Z, double* __restrict__ d0, WideChol* __restrict__ st, const int* skip) {
+  if (skip && *skip) return;
+  const int64_t tot = (int64_t)LP * LP;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += (int64_t)gridDim.x * 256) {
+    G0[i] = G[i];
+    Rb[i] = 0.0;
+    Z[i] = 0.0;
+  }
+  if (blockIdx.x == 0) {
+    __shared__ double part[256];
+    double a = 0.0;
+    for (int j = threadIdx.x; j < l; j += 256) {
+      const double d = G[(int64_t)j * LP + j];
+      d0[j] = d;
+      a += d;
+    }
+    part[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+      if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      st->tr = part[0];
+      st->retry = 0;
+    }
+  }
+}
+
+// G <- G0 + shift I (the shifted factor).
+__global__ void __launch_bounds__(256)
+k_wchol_restore(double* __restrict__ G, const double* __restrict__ G0, int LP, int l, int64_t rows,
+                const WideChol* __restrict__ st, const int* skip, const int* need) {
+  if (gate_off(skip, need)) return;
+  const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 0x1p-53 * st->tr;
+  const int64_t tot = (int64_t)LP * LP;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += (int64_t)gridDim.x * 256) {
+    const int64_t r = i / LP, c = i % LP;
+    G[i] = G0[i] + ((r == c && r < l) ? shift : 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_wchol_panel(double* __restrict__ G, int LP, int l, int p, const double* __restrict__ d0, int check,
+              double* __restrict__ Rb, double* __restrict__ Z, WideChol* __restrict__ st, DevInfo* __restrict__ info,
+              const int* skip, const int* need) {
+  if (gate_off(skip, need)) return;
+  __shared__ double Zs[kWB * kWLd], Si[kWB * kWLd], Sj[kWB * kWLd];
+  const int nbk = (l + kWB - 1) / kWB;
+  const int T = nbk - p - 1;  // trailing blocks
+  int I = p, K = p;
+  if (T > 0) {  // block index -> (i, k), 0 <= i <= k < T; row i holds T - i of them
+    int b = blockIdx.x, i = 0;
+    while (b >= T - i) {
+      b -= T - i;
+      ++i;
+    }
+    I = p + 1 + i;
+    K = I + b;
+  }
+  const int r0 = kWB * p;
+  load_block64(G, LP, r0, r0, Zs);
+  if (T > 0) {
+    load_block64(G, LP, r0, kWB * I, Si);
+    if (K != I) load_block64(G, LP, r0, kWB * K, Sj);
+  }
+  __syncthreads();
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const bool lead = blockIdx.x == 0;
+  if (w == 0) {
+    // Wave 0: lane c holds column c of the diagonal block, s[i] = S(i, c),
+    // and runs the elimination: step j scales row j by 1 / sqrt(d_j) (lane
+    // c >= j then holds R(j, c)) and subtracts R(j, i) R(j, c) from S(i, c),
+    // i > j. The R(j, i) come from lane i by readlane.
+    double s[kWB];
+#pragma unroll
+    for (int i = 0; i < kWB; ++i) s[i] = Zs[i * kWLd + lane];
+    bool bad = false, drop = false;
+#pragma unroll
+    for (int j = 0; j < kWB; ++j) {
+      const double d = readlane_f64(s[j], j);
+      const int gj = r0 + j;
+      const bool pad = gj >= l;
+      if (!pad && check && !(d > 1e-13 * d0[min(gj, l - 1)])) bad = true;
+      const bool ok = !pad && d > 0.0;
+      if (!pad && !check && !ok) drop = true;
+      const double isd = ok ? 1.0 / sqrt(d) : 0.0;
+      s[j] = lane >= j ? s[j] * isd : 0.0;
+#pragma unroll
+      for (int i = j + 1; i < kWB; ++i) s[i] = fma(-readlane_f64(s[j], i), s[j], s[i]);
+    }
+    // R_JJ into LDS (rows j, lane = column) and, by the lead workgroup, to Rb
+#pragma unroll
+    for (int j = 0; j < kWB; ++j) {
+      Zs[j * kWLd + lane] = s[j];
+      if (lead && r0 + j < LP && r0 + lane < LP) Rb[(int64_t)(r0 + j) * LP + r0 + lane] = s[j];
+    }
+    // Z_JJ = R_JJ^{-1} by back substitution, lane c forming column c:
+    // z_i = (delta_ic - sum_{t > i} R(i, t) z_t) / R(i, i) (0 for a dropped i)
+    double z[kWB];
+#pragma unroll
+    for (int i = kWB - 1; i >= 0; --i) {
+      double a = i == lane ? 1.0 : 0.0;
+#pragma unroll
+      for (int t = i + 1; t < kWB; ++t) a = fma(-Zs[i * kWLd + t], z[t], a);
+      const double rii = Zs[i * kWLd + i];
+      z[i] = rii != 0.0 ? a / rii : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kWB; ++i) {
+      Zs[i * kWLd + lane] = z[i];
+      if (lead && r0 + i < LP && r0 + lane < LP) Z[(int64_t)(r0 + i) * LP + r0 + lane] = z[i];
+    }
+    if (lead && lane == 0) {
+      if (bad) st->retry = 1;
+      if (drop) atomicOr(&info->flags, kFlagQrBreakdown);
+    }
+  }
+  __syncthreads();
+  if (T == 0) return;
+  // R_JI = Z_JJ^T S_JI (Z_JJ(k, i) = 0 for k > i: the strip of wave w needs k < 16 (w + 1))
+  f64x4 ri[4], rk[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) ri[ct] = rk[ct] = f64x4{0, 0, 0, 0};
+  mm64<true>(Zs, Si, 0, 16 * (w + 1), ri);
+  if (K != I) mm64<true>(Zs, Sj, 0, 16 * (w + 1), rk);
+  __syncthreads();
+  store_acc64(ri, Si);
+  if (K != I) store_acc64(rk, Sj);
+  __syncthreads();
+  if (K == I) {  // the diagonal trailing block publishes R_JI
+    for (int e = threadIdx.x; e < kWB * kWB; e += 256) {
+      const int r = e / kWB, c = e % kWB;
+      const int gr = r0 + r, gc = kWB * I + c;
+      if (gr < LP && gc < LP) Rb[(int64_t)gr * LP + gc] = Si[r * kWLd + c];
+    }
+  }
+  // S_IK -= R_JI^T R_JK
+  f64x4 u[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) u[ct] = f64x4{0, 0, 0, 0};
+  mm64<true>(Si, K != I ? Sj : Si, 0, kWB, u);
+  const int li = lane % 16, g = lane / 16;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = kWB * I + 16 * w + 4 * r + g, gc = kWB * K + 16 * ct + li;
+      if (gr < LP && gc < LP) G[(int64_t)gr * LP + gc] -= u[ct][r];
+    }
+}
+
+// One launch of a doubling level of Z = R^{-1} (pairs of diagonal blocks of
+// edge s, the first starting at a0 = 2 s pair, the second at b0 = a0 + s):
+//   step 0: X_12 = R_12 Z_22     (Z_22 upper triangular: k < c + 1)
+//   step 1: Z_12 = -Z_11 X_12    (Z_11 upper triangular: k >= r)
+// One workgroup per 64 x 64 output tile; operands staged through LDS in
+// slices of 32 contraction indices.
+__global__ void __launch_bounds__(256)
+k_wchol_inv(int LP, int l, int s, int step, const double* __restrict__ Rb, double* __restrict__ Z,
+            double* __restrict__ X, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ double As[kWB * 34], Bs[32 * kWLd];
+  const int lw = (l + kWB - 1) / kWB * kWB;
+  const int tpb = s / kWB;
+  const int pair = blockIdx.x / (tpb * tpb), t = blockIdx.x % (tpb * tpb);
+  const int ti = t / tpb, tj = t % tpb;
+  const int a0 = 2 * s * pair, b0 = a0 + s;
+  const int b1 = min(b0 + s, lw);
+  if (b0 + kWB * tj >= b1) return;  // beyond a ragged second block (uniform)
+  const int row0 = a0 + kWB * ti, col0 = b0 + kWB * tj;
+  const double* A = step == 0 ? Rb : Z;
+  const double* B = step == 0 ? Z : X;
+  const int k0 = step == 0 ? b0 : row0;
+  const int k1 = step == 0 ? col0 + kWB : a0 + s;
+  const double alpha = step == 0 ? 1.0 : -1.0;
+  double* C = step == 0 ? X : Z;
+  const int w = threadIdx.x / kWave, l64 = threadIdx.x % kWave;
+  const int li = l64 % 16, g = l64 / 16;
+  f64x4 acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = f64x4{0, 0, 0, 0};
+  for (int kb = k0; kb < k1; kb += 32) {
+    for (int e = threadIdx.x; e < kWB * 32; e += 256) {
+      const int r = e / 32, k = e % 32;
+      const int gr = row0 + r, gk = kb + k;
+      As[r * 34 + k] = (gr < LP && gk < LP && gk < k1) ? A[(int64_t)gr * LP + gk] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 32 * kWB; e += 256) {
+      const int k = e / kWB, c = e % kWB;
+      const int gk = kb + k, gc = col0 + c;
+      Bs[k * kWLd + c] = (gk < LP && gc < LP && gk < k1) ? B[(int64_t)gk * LP + gc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) {
+      const double a = As[(16 * w + li) * 34 + kk + g];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[(kk + g) * kWLd + 16 * ct + li], acc[ct], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = row0 + 16 * w + 4 * r + g, gc = col0 + 16 * ct + li;
+      if (gr < LP && gc < LP) C[(int64_t)gr * LP + gc] = alpha * acc[ct][r];
+    }
+}
+
+// The third Cholesky-QR step is needed only after a shifted factor (see
+// chol_inv_body): mode 0 sets *skip3 when the factor was unshifted, mode 1
+// clears it when it was shifted.
+__global__ void __launch_bounds__(64) k_wchol_skipset(const WideChol* __restrict__ st, int mode, int* skip3) {
+  if (threadIdx.x) return;
+  if (mode == 0) *skip3 = st->retry ? 0 : 1;
+  else if (mode == 1 && st->retry) *skip3 = 0;
+}
+
+// Scratch of launch_chol_wide: G0, R (LP x LP each), X (LP x LP), the
+// diagonal of G (LP) and the state record.
+size_t chol_wide_bytes(int LP) { return ((size_t)3 * LP * LP + LP) * 8 + 256; }
+
+hipError_t launch_chol_wide(double* G, int LP, int l, int64_t rows, int mode, double* Z, int* skip3, void* info,
+                            void* scratch, hipStream_t st) {
+  if (l <= 0 || l > LP) return hipErrorInvalidValue;
+  double* G0 = reinterpret_cast<double*>(scratch);
+  double* Rb = G0 + (size_t)LP * LP;
+  double* X = Rb + (size_t)LP * LP;
+  double* d0 = X + (size_t)LP * LP;
+  WideChol* wc = reinterpret_cast<WideChol*>(d0 + LP);
+  const int* skip = mode == 2 ? skip3 : nullptr;
+  DevInfo* di = (DevInfo*)info;
+  const int64_t tot = (int64_t)LP * LP;
+  const unsigned cblocks = (unsigned)std::min<int64_t>(1024, ceil_div(tot, 256));
+  hipLaunchKernelGGL(k_wchol_prep, dim3(cblocks), dim3(256), 0, st, G, LP, l, G0, Rb, Z, d0, wc, skip);
+  const int nbk = (int)ceil_div(l, kWB);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int* need = pass == 0 ? nullptr : &wc->retry;
+    if (pass == 1)
+      hipLaunchKernelGGL(k_wchol_restore, dim3(cblocks), dim3(256), 0, st, G, G0, LP, l, rows, wc, skip, need);
+    for (int p = 0; p < nbk; ++p) {
+      const int T = nbk - p - 1;
+      const unsigned blocks = (unsigned)std::max(1, T * (T + 1) / 2);
+      hipLaunchKernelGGL(k_wchol_panel, dim3(blocks), dim3(256), 0, st, G, LP, l, p, d0, pass == 0 ? 1 : 0, Rb, Z,
+                         wc, di, skip, need);
+    }
+  }
+  const int lw = nbk * kWB;
+  for (int s = kWB; s < lw; s *= 2) {
+    const int pairs = (int)ceil_div(lw - s, 2 * s);  // pairs whose second block starts below lw
+    const int tpb = s / kWB;
+    for (int step = 0; step < 2; ++step)
+      hipLaunchKernelGGL(k_wchol_inv, dim3((unsigned)(pairs * tpb * tpb)), dim3(256), 0, st, LP, l, s, step, Rb, Z,
+                         X, skip);
+  }
+  if (mode != 2) hipLaunchKernelGGL(k_wchol_skipset, dim3(1), dim3(64), 0, st, wc, mode, skip3);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Core SVD for l > 128: one-sided Jacobi on the columns of M, blocked. The
+// columns (zero-padded to nbe blocks of B, nbe even) are held column-major
+// in global memory (Mc, V in Vc, column stride ldc >= l, rows >= l zero). A
+// sweep pairs the blocks by the round-robin order (nbe - 1 steps of nbe / 2
+// disjoint block pairs; block 0 stays, the others move one place per step).
+// Per step one workgroup takes each block pair: its 2B columns go to LDS,
+// where one round-robin sweep of pair rotations runs over them (the
+// rotation of the one-workgroup kernel: zeta = (beta - alpha) / (2 gamma),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2),
+// s = c t, applied when gamma^2 > tol^2 alpha beta), while the product W of
+// the rotations (2B x 2B) is accumulated; then the columns go back and the
+// matching columns of V are multiplied by W. Every pair of columns meets at
+// least once per sweep. A sweep in which no workgroup rotated ends the
+// iteration (the later launches return at once); then sigma_j = |m_j|,
+// U~_j = m_j / sigma_j, V~_j = v_j, in descending order (ties: lower index).
+
+struct WideJacDims {
+  int B, nbe, ldc;
+};
+
+WideJacDims wjac_dims(int l) {
+  WideJacDims d;
+  d.ldc = (int)round_up(l, 32);
+  d.B = ((size_t)32 * d.ldc + 32 * 32) * 8 <= 150 * 1024 ? 16 : 8;
+  const int nb = (int)ceil_div(l, d.B);
+  d.nbe = nb + (nb & 1);
+  if (d.nbe < 2) d.nbe = 2;
+  return d;
+}
+
+// Scratch of launch_jacobi_wide: Mc, Vc (nbe B x ldc each), the singular
+// values (l), the per-sweep rotation counters (up to kWideMaxSweeps) and the
+// convergence word.
+constexpr int kWideMaxSweeps = 64;
+size_t jacobi_wide_bytes(int l) {
+  const WideJacDims d = wjac_dims(l);
+  return ((size_t)2 * d.nbe * d.B * d.ldc + l) * 8 + ((size_t)kWideMaxSweeps + 64) * 4;
+}
+
+__global__ void __launch_bounds__(256)
+k_wjac_init(const double* __restrict__ M, int LPm, int l, int ncp, int ldc, double* __restrict__ Mc,
+            double* __restrict__ Vc, int* __restrict__ cnt, int max_sweeps) {
+  const int64_t tot = (int64_t)ncp * ldc;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int j = (int)(e / ldc), i = (int)(e % ldc);
+    Mc[e] = (i < l && j < l) ? M[(int64_t)i * LPm + j] : 0.0;
+    Vc[e] = (i == j && j < l) ? 1.0 : 0.0;
+  }
+  if (blockIdx.x == 0)
+    for (int s = threadIdx.x; s <= max_sweeps; s += 256) cnt[s] = 0;  // cnt[max_sweeps]: convergence word
+}
+
+template <int B>
+__global__ void __launch_bounds__(256)
+k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, int nbe, int t, int sweep,
+            int* __restrict__ cnt, const int* __restrict__ conv, double tol2) {
+  if (*conv) return;
+  constexpr int NL = 2 * B, TPP = 256 / B;
+  extern __shared__ double sm[];
+  double* Ms = sm;              // NL columns of ldc
+  double* Ws = sm + NL * ldc;   // W, column-major: W(r, c) = Ws[c NL + r]
+  __shared__ int s_rot;
+  const int tid = threadIdx.x;
+  auto player = [](int pos, int step, int n) {
+    if (pos == 0) return 0;
+    int x = pos - 1 + step;
+    if (x >= n - 1) x -= n - 1;
+    return 1 + x;
+  };
+  const int bp = player(blockIdx.x, t, nbe), bq = player(nbe - 1 - blockIdx.x, t, nbe);
+  auto gcol = [&](int c) { return c < B ? bp * B + c : bq * B + (c - B); };
+  for (int e = tid; e < NL * ldc; e += 256) {
+    const int c = e / ldc, r = e % ldc;
+    Ms[e] = Mc[(int64_t)gcol(c) * ldc + r];
+  }
+  for (int e = tid; e < NL * NL; e += 256) Ws[e] = (e / NL == e % NL) ? 1.0 : 0.0;
+  if (tid == 0) s_rot = 0;
+  __syncthreads();
+  const int grp = tid / TPP, gl = tid % TPP;
+  bool rotated = false;
+  for (int step = 0; step < NL - 1; ++step) {
+    int p = player(grp, step, NL), q = player(NL - 1 - grp, step, NL);
+    if (p > q) {
+      const int x = p;
+      p = q;
+      q = x;
+    }
+    double* mp = Ms + p * ldc;
+    double* mq = Ms + q * ldc;
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int r = gl; r < ldc; r += TPP) {
+      const double x = mp[r], y = mq[r];
+      al = fma(x, x, al);
+      be = fma(y, y, be);
+      ga = fma(x, y, ga);
+    }
+#pragma unroll
+    for (int off = TPP / 2; off >= 1; off >>= 1) {  // butterfly: every lane of the group gets the same bits
+      al += __shfl_xor(al, off, kWave);
+      be += __shfl_xor(be, off, kWave);
+      ga += __shfl_xor(ga, off, kWave);
+    }
+    if (ga * ga > tol2 * (al * be)) {
+      const double zeta = (be - al) / (2.0 * ga);
+      const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double c = 1.0 / sqrt(1.0 + tt * tt);
+      const double s = c * tt;
+      for (int r = gl; r < ldc; r += TPP) {
+        const double x = mp[r], y = mq[r];
+        mp[r] = c * x - s * y;
+        mq[r] = s * x + c * y;
+      }
+      for (int r = gl; r < NL; r += TPP) {
+        const double x = Ws[p * NL + r], y = Ws[q * NL + r];
+        Ws[p * NL + r] = c * x - s * y;
+        Ws[q * NL + r] = s * x + c * y;
+      }
+      rotated = true;
+    }
+    __syncthreads();
+  }
+  if (rotated && gl == 0) s_rot = 1;
+  for (int e = tid; e < NL * ldc; e += 256) {
+    const int c = e / ldc, r = e % ldc;
+    Mc[(int64_t)gcol(c) * ldc + r] = Ms[e];
+  }
+  __syncthreads();
+  if (s_rot) {
+    // V columns of the pair <- (those columns) W, row by row
+    for (int r = tid; r < l; r += 256) {
+      double v[NL];
+#pragma unroll
+      for (int c = 0; c < NL; ++c) v[c] = Vc[(int64_t)gcol(c) * ldc + r];
+#pragma unroll 1
+      for (int j = 0; j < NL; ++j) {  // (not unrolled: W stays in LDS instead of being hoisted into registers)
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < NL; ++c) a = fma(v[c], Ws[j * NL + c], a);
+        Vc[(int64_t)gcol(j) * ldc + r] = a;
+      }
+    }
+    if (tid == 0) atomicAdd(&cnt[sweep], 1);
+  }
+}
+
+__global__ void __launch_bounds__(64)
+k_wjac_sweep_end(int* __restrict__ cnt, int sweep, int max_sweeps, DevInfo* __restrict__ info) {
+  if (threadIdx.x) return;
+  int* conv = cnt + max_sweeps;
+  if (*conv) return;
+  if (cnt[sweep] == 0) {
+    *conv = 1;
+    info->sweeps = sweep + 1;
+  } else if (sweep == max_sweeps - 1) {
+    info->sweeps = max_sweeps;
+    atomicOr(&info->flags, kFlagNoConv);
+  }
+}
+
+// sig[j] = |m_j| (fixed-order tree sum), one workgroup per column.
+__global__ void __launch_bounds__(256)
+k_wjac_norms(const double* __restrict__ Mc, int ldc, int l, double* __restrict__ sig) {
+  __shared__ double part[256];
+  const int j = blockIdx.x;
+  double a = 0.0;
+  for (int r = threadIdx.x; r < l; r += 256) {
+    const double x = Mc[(int64_t)j * ldc + r];
+    a = fma(x, x, a);
+  }
+  part[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sig[j] = sqrt(part[0]);
+}
+
+// Rank of column j by descending sigma (ties: lower index first); the first
+// k go to Ut, Vt (l x k, ld ldk) and sv.
+__global__ void __launch_bounds__(256)
+k_wjac_out(const double* __restrict__ Mc, const double* __restrict__ Vc, int ldc, int l, int k,
+           const double* __restrict__ sig, double* __restrict__ Ut, double* __restrict__ sv, double* __restrict__ Vt,
+           int ldk) {
+  __shared__ int part[256];
+  const int j = blockIdx.x;
+  const double sj = sig[j];
+  int cntr = 0;
+  for (int i = threadIdx.x; i < l; i += 256) cntr += (sig[i] > sj || (sig[i] == sj && i < j)) ? 1 : 0;
+  part[threadIdx.x] = cntr;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  const int rank = part[0];
+  if (rank >= k) return;
+  const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+  for (int r = threadIdx.x; r < l; r += 256) {
+    Ut[(int64_t)r * ldk + rank] = Mc[(int64_t)j * ldc + r] * inv;
+    Vt[(int64_t)r * ldk + rank] = Vc[(int64_t)j * ldc + r];
+  }
+  if (threadIdx.x == 0) sv[rank] = sj;
+}
+
+// M: l x l in an LPm-wide row-major buffer. tol <= 0: sqrt(l) 2^-52.
+// max_sweeps <= kWideMaxSweeps.
+hipError_t launch_jacobi_wide(const double* M, int LPm, int l, int k, int max_sweeps, double* Ut, double* sv,
+                              double* Vt, int ldk, void* scratch, void* info, hipStream_t st, double tol) {
+  if (l < 2 || k < 1 || k > l || max_sweeps < 1 || max_sweeps > kWideMaxSweeps) return hipErrorInvalidValue;
+  const WideJacDims d = wjac_dims(l);
+  const int ncp = d.nbe * d.B;
+  double* Mc = reinterpret_cast<double*>(scratch);
+  double* Vc = Mc + (size_t)ncp * d.ldc;
+  double* sig = Vc + (size_t)ncp * d.ldc;
+  int* cnt = reinterpret_cast<int*>(sig + l);
+  const int* conv = cnt + max_sweeps;
+  const double tol2 = tol > 0.0 ? tol * tol : (double)l * 0x1p-104;
+  DevInfo* di = (DevInfo*)info;
+  const int64_t tot = (int64_t)ncp * d.ldc;
+  hipLaunchKernelGGL(k_wjac_init, dim3((unsigned)std::min<int64_t>(1024, ceil_div(tot, 256))), dim3(256), 0, st, M,
+                     LPm, l, ncp, d.ldc, Mc, Vc, cnt, max_sweeps);
+  const size_t shm = ((size_t)2 * d.B * d.ldc + 4 * d.B * d.B) * 8;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    for (int t = 0; t < d.nbe - 1; ++t) {
+      if (d.B == 16)
+        hipLaunchKernelGGL(k_wjac_step<16>, dim3((unsigned)(d.nbe / 2)), dim3(256), shm, st, Mc, Vc, d.ldc, l, d.nbe,
+                           t, sw, cnt, conv, tol2);
+      else
+        hipLaunchKernelGGL(k_wjac_step<8>, dim3((unsigned)(d.nbe / 2)), dim3(256), shm, st, Mc, Vc, d.ldc, l, d.nbe,
+                           t, sw, cnt, conv, tol2);
+    }
+    hipLaunchKernelGGL(k_wjac_sweep_end, dim3(1), dim3(64), 0, st, cnt, sw, max_sweeps, di);
+  }
+  hipLaunchKernelGGL(k_wjac_norms, dim3((unsigned)l), dim3(256), 0, st, Mc, d.ldc, l, sig);
+  hipLaunchKernelGGL(k_wjac_out, dim3((unsigned)l), dim3(256), 0, st, Mc, Vc, d.ldc, l, k, sig, Ut, sv, Vt, ldk);
+  return hipGetLastError();
+}
+
+}  // namespace sor

@@ -97,8 +97,18 @@ def test_sorsvd_rejects_bad_arguments_before_launch(clib):
     assert _call(clib, wsb=1024) == EWORKSPACE
     assert _call(clib, ws=257) == EINVAL           # misaligned workspace
     assert _call(clib, t=7) == EINVAL
-    big = _lib.Opts(l=300)
-    assert _call(clib, k=200, ldu=200, ldv=200, opts=big) == EUNSUPPORTED  # wider than this build's passes
+    big = _lib.Opts(l=1100)
+    assert _call(clib, m=2000, n=1500, lda=1500, k=200, ldu=200, ldv=200, opts=big) == EUNSUPPORTED  # l > 1024
+
+
+def test_wide_sketches_have_a_workspace(clib):
+    # widths up to 1024 (column-blocked passes, blocked QR factor and core SVD)
+    for t in (P.SORSVD_F64, P.SORSVD_F32, P.SORSVD_BF16, P.SORSVD_F16):
+        for l in (129, 200, 256, 300, 512, 700, 1024):
+            o = _lib.Opts(l=l)
+            assert clib.sorsvd_workspace_bytes(4000, 3000, min(l, 100), 1, t, ctypes.byref(o)) > 0, (t, l)
+    o = _lib.Opts(l=1025)
+    assert clib.sorsvd_workspace_bytes(4000, 3000, 100, 1, P.SORSVD_F64, ctypes.byref(o)) == 0
 
 
 def test_step_entry_points_reject_bad_arguments(clib):

@@ -112,16 +112,21 @@ def test_batched_diagonal_equals_single(lib):
 
 
 def test_auto_fallback_and_judge(lib):
-    # fast decay: the fallback (k = 128, q = 2) meets 1e-3; the identity is the FP32 judge
+    # fast decay: the first fixed rung (k = 256, q = 2) meets 1e-3; the identity is the FP32 judge
     n = 1500
     A, _, _ = W.spectral(n, n, np.arange(1, n + 1) ** -2.5, 9)
     U, S, V, info = lib.auto(torch.as_tensor(A, dtype=torch.float32).cuda(), 1e-3, None, seed=1)
-    assert info["met"] and info["used_fallback"] == 1 and info["k_used"] == 128 and info["q_used"] == 2
-    assert info["err"] <= 1e-3
-    # slow decay: nothing of width <= 128 meets 1e-3 -> ETOL with the fallback's result
+    assert info["met"] and info["used_fallback"] == 1 and info["k_used"] == 256 and info["q_used"] == 2
+    assert info["runs"] == 1 and info["err"] <= 1e-3
+    # j^-1.5: the Eckart-Young floor at 256 is above 1e-3 (2.4e-3), so the
+    # ladder doubles the width until the judge accepts (512: floor 1.2e-3; 1024)
+    C, _, _ = W.spectral(n, n, np.arange(1, n + 1) ** -1.5, 11)
+    _, _, _, info3 = lib.auto(torch.as_tensor(C, dtype=torch.float32).cuda(), 1e-3, None, seed=1)
+    assert info3["met"] and info3["k_used"] == 1024 and info3["runs"] == 3 and info3["err"] <= 1e-3
+    # slow decay: nothing of width <= 1024 meets 1e-3 -> ETOL with the last rung's result
     B, _, _ = W.spectral(n, n, np.arange(1, n + 1) ** -0.8, 10)
     _, _, _, info2 = lib.auto(torch.as_tensor(B, dtype=torch.float32).cuda(), 1e-3, None, seed=1)
-    assert not info2["met"] and info2["err"] > 1e-3
+    assert not info2["met"] and info2["err"] > 1e-3 and info2["k_used"] == 1024
 
 
 def test_auto_run_from_probe_matches_oracle(lib):
