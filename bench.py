@@ -263,7 +263,7 @@ RPCA_DESC = ("robust PCA by the ALM-SOR-SVD iteration (Table III): X = L + S, n 
              "(N(0,1) factors), 5% of entries +-50, l = 2 rank, q = 1, tol 1e-7 (the paper's Table IV setup)")
 
 
-def run_rpca(torch, P, sizes=(1000, 1280), reps=3):
+def run_rpca(torch, P, sizes=(1000, 2000, 3000), reps=3):
     """Time to solve one RPCA problem (all iterations, host loop included)."""
     import numpy as np
     out = {"workload": RPCA_DESC, "cases": {}}

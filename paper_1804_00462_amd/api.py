@@ -432,8 +432,13 @@ def auto(A, tol, params=None, seed=0):
     """Learned (k, q) + judge + fallback (params None: fallback only). Returns (U, S, V, info dict, status)."""
     torch = _torch()
     lib = _lib.load()
-    _check_matrix(A)
-    code, (m, n) = dtype_code(A.dtype), A.shape
+    if A.dim() == 1:  # A = diag(sigma), FP64 (the stand-in of the training spectra)
+        if A.dtype != torch.float64 or not A.is_cuda:
+            raise ValueError("diagonal A must be a 1-D FP64 device tensor")
+        code, m, n, lda = SORSVD_DIAG, A.shape[0], A.shape[0], A.shape[0]
+    else:
+        _check_matrix(A)
+        code, (m, n), lda = dtype_code(A.dtype), A.shape, A.stride(0)
     kcap = min(1024, m, n)
     nbytes = int(lib.sorsvd_auto_workspace_bytes(m, n, code))
     if nbytes == 0:
@@ -443,7 +448,7 @@ def auto(A, tol, params=None, seed=0):
     S = torch.empty(kcap, dtype=torch.float64, device=A.device)
     V = torch.empty(n, kcap, dtype=torch.float64, device=A.device)
     out = AutoInfo()
-    st = lib.sorsvd_auto(_ptr(A), A.stride(0), code, m, n, seed, float(tol),
+    st = lib.sorsvd_auto(_ptr(A), lda, code, m, n, seed, float(tol),
                          _ptr(params) if params is not None else None, _ptr(U), kcap, _ptr(S), _ptr(V), kcap,
                          _ptr(ws), nbytes, _stream(), ctypes.byref(out))
     if st not in (0, -6):

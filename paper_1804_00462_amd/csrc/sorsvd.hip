@@ -118,7 +118,8 @@ hipError_t launch_chol_wide(double* G, int LP, int l, int64_t rows, int mode, do
                             void* scratch, hipStream_t st);
 size_t jacobi_wide_bytes(int l);
 hipError_t launch_jacobi_wide(const double* M, int LPm, int l, int k, int max_sweeps, double* Ut, double* sv,
-                              double* Vt, int ldk, void* scratch, void* info, hipStream_t st, double tol);
+                              double* Vt, int ldk, void* scratch, void* info, hipStream_t st, double tol,
+                              bool trans = false);
 
 namespace {
 
@@ -892,12 +893,35 @@ int sorsvd_step_core_svd(const double* M, int64_t l, int64_t k, double* Ut, doub
   SORSVD_TRY(launch_fill(Ut, l * k, 0.0, st));
   SORSVD_TRY(launch_fill(Vt, l * k, 0.0, st));
   if (p.wide) {
-    // a general M (not the near-triangular core matrix of the method) can
-    // take as many sweeps as the one-workgroup kernel's default allows
+    // A general M (unlike the core matrix of the method, which is R2^T of
+    // the last QR step up to rounding) is first factored M = Q R (Cholesky
+    // QR); one-sided Jacobi on R^T then needs far fewer sweeps (the QR
+    // preconditioning of Drmac and Veselic). With R^T = U' S V'^T,
+    // M = (Q V') S U'^T.
     if (max_sweeps > kWideMaxSweeps) return SORSVD_EINVAL;
     const int ms = max_sweeps > 0 ? max_sweeps : 40;
-    SORSVD_TRY(launch_jacobi_wide(M, (int)l, (int)l, (int)k, ms, Ut, s, Vt, (int)k, at<void>(ws, p.off_wjac),
-                                  at<void>(ws, p.off_info), st, 0.0));
+    const int LP = (int)p.LP, KP = (int)p.KP;
+    double* Tq = at<double>(ws, p.off_t1);  // M, then Q (l x LP)
+    double* Mp = at<double>(ws, p.total);   // M (l x LP)
+    double* P = at<double>(ws, p.off_p);
+    double* R = at<double>(ws, p.off_m);
+    double* Ua = at<double>(ws, p.off_ut);  // U' (l x KP)
+    double* Va = at<double>(ws, p.off_vt);  // V' (l x KP)
+    double* QV = at<double>(ws, p.off_u64);
+    SORSVD_TRY(launch_pack_f64(M, l, (int)l, l, Tq, LP, st));
+    SORSVD_TRY(launch_pack_f64(M, l, (int)l, l, Mp, LP, st));
+    if ((rc = tsqr_inplace(p, Tq, l, p.gram_m, ws, st))) return rc;
+    SORSVD_TRY(launch_skinny_f64(true, Tq, LP, LP, l, Mp, LP, LP, p.gram_m.kchunk, p.gram_m.nsplit, P, nullptr,
+                                 nullptr, st, nullptr, false, p.ncb));
+    SORSVD_TRY(launch_reduce_f64(P, LP, LP, p.gram_m.nsplit, R, LP, LP, st));
+    SORSVD_TRY(launch_fill(Ua, (int64_t)LP * KP, 0.0, st));
+    SORSVD_TRY(launch_fill(Va, (int64_t)LP * KP, 0.0, st));
+    SORSVD_TRY(launch_jacobi_wide(R, LP, (int)l, (int)k, ms, Ua, s, Va, KP, at<void>(ws, p.off_wjac),
+                                  at<void>(ws, p.off_info), st, 0.0, true));
+    SORSVD_TRY(launch_skinny_f64(false, Tq, LP, l, LP, Va, KP, KP, LP, 1, QV, nullptr, nullptr, st, nullptr, false,
+                                 p.ncbk));
+    SORSVD_TRY(launch_pack_f64(QV, l, (int)k, KP, Ut, (int)k, st));
+    SORSVD_TRY(launch_pack_f64(Ua, l, (int)k, KP, Vt, (int)k, st));
     return SORSVD_OK;
   }
   const int ms = max_sweeps > 0 ? max_sweeps : 40;
@@ -1087,7 +1111,19 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
   double* keep_n = nullptr;
   int64_t keep_ld = 0;
   int keep_parts = 0;
-  const double ridge = a_type == SORSVD_BF16 ? 312.0 : 39.0;  // width where a pass turns MFMA-bound
+  // Modelled time of a run of width k with q power steps (seconds), to pick
+  // q among the predicted widths: the passes over A (bytes at ~5 TB/s or
+  // flops at the MFMA rate reached, whichever is larger), the FP64 Cholesky
+  // QRs of the two sketches (a Gram and an apply per step, ~2 steps per QR)
+  // and the core SVD (~1e-11 k^3 s for the blocked one-sided Jacobi).
+  const double es = a_type == SORSVD_BF16 ? 2.0 : (a_type == SORSVD_F32 ? 4.0 : 8.0);
+  const double rate = a_type == SORSVD_BF16 ? 1.2e15 : (a_type == SORSVD_F32 ? 9e13 : 4e13);
+  auto model_s = [&](double kk, int qq) {
+    const double passes = 2.0 * qq + (a_type == SORSVD_BF16 ? 2.0 : 3.0);  // see auto_opts
+    const double t_pass = std::max((double)m * n * es / 5e12, 2.0 * m * n * kk / rate);
+    const double t_qr = (2.0 * qq + 2.0) * 2.0 * 3.0 * (double)(m + n) / 2.0 * kk * kk / 4e13;
+    return passes * t_pass + t_qr + 1e-11 * kk * kk * kk;
+  };
   int64_t k = std::min(kAutoFallbackK, kcap);
   int q = kAutoFallbackQ;
   bool predicted = false;
@@ -1117,8 +1153,7 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
       const double kk = std::ceil(kAutoMargin * out->k_pred[qq] / 8.0) * 8.0;
       if (!(kk <= (double)kcap)) continue;
       const int64_t ki = std::max<int64_t>(1, (int64_t)kk);
-      const double passes = 2.0 * qq + (a_type == SORSVD_BF16 ? 2.0 : 3.0);  // see auto_opts
-      const double cost = passes * std::max(1.0, (double)ki / ridge);
+      const double cost = model_s((double)ki, qq);
       if (cost < best) {
         best = cost;
         k = ki;

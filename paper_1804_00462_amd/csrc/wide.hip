@@ -398,12 +398,12 @@ size_t jacobi_wide_bytes(int l) {
 }
 
 __global__ void __launch_bounds__(256)
-k_wjac_init(const double* __restrict__ M, int LPm, int l, int ncp, int ldc, double* __restrict__ Mc,
+k_wjac_init(const double* __restrict__ M, int LPm, int l, int trans, int ncp, int ldc, double* __restrict__ Mc,
             double* __restrict__ Vc, int* __restrict__ cnt, int max_sweeps) {
   const int64_t tot = (int64_t)ncp * ldc;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
     const int j = (int)(e / ldc), i = (int)(e % ldc);
-    Mc[e] = (i < l && j < l) ? M[(int64_t)i * LPm + j] : 0.0;
+    Mc[e] = (i < l && j < l) ? M[trans ? (int64_t)j * LPm + i : (int64_t)i * LPm + j] : 0.0;
     Vc[e] = (i == j && j < l) ? 1.0 : 0.0;
   }
   if (blockIdx.x == 0)
@@ -564,9 +564,9 @@ k_wjac_out(const double* __restrict__ Mc, const double* __restrict__ Vc, int ldc
 }
 
 // M: l x l in an LPm-wide row-major buffer. tol <= 0: sqrt(l) 2^-52.
-// max_sweeps <= kWideMaxSweeps.
+// max_sweeps <= kWideMaxSweeps; trans: the SVD of M^T.
 hipError_t launch_jacobi_wide(const double* M, int LPm, int l, int k, int max_sweeps, double* Ut, double* sv,
-                              double* Vt, int ldk, void* scratch, void* info, hipStream_t st, double tol) {
+                              double* Vt, int ldk, void* scratch, void* info, hipStream_t st, double tol, bool trans) {
   if (l < 2 || k < 1 || k > l || max_sweeps < 1 || max_sweeps > kWideMaxSweeps) return hipErrorInvalidValue;
   const WideJacDims d = wjac_dims(l);
   const int ncp = d.nbe * d.B;
@@ -579,7 +579,7 @@ hipError_t launch_jacobi_wide(const double* M, int LPm, int l, int k, int max_sw
   DevInfo* di = (DevInfo*)info;
   const int64_t tot = (int64_t)ncp * d.ldc;
   hipLaunchKernelGGL(k_wjac_init, dim3((unsigned)std::min<int64_t>(1024, ceil_div(tot, 256))), dim3(256), 0, st, M,
-                     LPm, l, ncp, d.ldc, Mc, Vc, cnt, max_sweeps);
+                     LPm, l, trans ? 1 : 0, ncp, d.ldc, Mc, Vc, cnt, max_sweeps);
   const size_t shm = ((size_t)2 * d.B * d.ldc + 4 * d.B * d.B) * 8;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int t = 0; t < d.nbe - 1; ++t) {

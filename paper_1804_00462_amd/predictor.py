@@ -8,13 +8,15 @@ training (every step on the GPU through the library's entry points).
   running the method itself. Training spectra are diagonal stand-ins
   A = diag(sigma) (the Gaussian Omega is rotation-invariant, so this is exact in
   distribution for U diag(sigma) V^T with Haar U, V). Two reductions keep the
-  labelling cheap without changing the answer:
+  labelling cheap:
     - Eckart-Young censoring: the method never beats the rank-k floor (Th. 1),
-      so a spectrum whose floor at k = 128 exceeds the tolerance is labelled
-      "more than 128" (log2 256) without a run;
-    - tail truncation: runs use the leading 2048 diagonal entries and add the
+      so a spectrum whose floor at k = 1024 (the widest sketch) exceeds the
+      tolerance is labelled "more than 1024" (log2 2048) without a run;
+    - tail truncation: runs use the leading 2048 diagonal entries (widths up to
+      128; the batched engine) or 4096 (wider; one run each) and add the
       energy of the rest back into the error identity (those directions are
-      outside every rank-128 sketch subspace of the truncated problem).
+      nearly outside the sketch subspaces of the truncated problem; this is
+      an approximation of the labels, not of the method).
   Candidate widths are multiples of the Eckart-Young width k_EY; the label is
   the crossing of the tolerance, interpolated in log error between the widest
   failing and the narrowest passing candidate.
@@ -32,10 +34,13 @@ from . import api
 from ._lib import SORSVD_DIAG
 
 TOL = 1e-3
-KCAP = 128
-N_LAB = 2048
-CENSORED = 8.0  # log2(256): "needs more than 128"
+KCAP = 1024        # widest sketch
+NARROW = 128       # widest problem of the batched engine
+N_LAB = 2048       # diagonal entries kept for runs of width <= NARROW
+N_LAB_WIDE = 4096  # ... and for wider runs
+CENSORED = 11.0    # log2(2048): "needs more than 1024"
 WIDTH_FACTORS = (1.0, 1.1, 1.25, 1.5, 2.0, 3.0)
+WIDE_FACTORS = (1.0, 1.25, 1.6, 2.0)  # fewer candidates where every run is a single wide SOR-SVD
 PARAMS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "predictor_params.f32")
 PARAMS_FILE_BF16 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "predictor_params_bf16.f32")
 # relative Frobenius size of the rounding of a dense matrix with Gaussian-like
@@ -56,14 +61,25 @@ def ey_floor(sigma, kmax=KCAP):
 
 
 def candidate_widths(sigma, tol=TOL):
-    """(k_EY, candidate widths) or (None, []) if no width <= 128 can meet tol."""
+    """(k_EY, candidate widths) or (None, []) if no width <= KCAP can meet tol.
+    Narrow candidates (k_EY <= 128) end with 128 and, where 128 may still fail,
+    the wide ladder 256, 512, 1024; wide ones are multiples of k_EY up to 1024."""
     e = ey_floor(sigma)
     ok = np.nonzero(e <= tol)[0]
     if ok.size == 0:
         return None, []
     k_ey = max(1, int(ok[0]))
-    ws = sorted({min(KCAP, max(k_ey, int(math.ceil(f * k_ey)))) for f in WIDTH_FACTORS} | {KCAP})
-    return k_ey, ws
+    if k_ey <= NARROW:
+        ws = {min(NARROW, max(k_ey, int(math.ceil(f * k_ey)))) for f in WIDTH_FACTORS} | {NARROW}
+        if 3 * k_ey > NARROW:
+            ws |= {256, 512, KCAP}
+    else:
+        ws = {min(KCAP, max(k_ey, int(math.ceil(f * k_ey)))) for f in WIDE_FACTORS} | {KCAP}
+    return k_ey, sorted(ws)
+
+
+def _nlab(n, w):
+    return min(n, N_LAB if w <= NARROW else N_LAB_WIDE)
 
 
 def label_spectra(spectra, tol=TOL, batch_bytes=24e9, log=print):
@@ -71,23 +87,30 @@ def label_spectra(spectra, tol=TOL, batch_bytes=24e9, log=print):
     torch = _torch()
     count = len(spectra)
     labels = np.full((count, 4), CENSORED)
-    probs = []          # (spectrum, width, q)
+    probs = []          # (spectrum, width, q), widths <= NARROW: the batched engine
+    wide = []           # wider: one SOR-SVD each
     dev = {}
     meta = {}
     for i, (_, n, s) in enumerate(spectra):
         k_ey, ws = candidate_widths(s, tol)
         if k_ey is None:
             continue
-        nl = min(n, N_LAB)
-        tail = float(np.sum(s[nl:] ** 2))
-        meta[i] = (float(np.sum(s ** 2)), float(np.sum(s[:nl] ** 2)), tail, ws)
+        meta[i] = (float(np.sum(s ** 2)), ws)
         for w in ws:
-            if w > nl:
+            if w > _nlab(n, w):
                 continue
             for q in range(4):
-                probs.append((i, w, q))
-    log(f"[labels] {len(meta)} of {count} spectra can meet {tol:g} with k <= {KCAP}; {len(probs)} runs")
+                (probs if w <= NARROW else wide).append((i, w, q))
+    log(f"[labels] {len(meta)} of {count} spectra can meet {tol:g} with k <= {KCAP}; "
+        f"{len(probs)} batched runs, {len(wide)} wide runs")
     err = {}
+
+    def record(i, w, q, e_run):
+        _, n, s = spectra[i]
+        nl = _nlab(n, w)
+        trunc, tail = float(np.sum(s[:nl] ** 2)), float(np.sum(s[nl:] ** 2))
+        err[(i, w, q)] = math.sqrt(max((e_run ** 2) * trunc + tail, 0.0) / meta[i][0])
+
     t0 = time.perf_counter()
     start = 0
     while start < len(probs):
@@ -101,7 +124,7 @@ def label_spectra(spectra, tol=TOL, batch_bytes=24e9, log=print):
         mats, ks, qs, seeds = [], [], [], []
         for i, w, q in chunk:
             if i not in dev:
-                dev[i] = torch.as_tensor(spectra[i][2][:min(spectra[i][1], N_LAB)]).cuda()
+                dev[i] = torch.as_tensor(spectra[i][2][:_nlab(spectra[i][1], w)]).cuda()
             mats.append(dev[i])
             ks.append(w)
             qs.append(q)
@@ -110,14 +133,28 @@ def label_spectra(spectra, tol=TOL, batch_bytes=24e9, log=print):
         b.run()
         infos = b.info()
         for (i, w, q), inf in zip(chunk, infos):
-            tot, trunc, tail, _ = meta[i]
-            e2 = (inf["err_fro"] ** 2) * trunc + tail
-            err[(i, w, q)] = math.sqrt(max(e2, 0.0) / tot)
+            record(i, w, q, inf["err_fro"])
         b.close()
         del b
         start = end
         log(f"[labels] {end}/{len(probs)} runs, {time.perf_counter() - t0:.1f} s")
-    for i, (_, _, _, ws) in meta.items():
+    dev.clear()
+    # wide runs, grouped by shape so that one plan (workspace) serves each group
+    groups = {}
+    for i, w, q in wide:
+        groups.setdefault((_nlab(spectra[i][1], w), w, q), []).append(i)
+    done = 0
+    for (nl, w, q), idx in sorted(groups.items()):
+        plan = api.Plan(nl, nl, w, q, SORSVD_DIAG)
+        for i in idx:
+            sig = torch.as_tensor(spectra[i][2][:nl]).cuda()
+            plan.run(sig, seed=1000 + i)
+            record(i, w, q, plan.info()["err_fro"])
+            done += 1
+        del plan
+        if done % 2000 < len(idx):
+            log(f"[labels] {done}/{len(wide)} wide runs, {time.perf_counter() - t0:.1f} s")
+    for i, (_, ws) in meta.items():
         for q in range(4):
             prev = None
             for w in ws:
@@ -220,12 +257,13 @@ def load_params(path=PARAMS_FILE, device="cuda"):
     return torch.as_tensor(p).to(device)
 
 
-def eval_matrix(n, sigma, seed, rank=2048, device="cuda"):
-    """FP64 device matrix U diag(sigma) V^T (n x n) with Haar U, V restricted to the
-    leading `rank` singular values (the rest is dropped; for spectra that a width
-    <= 128 can resolve to 1e-3 their energy is below 1e-15 relative)."""
+def eval_matrix(n, sigma, seed, rank=None, device="cuda"):
+    """FP64 device matrix U diag(sigma) V^T (n x n) with Haar U, V; with `rank`
+    only the leading `rank` singular values are kept (the relative Frobenius
+    size of what is dropped is sqrt(sum_{j > rank} sigma_j^2) / ||sigma||, which
+    the caller must keep well below its tolerance)."""
     torch = _torch()
-    r = min(n, rank)
+    r = n if rank is None else min(n, rank)
     g = torch.Generator(device=device)
     g.manual_seed(seed)
 
@@ -261,9 +299,44 @@ def true_error(A64, U, S, V):
     return float(torch.linalg.norm(A64 - (U * S) @ V.T) / torch.linalg.norm(A64))
 
 
+def heldout_eval(params, count=200, seed=77, tol=TOL, log=print):
+    """The learned choice against the fixed ladder on held-out spectra (drawn
+    like the training spectra, another seed), as diagonal stand-ins at their
+    nominal size (exact in distribution for Haar U, V; FP64). Returns the share
+    of spectra whose predicted run met the tolerance at once, the share met by
+    either, and the mean number of SOR-SVD runs and summed widths (the work)
+    of each."""
+    import workloads as W
+    torch = _torch()
+    spectra = W.c5_training_spectra(count, seed)
+    first = met_l = met_p = 0
+    runs_l = runs_p = width_l = width_p = 0
+    reachable = 0
+    for i, (_, n, s) in enumerate(spectra):
+        if ey_floor(s, min(KCAP, n))[-1] > tol:
+            continue  # no width <= 1024 can meet tol: both end at ETOL
+        reachable += 1
+        sig = torch.as_tensor(s).cuda()
+        _, _, _, il = api.auto(sig, tol, params, seed=1000 + i)
+        _, _, _, ip = api.auto(sig, tol, None, seed=1000 + i)
+        first += int(il["met"] and not il["used_fallback"])
+        met_l += int(il["met"])
+        met_p += int(ip["met"])
+        runs_l += il["runs"]
+        runs_p += ip["runs"]
+        width_l += il["k_used"] if il["runs"] == 1 else il["k_used"] * il["runs"]
+        width_p += ip["k_used"] if ip["runs"] == 1 else ip["k_used"] * ip["runs"]
+    r = max(reachable, 1)
+    out = {"spectra": count, "reachable": reachable, "first_run_success": first / r, "met_learned": met_l / r,
+           "met_plain": met_p / r, "mean_runs_learned": runs_l / r, "mean_runs_plain": runs_p / r}
+    log(f"[heldout] {out}")
+    return out
+
+
 def compare(A64, tol, params, seed=1, log=print, label=""):
-    """BF16 + learned against FP32 plain (fixed (128, 2) + judge), and the other
-    two combinations, on one FP64 matrix: time-to-tolerance and true error."""
+    """BF16 + learned against FP32 plain (the fixed ladder (256, 2), (512, 2),
+    (1024, 2) + judge), and the other two combinations, on one FP64 matrix:
+    time-to-tolerance and true error."""
     torch = _torch()
     out = {}
     p16 = load_params("bf16") if os.path.exists(PARAMS_FILE_BF16) else params

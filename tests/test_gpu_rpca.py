@@ -43,6 +43,27 @@ def test_rpca_matches_oracle_and_recovers(lib, n, frac):
     assert abs(info["xi"] - io["xi"]) <= 1e-3 * io["xi"]
 
 
+@pytest.mark.parametrize("n,frac", [(2000, 0.05), (3000, 0.05), (2000, 0.1)])
+def test_rpca_paper_sizes_recover(lib, n, frac):
+    """The sizes of the paper's Tables IV and V (l = 2 rank = 200, 300: the
+    wide-sketch path): rank and support recovered exactly; n = 2000 also
+    against the oracle from the same start."""
+    r = int(0.05 * n)
+    L0, S0 = problem(n, r, frac, 1)
+    X = L0 + S0
+    L, S, info = lib.rpca(torch.as_tensor(X).cuda(), 2 * r, q=1, seed=3)
+    L, S = L.cpu().numpy(), S.cpu().numpy()
+    assert info["met"] and info["xi"] < 1e-7
+    assert info["rank"] == r
+    assert np.array_equal(S != 0, S0 != 0)
+    assert np.linalg.norm(L - L0) <= 1e-5 * np.linalg.norm(L0)
+    if n == 2000 and frac == 0.05:
+        Lo, So, io = orpca.alm_sorsvd(X, 2 * r, q=1, seed=3, norm2=info["norm2"])
+        assert info["iters"] == io["iters"]
+        assert np.linalg.norm(L - Lo) <= 1e-8 * np.linalg.norm(Lo)
+        assert np.linalg.norm(S - So) <= 1e-8 * np.linalg.norm(So)
+
+
 def test_rpca_stops_at_max_iter_with_the_last_iterate(lib):
     L0, S0 = problem(120, 6, 0.05, 2)
     X = torch.as_tensor(L0 + S0).cuda()

@@ -77,22 +77,26 @@ def test_wide_core_svd_against_lapack(lib, l, k):
     Va = align_signs(Vt, Vrt[:k].T)
     assert np.abs(Ua - Ur[:, :k])[:, gap_ok].max(initial=0) < 1e-8
     assert np.abs(Va - Vrt[:k].T)[:, gap_ok].max(initial=0) < 1e-8
-    assert np.abs(Ut.T @ Ut - np.eye(k)).max() < 1e-12
-    assert np.abs(Vt.T @ Vt - np.eye(k)).max() < 1e-12
+    # (V' accumulates the rotation products of every step: drift ~ steps u)
+    assert np.abs(Ut.T @ Ut - np.eye(k)).max() < 5e-12
+    assert np.abs(Vt.T @ Vt - np.eye(k)).max() < 5e-12
     # M V = U diag(s)
     assert np.abs(Mtx @ Vt - Ut * s[None, :]).max() < 1e-12 * s[0]
 
 
 def test_wide_core_svd_diagonal_is_a_permutation(lib):
-    """Orthogonal columns take no rotation: V is the permutation that sorts them."""
+    """Orthogonal columns: after the QR preconditioning (which reproduces a
+    diagonal M to rounding) no rotation is needed, and V is the permutation
+    that sorts the values."""
     l = 300
     d = W.rng(4).permutation(np.arange(1, l + 1)).astype(np.float64)
     Ut, s, Vt, info = lib.step_core_svd(dev(np.diag(d)), l)
     order = np.argsort(-d, kind="stable")
-    assert np.array_equal(host(s), d[order])
+    assert np.max(np.abs(host(s) - d[order]) / d[order]) <= 8 * 2.0 ** -52
     P = np.eye(l)[:, order]
-    assert np.array_equal(np.abs(host(Vt)), P)
-    assert info["sweeps"] == 1
+    assert np.abs(np.abs(host(Vt)) - P).max() <= 1e-15
+    assert np.abs(np.abs(host(Ut)) - P).max() <= 1e-15
+    assert info["sweeps"] <= 2
 
 
 @pytest.mark.parametrize("rows,l,cond", [(3000, 256, 1e2), (5000, 512, 1e6), (2500, 1024, 1e4),
