@@ -152,6 +152,25 @@ int sorsvd(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
 int sorsvd_read_info(const void* workspace, sorsvd_info* out, void* stream);
 
 /*
+ * sorsvd_noalloc - sorsvd() that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Arguments as sorsvd(); the workspace is a
+ * fixed array of SORSVD_NOALLOC_BYTES in device memory that the library holds
+ * on every device it runs on until the process ends (its address is taken on
+ * a device's first call). A problem whose workspace (sorsvd_workspace_bytes)
+ * exceeds it returns SORSVD_EWORKSPACE before anything is enqueued. Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (other streams, other threads) race, and must be serialised by the
+ * caller. info (host, nullable): when given, the stream is synchronised and
+ * the result record copied there (leave it null under graph capture).
+ */
+#define SORSVD_NOALLOC_BYTES ((size_t)64 << 20)
+int sorsvd_noalloc(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
+                   int64_t k, int32_t q, uint64_t seed,
+                   double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                   void* stream, const sorsvd_opts* opts, sorsvd_info* info);
+
+/*
  * sorsvd_pack_f16 - FP16 storage of an FP32 / FP64 matrix with power-of-two
  * column scaling (the input form of SORSVD_F16 with opts.col_exp). Not part
  * of the method: it extends the reduced-precision storage of A to FP16's

@@ -58,6 +58,8 @@ _SIGS = {
     "sorsvd": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_i64, c_i32, c_u64,
                        c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp, c_vp]),
     "sorsvd_read_info": (c_i32, [c_vp, c_vp, c_vp]),
+    "sorsvd_noalloc": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_i64, c_i32, c_u64,
+                               c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "sorsvd_pack_f16": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "sorsvd_philox_normal": (c_i32, [c_u64, c_u64, c_u64, c_i64, c_i64, c_vp, c_vp]),
     "sorsvd_step_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i32]),

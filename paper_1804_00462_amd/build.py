@@ -29,6 +29,7 @@ SOURCES = {
     "gemm.hip": [],
     "sorsvd.hip": [],
     "pack.hip": [],
+    "noalloc.hip": [],
     "residual.hip": [],
     "mlp.hip": [],
     "rpca.hip": [],
