@@ -100,6 +100,15 @@ typedef struct sorsvd_opts {
                              result (U, S, V, ||A||_F, errors) is that of A, not of A_stored.
                              |e_j| <= 256 keeps every FP64 intermediate in range; larger
                              values set flags bit 3 and the run goes on with them. */
+  int32_t literal;    /* 1 = Alg. 4 as printed: T2 <- Omega, q + 1 times {T1 = A T2; T2 = A^T T1}
+                         with no orthonormalisation between the products, then Q1 = qr(T1),
+                         Q2 = qr(T2) and M = Q1^T A Q2. The products' condition number grows
+                         as (sigma_1 / sigma_l)^(2q+2), so this mode suits well-conditioned
+                         inputs only (the default orthonormalises after every product, same
+                         spans in exact arithmetic by Lemma 1). Not with pass_efficient, not
+                         for the DIAG type (SORSVD_EUNSUPPORTED). */
+  int32_t out_f32;    /* 1 = U and V are written as FP32 (the U and V pointers are float*,
+                         ldu / ldv in elements); S and everything before the output stay FP64 */
 } sorsvd_opts;
 
 /* Result record, kept by the library in the first 256 bytes of the workspace. */
@@ -133,7 +142,8 @@ size_t sorsvd_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t q,
  *   k    target rank, 1 <= k <= min(m, n).  q >= 0 power steps.
  *   seed Philox key word of Omega: Omega[i][j] is N(0,1) draw number i + j*n of
  *        key (seed, 0) (see sorsvd_philox_normal).
- *   U    m x k FP64, ldu >= k.   S  k FP64 (descending).   V  n x k FP64, ldv >= k.
+ *   U    m x k FP64 (FP32 with opts.out_f32), ldu >= k.   S  k FP64 (descending).
+ *   V    n x k FP64 (FP32 with opts.out_f32), ldv >= k.
  *
  * Steps (Sec. III): T1 = A Omega; Q1 = qr(T1); Q2 = qr(A^T Q1); q times
  * {Q1 = qr(A Q2); Q2 = qr(A^T Q1)}; M = Q1^T A Q2; M = U~ S~ V~^T (FP64 one-sided
@@ -144,7 +154,7 @@ size_t sorsvd_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t q,
  */
 int sorsvd(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
            int64_t k, int32_t q, uint64_t seed,
-           double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+           void* U, int64_t ldu, double* S, void* V, int64_t ldv,
            void* workspace, size_t ws_bytes, void* stream, const sorsvd_opts* opts);
 
 /* Copy the sorsvd_info record out of `workspace` into host memory `out`,
@@ -167,7 +177,7 @@ int sorsvd_read_info(const void* workspace, sorsvd_info* out, void* stream);
 #define SORSVD_NOALLOC_BYTES ((size_t)64 << 20)
 int sorsvd_noalloc(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n,
                    int64_t k, int32_t q, uint64_t seed,
-                   double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                   void* U, int64_t ldu, double* S, void* V, int64_t ldv,
                    void* stream, const sorsvd_opts* opts, sorsvd_info* info);
 
 /*
@@ -403,6 +413,22 @@ size_t sorsvd_auto_workspace_bytes(int64_t m, int64_t n, int32_t a_type);
 int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed, double tol,
                 const float* params, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
                 void* workspace, size_t ws_bytes, void* stream, sorsvd_auto_info* out);
+
+/*
+ * sorsvd_predict_kq - the (k, q) that sorsvd_auto would run first, without
+ * running it: the probe sketch (one pass over A), its features and the
+ * network (params as for sorsvd_auto), then the q of the least modelled time
+ * among the predicted widths (with head-room) that fit min(1024, m, n).
+ * The network was trained for tol = 1e-3 (tol must be > 0; it does not
+ * rescale the prediction). k_pred (host, nullable): the 4 raw predicted
+ * widths 2^y_q, q = 0..3. Returns SORSVD_OK, or SORSVD_ETOL with the first
+ * rung of the fixed ladder (256, 2) when no predicted width fits.
+ * Workspace: sorsvd_auto_workspace_bytes(m, n, a_type). Synchronises the
+ * stream (the prediction is read back).
+ */
+int sorsvd_predict_kq(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed,
+                      const float* params, double tol, int64_t* k_out, int32_t* q_out, double* k_pred,
+                      void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Robust PCA by the ALM-SOR-SVD iteration (Sec. V, "Robust Principal

@@ -29,7 +29,8 @@ class SorsvdError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("l", c_i64), ("max_sweeps", c_i32), ("refine", c_i32), ("residual", c_i32),
-                ("split", c_i32), ("tile", c_i32), ("pass_efficient", c_i32), ("col_exp", c_vp)]
+                ("split", c_i32), ("tile", c_i32), ("pass_efficient", c_i32), ("col_exp", c_vp),
+                ("literal", c_i32), ("out_f32", c_i32)]
 
 
 class Problem(ctypes.Structure):
@@ -58,6 +59,8 @@ _SIGS = {
     "sorsvd": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_i64, c_i32, c_u64,
                        c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp, c_vp]),
     "sorsvd_read_info": (c_i32, [c_vp, c_vp, c_vp]),
+    "sorsvd_predict_kq": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_dbl, c_vp, c_vp, c_vp,
+                                  c_vp, c_sz, c_vp]),
     "sorsvd_noalloc": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_i64, c_i32, c_u64,
                                c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "sorsvd_pack_f16": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),

@@ -49,7 +49,8 @@ def _info_dict(o):
             "sweeps": o.sweeps, "flags": o.flags, "a_noise_rel": o.a_noise_rel}
 
 
-def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0, pass_efficient=0, col_exp=None):
+def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0, pass_efficient=0, col_exp=None, literal=0,
+              out_f32=0):
     """col_exp: None, or a device int32 tensor of n column exponents (FP16 A;
     the caller keeps it alive while the options are in use)."""
     ce = None
@@ -59,7 +60,7 @@ def make_opts(l=0, max_sweeps=0, refine=0, residual=0, split=0, tile=0, pass_eff
             raise ValueError("col_exp must be a contiguous int32 device tensor")
         ce = col_exp.data_ptr()
     return Opts(l=l, max_sweeps=max_sweeps, refine=refine, residual=residual, split=split, tile=tile,
-                pass_efficient=pass_efficient, col_exp=ce)
+                pass_efficient=pass_efficient, col_exp=ce, literal=literal, out_f32=out_f32)
 
 
 def workspace_bytes(m, n, k, q, dtype_or_code, **opts):
@@ -85,9 +86,10 @@ class Plan:
             raise _lib.SorsvdError(-1, "sorsvd_workspace_bytes")
         self.ws_bytes = nbytes
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.U = torch.empty(m, k, dtype=torch.float64, device=device)
+        out_t = torch.float32 if opts.get("out_f32") else torch.float64
+        self.U = torch.empty(m, k, dtype=out_t, device=device)
         self.S = torch.empty(k, dtype=torch.float64, device=device)
-        self.V = torch.empty(n, k, dtype=torch.float64, device=device)
+        self.V = torch.empty(n, k, dtype=out_t, device=device)
 
     def run(self, A, seed=0, stream=None):
         if self.code == SORSVD_DIAG:
@@ -457,6 +459,28 @@ def auto(A, tol, params=None, seed=0):
     info = {"k_used": k, "q_used": out.q_used, "used_fallback": out.used_fallback, "runs": out.runs,
             "err": out.err, "k_pred": list(out.k_pred), "flags": out.flags, "met": st == 0}
     return U[:, :k], S[:k], V[:, :k], info
+
+
+def predict_kq(A, params, tol=1e-3, seed=0):
+    """The (k, q) sorsvd_auto would run first (probe + network), without running
+    it. Returns (k, q, k_pred list, predicted flag)."""
+    torch = _torch()
+    lib = _lib.load()
+    if A.dim() == 1:
+        code, m, n, lda = SORSVD_DIAG, A.shape[0], A.shape[0], A.shape[0]
+    else:
+        _check_matrix(A)
+        code, (m, n), lda = dtype_code(A.dtype), A.shape, A.stride(0)
+    nbytes = int(lib.sorsvd_auto_workspace_bytes(m, n, code))
+    if nbytes == 0:
+        raise _lib.SorsvdError(-1, "sorsvd_auto_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    k, q, kp = ctypes.c_int64(), ctypes.c_int32(), (ctypes.c_double * 4)()
+    st = lib.sorsvd_predict_kq(_ptr(A), lda, code, m, n, seed, _ptr(params), float(tol), ctypes.byref(k),
+                               ctypes.byref(q), kp, _ptr(ws), nbytes, _stream())
+    if st not in (0, -6):
+        check(st, "sorsvd_predict_kq")
+    return int(k.value), int(q.value), list(kp), st == 0
 
 
 def rpca(X, l, q=1, seed=0, tol=1e-7, max_iter=100):

@@ -39,7 +39,7 @@ int scratch_address(void** out) {
 }  // namespace
 
 extern "C" int sorsvd_noalloc(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, int64_t k,
-                              int32_t q, uint64_t seed, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                              int32_t q, uint64_t seed, void* U, int64_t ldu, double* S, void* V, int64_t ldv,
                               void* stream, const sorsvd_opts* opts, sorsvd_info* info) {
   void* ws = nullptr;
   int rc = scratch_address(&ws);

@@ -220,15 +220,16 @@ k_signs(const double* __restrict__ U, int ld, int k, int nblocks, const double* 
   }
 }
 
-// Stage 3: out[r][c] = sgn[c] * src[r][c] for c < k.
+// Stage 3: out[r][c] = sgn[c] * src[r][c] for c < k, in FP64 or FP32.
+template <typename TO>
 __global__ void __launch_bounds__(256)
 k_apply_signs(const double* __restrict__ src, int64_t rows, int lds, int k,
-              const double* __restrict__ sgn, double* __restrict__ out, int64_t ldo) {
+              const double* __restrict__ sgn, TO* __restrict__ out, int64_t ldo) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= rows * k) return;
   const int64_t r = idx / k;
   const int c = (int)(idx % k);
-  out[r * ldo + c] = sgn[c] * src[r * lds + c];
+  out[r * ldo + c] = (TO)(sgn[c] * src[r * lds + c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,9 +349,10 @@ hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, 
   return hipGetLastError();
 }
 
+// U, V: double* (out_f32 = 0) or float* (out_f32 = 1).
 hipError_t launch_signfix(const double* U64, int64_t m, const double* V64, int64_t n, int ld, int k,
-                          double* pval, int64_t* pidx, int nblocks_max, double* sgn, double* U,
-                          int64_t ldu, double* V, int64_t ldv, hipStream_t st) {
+                          double* pval, int64_t* pidx, int nblocks_max, double* sgn, void* U,
+                          int64_t ldu, void* V, int64_t ldv, hipStream_t st, int out_f32) {
   if (k == 0) return hipSuccess;
   int64_t rpb = ceil_div(m, nblocks_max);
   rpb = rpb < 64 ? 64 : rpb;
@@ -359,10 +361,14 @@ hipError_t launch_signfix(const double* U64, int64_t m, const double* V64, int64
     hipLaunchKernelGGL(k_colmax, dim3(nb), dim3(256), 0, st, U64, m, ld, k, rpb, pval, pidx);
     hipLaunchKernelGGL(k_signs, dim3(k), dim3(256), 0, st, U64, ld, k, nb, pval, pidx, sgn);
   }
-  if (m * k > 0)
-    hipLaunchKernelGGL(k_apply_signs, dim3((unsigned)ceil_div(m * k, 256)), dim3(256), 0, st, U64, m, ld, k, sgn, U, ldu);
-  if (n * k > 0)
-    hipLaunchKernelGGL(k_apply_signs, dim3((unsigned)ceil_div(n * k, 256)), dim3(256), 0, st, V64, n, ld, k, sgn, V, ldv);
+  const dim3 gu((unsigned)ceil_div(m * k, 256)), gv((unsigned)ceil_div(n * k, 256));
+  if (out_f32) {
+    if (m * k > 0) hipLaunchKernelGGL(k_apply_signs<float>, gu, dim3(256), 0, st, U64, m, ld, k, sgn, (float*)U, ldu);
+    if (n * k > 0) hipLaunchKernelGGL(k_apply_signs<float>, gv, dim3(256), 0, st, V64, n, ld, k, sgn, (float*)V, ldv);
+  } else {
+    if (m * k > 0) hipLaunchKernelGGL(k_apply_signs<double>, gu, dim3(256), 0, st, U64, m, ld, k, sgn, (double*)U, ldu);
+    if (n * k > 0) hipLaunchKernelGGL(k_apply_signs<double>, gv, dim3(256), 0, st, V64, n, ld, k, sgn, (double*)V, ldv);
+  }
   return hipGetLastError();
 }
 

@@ -91,8 +91,8 @@ hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, 
 size_t jacobi_log_bytes(int l, int max_sweeps);
 bool jacobi_uses_log(int l);
 hipError_t launch_signfix(const double* U64, int64_t m, const double* V64, int64_t n, int ld, int k,
-                          double* pval, int64_t* pidx, int nblocks_max, double* sgn, double* U,
-                          int64_t ldu, double* V, int64_t ldv, hipStream_t st);
+                          double* pval, int64_t* pidx, int nblocks_max, double* sgn, void* U,
+                          int64_t ldu, void* V, int64_t ldv, hipStream_t st, int out_f32);
 hipError_t launch_finalize(const double* normp, int nparts, const double* sv, int k, void* info,
                            hipStream_t st);
 hipError_t launch_info_init(void* info, hipStream_t st);
@@ -216,6 +216,8 @@ struct Plan {
   int refine;     // 16-bit A: projection pass with Q2 = hi + lo
   int residual;   // explicit residual pass after the lift
   int pass_eff;   // M from the last orbit product (no projection pass)
+  int literal;    // Alg. 4 as printed: no QR between the products
+  int out_f32;    // U and V written as FP32
   int64_t ldt;    // 16-bit A: leading dimension of the transposed skinny operands
   int rt_nn, rt_tn, rt_proj;  // 16-bit A: rows (NN) / columns (TN) of A per workgroup = 64 rt
   Split projb;    // 16-bit A: split of the refinement projection pass
@@ -272,6 +274,9 @@ int make_plan(int64_t m, int64_t n, int64_t k, int32_t q, int32_t a_type, const 
   p->refine = (h16 && o && o->refine) ? 1 : 0;
   p->residual = (o && o->residual) ? 1 : 0;
   p->pass_eff = (o && o->pass_efficient) ? 1 : 0;
+  p->literal = (o && o->literal) ? 1 : 0;
+  p->out_f32 = (o && o->out_f32) ? 1 : 0;
+  if (p->literal && (p->pass_eff || a_type == SORSVD_DIAG)) return SORSVD_EUNSUPPORTED;
   p->ldt = round_up(std::max(m, n), 128) + 128;  // room for the last step's over-read
   const int forced = o ? o->split : 0;
   const int ks = skinny_step(a_type == SORSVD_DIAG ? SORSVD_F64 : a_type);
@@ -545,8 +550,8 @@ int h16_setup(const Plan& p, void* ws, hipStream_t st) {
 // sketch A Omega' with Omega nested in Omega'), together with the sums of
 // squares of A (normp_ext, nparts_ext slots); the first pass and its QR are
 // skipped.
-int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int64_t ldu, double* S,
-        double* V, int64_t ldv, void* ws, hipStream_t st, const double* q1 = nullptr, int64_t ldq1 = 0,
+int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, void* U, int64_t ldu, double* S,
+        void* V, int64_t ldv, void* ws, hipStream_t st, const double* q1 = nullptr, int64_t ldq1 = 0,
         const double* normp_ext = nullptr, int nparts_ext = 0) {
   const int LP = (int)p.LP, KP = (int)p.KP;
   void* info = at<void>(ws, p.off_info);
@@ -577,8 +582,26 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
       SORSVD_TRY(launch_omega_bf16_t(seed, p.n, p.l, (bf16_t*)Xc, p.ldt, st));
   }
 
+  if (p.literal) {
+    // Alg. 4 as printed: T2 <- Omega; q + 1 times {T1 = A T2; T2 = A^T T1};
+    // the QRs only at the end
+    if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
+    for (int it = 0; it <= p.q; ++it) {
+      const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true);
+      if (rc) return rc;
+      if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st))) return rc;
+      if (it == p.q) break;
+      const void* X = as_operand(p, T2, p.n, ws, st, &rc);
+      if (rc) return rc;
+      if ((rc = pass(p, false, A, lda, X, T1, nullptr, ws, st))) return rc;
+    }
+    if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st))) return rc;
+    if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st))) return rc;
+  }
   // T1 = A Omega (eq. T1), with ||A||_F^2 accumulated on the way; Q1 = qr(T1).
-  if (q1) {
+  if (p.literal) {
+    // (done above)
+  } else if (q1) {
     SORSVD_TRY(launch_pack_f64(q1, p.m, (int)p.l, ldq1, T1, LP, st));
   } else {
     if ((rc = pass(p, false, A, lda, Xc, T1, normp, ws, st))) return rc;
@@ -588,19 +611,21 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
   // (the pass-efficient form with refinement splits Q1 into hi + lo for the
   // orbit product that M is formed from)
   const bool pe_lo = p.pass_eff && p.refine;
-  const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true, pe_lo && p.q == 0);
-  if (rc) return rc;
-  if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st, pe_lo && p.q == 0))) return rc;
-  if (p.pass_eff && p.q == 0) SORSVD_TRY(launch_pack_f64(T2, p.n, LP, LP, T2P, LP, st));
-  if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st, p.q == 0))) return rc;
+  if (!p.literal) {
+    const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true, pe_lo && p.q == 0);
+    if (rc) return rc;
+    if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st, pe_lo && p.q == 0))) return rc;
+    if (p.pass_eff && p.q == 0) SORSVD_TRY(launch_pack_f64(T2, p.n, LP, LP, T2P, LP, st));
+    if ((rc = tsqr_inplace(p, T2, p.n, p.gram_n, ws, st, p.q == 0))) return rc;
+  }
   // Power method (Alg. 4 loop), orthonormalising after each product.
-  for (int it = 0; it < p.q; ++it) {
+  for (int it = 0; !p.literal && it < p.q; ++it) {
     const bool last = it == p.q - 1;
     const void* X = as_operand(p, T2, p.n, ws, st, &rc);
     if (rc) return rc;
     if ((rc = pass(p, false, A, lda, X, T1, nullptr, ws, st))) return rc;
     if ((rc = tsqr_inplace(p, T1, p.m, p.gram_m, ws, st, last))) return rc;
-    Y = as_operand(p, T1, p.m, ws, st, &rc, true, pe_lo && last);
+    const void* Y = as_operand(p, T1, p.m, ws, st, &rc, true, pe_lo && last);
     if (rc) return rc;
     if ((rc = pass(p, true, A, lda, Y, T2, nullptr, ws, st, pe_lo && last))) return rc;
     if (p.pass_eff && last) SORSVD_TRY(launch_pack_f64(T2, p.n, LP, LP, T2P, LP, st));
@@ -640,14 +665,16 @@ int run(const Plan& p, const void* A, int64_t lda, uint64_t seed, double* U, int
                                p.ncbk));
   SORSVD_TRY(launch_signfix(U64, p.m, V64, p.n, KP, (int)p.k, at<double>(ws, p.off_pval),
                             at<int64_t>(ws, p.off_pidx), kSignBlocks, at<double>(ws, p.off_sgn), U, ldu,
-                            V, ldv, st));
+                            V, ldv, st, p.out_f32));
   SORSVD_TRY(launch_finalize(normp_ext ? normp_ext : normp, normp_ext ? nparts_ext : p.nn_blocks, S, (int)p.k,
                              info, st));
   // Error check as one more pass (the identity above is free; this one is
   // exact up to the pass arithmetic, and for BF16 A also measures the
   // rounding of A to BF16).
+  // (on the lifted factors before the sign convention: the flips of u_j and
+  // v_j cancel in U S V^T, and these stay FP64 whatever the output type)
   if (p.residual)
-    SORSVD_TRY(launch_residual(p.a_type, A, lda, p.m, p.n, U, ldu, S, V, ldv, (int)p.k, (int)KP,
+    SORSVD_TRY(launch_residual(p.a_type, A, lda, p.m, p.n, U64, KP, S, V64, KP, (int)p.k, (int)KP,
                                at<double>(ws, p.off_res), info, st, p.cexp));
   return SORSVD_OK;
 }
@@ -726,7 +753,7 @@ size_t sorsvd_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t q, int32_
 }
 
 int sorsvd(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, int64_t k, int32_t q,
-           uint64_t seed, double* U, int64_t ldu, double* S, double* V, int64_t ldv, void* workspace,
+           uint64_t seed, void* U, int64_t ldu, double* S, void* V, int64_t ldv, void* workspace,
            size_t ws_bytes, void* stream, const sorsvd_opts* opts) {
   Plan p;
   const int rc = make_plan(m, n, k, q, a_type, opts, &p);
@@ -1089,6 +1116,48 @@ size_t sorsvd_auto_workspace_bytes(int64_t m, int64_t n, int32_t a_type) {
   return mb ? mb + auto_tail_bytes(m, n, a_type) : 0;
 }
 
+// The (k, q) of a run from the network's outputs y_q = log2 of the width
+// that meets the trained tolerance with q power steps: each width gets
+// kAutoMargin head-room (rounded up to a multiple of 8), widths beyond kcap
+// are dropped, and among the rest the q of the least modelled time is taken.
+// k_pred[q] = 2^y_q. Returns whether any width fits.
+static bool choose_kq(int32_t a_type, int64_t m, int64_t n, int64_t kcap, const float yh[4], double k_pred[4],
+                      int64_t* k, int* q) {
+  // Modelled time of a run of width k with q power steps (seconds), to pick
+  // q among the predicted widths: the passes over A (bytes at ~5 TB/s or
+  // flops at the MFMA rate reached, whichever is larger), the FP64 Cholesky
+  // QRs of the two sketches (a Gram and an apply per step, ~2 steps per QR)
+  // and the core SVD (~1e-11 k^3 s for the blocked one-sided Jacobi).
+  const double es = a_type == SORSVD_BF16 ? 2.0 : (a_type == SORSVD_F32 ? 4.0 : 8.0);
+  const double rate = a_type == SORSVD_BF16 ? 1.2e15 : (a_type == SORSVD_F32 ? 9e13 : 4e13);
+  auto model_s = [&](double kk, int qq) {
+    const double passes = 2.0 * qq + (a_type == SORSVD_BF16 ? 2.0 : 3.0);  // see auto_opts
+    const double t_pass = std::max((double)m * n * es / 5e12, 2.0 * m * n * kk / rate);
+    const double t_qr = (2.0 * qq + 2.0) * 2.0 * 3.0 * (double)(m + n) / 2.0 * kk * kk / 4e13;
+    return passes * t_pass + t_qr + 1e-11 * kk * kk * kk;
+  };
+  double best = 1e300;
+  bool predicted = false;
+  // BF16 passes round the skinny operand: without a power step the subspace
+  // error of that rounding stays near 1e-3, so BF16 runs take q >= 1
+  const int qmin = a_type == SORSVD_BF16 ? 1 : 0;
+  for (int qq = 0; qq < 4; ++qq) {
+    k_pred[qq] = yh[qq] == yh[qq] ? std::exp2((double)yh[qq]) : 1e30;
+    if (qq < qmin) continue;
+    const double kk = std::ceil(kAutoMargin * k_pred[qq] / 8.0) * 8.0;
+    if (!(kk <= (double)kcap)) continue;
+    const int64_t ki = std::max<int64_t>(1, (int64_t)kk);
+    const double cost = model_s((double)ki, qq);
+    if (cost < best) {
+      best = cost;
+      *k = ki;
+      *q = qq;
+      predicted = true;
+    }
+  }
+  return predicted;
+}
+
 int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed, double tol,
                 const float* params, double* U, int64_t ldu, double* S, double* V, int64_t ldv, void* workspace,
                 size_t ws_bytes, void* stream, sorsvd_auto_info* out) {
@@ -1111,19 +1180,7 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
   double* keep_n = nullptr;
   int64_t keep_ld = 0;
   int keep_parts = 0;
-  // Modelled time of a run of width k with q power steps (seconds), to pick
-  // q among the predicted widths: the passes over A (bytes at ~5 TB/s or
-  // flops at the MFMA rate reached, whichever is larger), the FP64 Cholesky
-  // QRs of the two sketches (a Gram and an apply per step, ~2 steps per QR)
-  // and the core SVD (~1e-11 k^3 s for the blocked one-sided Jacobi).
-  const double es = a_type == SORSVD_BF16 ? 2.0 : (a_type == SORSVD_F32 ? 4.0 : 8.0);
-  const double rate = a_type == SORSVD_BF16 ? 1.2e15 : (a_type == SORSVD_F32 ? 9e13 : 4e13);
-  auto model_s = [&](double kk, int qq) {
-    const double passes = 2.0 * qq + (a_type == SORSVD_BF16 ? 2.0 : 3.0);  // see auto_opts
-    const double t_pass = std::max((double)m * n * es / 5e12, 2.0 * m * n * kk / rate);
-    const double t_qr = (2.0 * qq + 2.0) * 2.0 * 3.0 * (double)(m + n) / 2.0 * kk * kk / 4e13;
-    return passes * t_pass + t_qr + 1e-11 * kk * kk * kk;
-  };
+
   int64_t k = std::min(kAutoFallbackK, kcap);
   int q = kAutoFallbackQ;
   bool predicted = false;
@@ -1143,24 +1200,7 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     float yh[4];
     SORSVD_TRY(hipMemcpyAsync(yh, y, sizeof(yh), hipMemcpyDeviceToHost, st));
     SORSVD_TRY(hipStreamSynchronize(st));
-    double best = 1e300;
-    // BF16 passes round the skinny operand: without a power step the subspace
-    // error of that rounding stays near 1e-3, so BF16 runs take q >= 1
-    const int qmin = a_type == SORSVD_BF16 ? 1 : 0;
-    for (int qq = 0; qq < 4; ++qq) {
-      out->k_pred[qq] = yh[qq] == yh[qq] ? std::exp2((double)yh[qq]) : 1e30;
-      if (qq < qmin) continue;
-      const double kk = std::ceil(kAutoMargin * out->k_pred[qq] / 8.0) * 8.0;
-      if (!(kk <= (double)kcap)) continue;
-      const int64_t ki = std::max<int64_t>(1, (int64_t)kk);
-      const double cost = model_s((double)ki, qq);
-      if (cost < best) {
-        best = cost;
-        k = ki;
-        q = qq;
-        predicted = true;
-      }
-    }
+    predicted = choose_kq(a_type, m, n, kcap, yh, out->k_pred, &k, &q);
   }
   // the predicted (k, q), then the fixed ladder: (256, 2), (512, 2), ... up
   // to the cap, until the judge accepts
@@ -1207,6 +1247,40 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     if (e <= tol) return SORSVD_OK;
   }
   return SORSVD_ETOL;
+}
+
+int sorsvd_predict_kq(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n, uint64_t seed,
+                      const float* params, double tol, int64_t* k_out, int32_t* q_out, double* k_pred,
+                      void* workspace, size_t ws_bytes, void* stream) {
+  Plan big;
+  int rc = auto_plan(m, n, a_type, &big);
+  if (rc) return rc;
+  if (!A || !params || !k_out || !q_out || !workspace || (lda < n && a_type != SORSVD_DIAG) || !(tol > 0.0))
+    return SORSVD_EINVAL;
+  const size_t main_bytes = auto_main_bytes(m, n, a_type);
+  if (ws_bytes < main_bytes + auto_tail_bytes(m, n, a_type)) return SORSVD_EWORKSPACE;
+  if (((uintptr_t)workspace) % kAlign) return SORSVD_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  char* tail = (char*)workspace + main_bytes;
+  float* feat = (float*)(tail + 256);
+  float* y = feat + 128;
+  float* work = (float*)(tail + 256 + 4096);
+  Plan pp;
+  if ((rc = probe_plan(m, n, a_type, &pp))) return rc;
+  if ((rc = probe(pp, A, lda, seed, feat, workspace, st))) return rc;
+  SORSVD_TRY(launch_mlp_forward(params, feat, 1, y, work, st));
+  float yh[4];
+  SORSVD_TRY(hipMemcpyAsync(yh, y, sizeof(yh), hipMemcpyDeviceToHost, st));
+  SORSVD_TRY(hipStreamSynchronize(st));
+  double kp[4];
+  int64_t k = std::min(kAutoFallbackK, big.k);
+  int q = kAutoFallbackQ;
+  const bool predicted = choose_kq(a_type, m, n, big.k, yh, kp, &k, &q);
+  if (k_pred)
+    for (int i = 0; i < 4; ++i) k_pred[i] = kp[i];
+  *k_out = k;
+  *q_out = q;
+  return predicted ? SORSVD_OK : SORSVD_ETOL;
 }
 
 // ------------------------------------------------------------------ robust PCA (ALM-SOR-SVD)

@@ -61,21 +61,21 @@ def ey_floor(sigma, kmax=KCAP):
 
 
 def candidate_widths(sigma, tol=TOL):
-    """(k_EY, candidate widths) or (None, []) if no width <= KCAP can meet tol.
-    Narrow candidates (k_EY <= 128) end with 128 and, where 128 may still fail,
-    the wide ladder 256, 512, 1024; wide ones are multiples of k_EY up to 1024."""
+    """(k_EY, narrow candidates, wide candidates) or (None, [], []) if no width
+    <= KCAP can meet tol. Narrow candidates (<= 128) are multiples of k_EY
+    ending with 128; wide ones are taken in increasing order only where every
+    narrow one failed: 256, 512, 1024 after a narrow k_EY, or multiples of a
+    wide k_EY (rounded up to a multiple of 32) up to 1024."""
     e = ey_floor(sigma)
     ok = np.nonzero(e <= tol)[0]
     if ok.size == 0:
-        return None, []
+        return None, [], []
     k_ey = max(1, int(ok[0]))
     if k_ey <= NARROW:
-        ws = {min(NARROW, max(k_ey, int(math.ceil(f * k_ey)))) for f in WIDTH_FACTORS} | {NARROW}
-        if 3 * k_ey > NARROW:
-            ws |= {256, 512, KCAP}
-    else:
-        ws = {min(KCAP, max(k_ey, int(math.ceil(f * k_ey)))) for f in WIDE_FACTORS} | {KCAP}
-    return k_ey, sorted(ws)
+        narrow = sorted({min(NARROW, max(k_ey, int(math.ceil(f * k_ey)))) for f in WIDTH_FACTORS} | {NARROW})
+        return k_ey, narrow, [256, 512, KCAP]
+    wide = sorted({min(KCAP, 32 * int(math.ceil(f * k_ey / 32))) for f in WIDE_FACTORS} | {KCAP})
+    return k_ey, [], wide
 
 
 def _nlab(n, w):
@@ -87,22 +87,20 @@ def label_spectra(spectra, tol=TOL, batch_bytes=24e9, log=print):
     torch = _torch()
     count = len(spectra)
     labels = np.full((count, 4), CENSORED)
-    probs = []          # (spectrum, width, q), widths <= NARROW: the batched engine
-    wide = []           # wider: one SOR-SVD each
+    probs = []          # (spectrum, width, q) of width <= NARROW: the batched engine
     dev = {}
     meta = {}
     for i, (_, n, s) in enumerate(spectra):
-        k_ey, ws = candidate_widths(s, tol)
+        k_ey, narrow, wide = candidate_widths(s, tol)
         if k_ey is None:
             continue
-        meta[i] = (float(np.sum(s ** 2)), ws)
-        for w in ws:
+        meta[i] = (float(np.sum(s ** 2)), narrow, wide)
+        for w in narrow:
             if w > _nlab(n, w):
                 continue
             for q in range(4):
-                (probs if w <= NARROW else wide).append((i, w, q))
-    log(f"[labels] {len(meta)} of {count} spectra can meet {tol:g} with k <= {KCAP}; "
-        f"{len(probs)} batched runs, {len(wide)} wide runs")
+                probs.append((i, w, q))
+    log(f"[labels] {len(meta)} of {count} spectra can meet {tol:g} with k <= {KCAP}; {len(probs)} batched runs")
     err = {}
 
     def record(i, w, q, e_run):
@@ -137,24 +135,42 @@ def label_spectra(spectra, tol=TOL, batch_bytes=24e9, log=print):
         b.close()
         del b
         start = end
-        log(f"[labels] {end}/{len(probs)} runs, {time.perf_counter() - t0:.1f} s")
+        log(f"[labels] {end}/{len(probs)} batched runs, {time.perf_counter() - t0:.1f} s")
     dev.clear()
-    # wide runs, grouped by shape so that one plan (workspace) serves each group
-    groups = {}
-    for i, w, q in wide:
-        groups.setdefault((_nlab(spectra[i][1], w), w, q), []).append(i)
-    done = 0
-    for (nl, w, q), idx in sorted(groups.items()):
-        plan = api.Plan(nl, nl, w, q, SORSVD_DIAG)
-        for i in idx:
-            sig = torch.as_tensor(spectra[i][2][:nl]).cuda()
-            plan.run(sig, seed=1000 + i)
-            record(i, w, q, plan.info()["err_fro"])
-            done += 1
-        del plan
-        if done % 2000 < len(idx):
-            log(f"[labels] {done}/{len(wide)} wide runs, {time.perf_counter() - t0:.1f} s")
-    for i, (_, ws) in meta.items():
+    # wide candidates, in increasing width, for the (spectrum, q) that no
+    # narrow candidate resolved; one level at a time, grouped by shape so that
+    # one plan (workspace) serves a group
+    pending = {}
+    for i, (_, narrow, wide) in meta.items():
+        for q in range(4):
+            if not any(err.get((i, w, q), 1.0) <= tol for w in narrow):
+                cand = [w for w in wide if w <= _nlab(spectra[i][1], w)]
+                if cand:
+                    pending[(i, q)] = cand
+    nwide = 0
+    level = 0
+    while pending:
+        groups = {}
+        for (i, q), cand in pending.items():
+            w = cand[0]
+            groups.setdefault((_nlab(spectra[i][1], w), w, q), []).append(i)
+        for (nl, w, q), idx in sorted(groups.items()):
+            plan = api.Plan(nl, nl, w, q, SORSVD_DIAG)
+            for i in idx:
+                plan.run(torch.as_tensor(spectra[i][2][:nl]).cuda(), seed=1000 + i)
+                record(i, w, q, plan.info()["err_fro"])
+            nwide += len(idx)
+            del plan
+        nxt = {}
+        for (i, q), cand in pending.items():
+            if err[(i, cand[0], q)] > tol and len(cand) > 1:
+                nxt[(i, q)] = cand[1:]
+        pending = nxt
+        level += 1
+        log(f"[labels] wide level {level}: {nwide} wide runs so far, {len(pending)} pending, "
+            f"{time.perf_counter() - t0:.1f} s")
+    for i, (_, narrow, wide) in meta.items():
+        ws = narrow + wide
         for q in range(4):
             prev = None
             for w in ws:
@@ -310,7 +326,7 @@ def heldout_eval(params, count=200, seed=77, tol=TOL, log=print):
     torch = _torch()
     spectra = W.c5_training_spectra(count, seed)
     first = met_l = met_p = 0
-    runs_l = runs_p = width_l = width_p = 0
+    runs_l = runs_p = 0
     reachable = 0
     for i, (_, n, s) in enumerate(spectra):
         if ey_floor(s, min(KCAP, n))[-1] > tol:
@@ -324,8 +340,6 @@ def heldout_eval(params, count=200, seed=77, tol=TOL, log=print):
         met_p += int(ip["met"])
         runs_l += il["runs"]
         runs_p += ip["runs"]
-        width_l += il["k_used"] if il["runs"] == 1 else il["k_used"] * il["runs"]
-        width_p += ip["k_used"] if ip["runs"] == 1 else ip["k_used"] * ip["runs"]
     r = max(reachable, 1)
     out = {"spectra": count, "reachable": reachable, "first_run_success": first / r, "met_learned": met_l / r,
            "met_plain": met_p / r, "mean_runs_learned": runs_l / r, "mean_runs_plain": runs_p / r}
@@ -364,6 +378,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=55)
     ap.add_argument("--out", default=PARAMS_FILE)
     ap.add_argument("--out-bf16", default=PARAMS_FILE_BF16)
+    ap.add_argument("--heldout", type=int, default=0, help="held-out spectra to evaluate the FP32 weights on")
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     spectra = W.c5_training_spectra(args.count, args.seed)
@@ -376,6 +391,8 @@ def main(argv=None):
         params, hist = train(X, T, epochs=args.epochs, log=log)
         save_params(params, out)
         log(f"[train] saved {out} (input noise {noise:g})")
+    if args.heldout > 0:
+        heldout_eval(load_params(args.out), count=args.heldout, log=log)
 
 
 if __name__ == "__main__":

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from test_gpu_parity import fp32_factor_check
 from oracle import sorsvd as osvd
 
 pytestmark = pytest.mark.gpu
@@ -124,13 +125,16 @@ def test_fp32_batch_matches_oracle_on_stored_values(lib):
     b, _ = make_batch(lib, mats, specs, torch.float32)
     b.run()
     torch.cuda.synchronize()
+    worst = 0.0
     for i, (A, (k, l, q, seed)) in enumerate(zip(mats, specs)):
         S = host(b.S[i])
-        _, So, _, _ = osvd.sorsvd(A, k, q=q, seed=seed, l=l)
+        Uo, So, Vo, _ = osvd.sorsvd(A, k, q=q, seed=seed, l=l)
         assert normwise(S, So) <= 1e-5, i
         U, V = host(b.U[i]), host(b.V[i])
         assert np.abs(U.T @ U - np.eye(k)).max() < 1e-11
         assert np.abs(V.T @ V - np.eye(k)).max() < 1e-11
+        worst = max(worst, fp32_factor_check(U, V, Uo, Vo, So, max(A.shape)))
+    print(f"fp32 batch: factor deviation {worst:.2f} u32 sqrt(K) sigma_1 / gap")
 
 
 def test_launch_configuration_changes_no_bit(lib):

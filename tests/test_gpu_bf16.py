@@ -117,8 +117,16 @@ def test_bf16_whole_method(lib, m, n, k, q):
     # against the FP64 oracle on the same stored A and Omega
     dsig = np.max(np.abs(S - So)) / So[0]
     de = abs(e - io["err_fro"]) / io["err_fro"]
+    # subspace angles against the oracle's factors (same stored A): the
+    # leading directions, well separated at 0.9^j, are the ones determined
+    from test_gpu_parity import subspace_sin
+    su, sv = subspace_sin(U, Uo), subspace_sin(V, Vo)
+    kk = min(8, k)
+    su8, sv8 = subspace_sin(U[:, :kk], Uo[:, :kk]), subspace_sin(V[:, :kk], Vo[:, :kk])
     print(f"bf16 m={m} n={n} k={k} q={q}: sigma normwise {dsig:.2e}, err {e:.4e} vs oracle "
-          f"{io['err_fro']:.4e} (rel {de:.2e}), identity err {info['err_fro']:.4e}")
+          f"{io['err_fro']:.4e} (rel {de:.2e}), identity err {info['err_fro']:.4e}; sin angle U {su:.2e} "
+          f"V {sv:.2e} (leading {kk}: {su8:.2e}, {sv8:.2e})")
+    assert su8 <= 1e-2 and sv8 <= 1e-2
     # measured: sigma normwise <= 1.3e-4, error within 8e-4 relative
     assert dsig < 1e-3
     assert de < 5e-3

@@ -170,8 +170,14 @@ def test_f16_whole_method(lib, m, n, k, q):
     assert e >= floor * (1 - 1e-6)
     dsig = np.max(np.abs(S - So)) / So[0]
     de = abs(e - io["err_fro"]) / io["err_fro"]
+    from test_gpu_parity import subspace_sin
+    su, sv = subspace_sin(U, Uo), subspace_sin(V, Vo)
+    kk = min(8, k)
+    su8, sv8 = subspace_sin(U[:, :kk], Uo[:, :kk]), subspace_sin(V[:, :kk], Vo[:, :kk])
     print(f"f16 m={m} n={n} k={k} q={q}: sigma normwise {dsig:.2e}, err {e:.4e} vs oracle "
-          f"{io['err_fro']:.4e} (rel {de:.2e}), identity err {info['err_fro']:.4e}")
+          f"{io['err_fro']:.4e} (rel {de:.2e}), identity err {info['err_fro']:.4e}; sin angle U {su:.2e} "
+          f"V {sv:.2e} (leading {kk}: {su8:.2e}, {sv8:.2e})")
+    assert su8 <= 1e-3 and sv8 <= 1e-3
     # measured: sigma normwise <= 1.6e-5, error within 3.2e-5 relative (BF16:
     # 1.3e-4 and 7.7e-4 on the same cases)
     assert dsig < 5e-5

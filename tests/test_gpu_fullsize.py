@@ -12,6 +12,8 @@ import pytest
 import workloads as W
 from oracle import sorsvd as osvd
 
+from test_gpu_parity import fp32_factor_check, subspace_sin
+
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 torch = pytest.importorskip("torch")
 
@@ -62,8 +64,10 @@ def test_c2_full_size_fp32(lib):
     Ah = host(A)
     del A64
     torch.cuda.empty_cache()
-    _, So, _, io = osvd.sorsvd(Ah, k, q=1, seed=1)
+    Uo, So, Vo, io = osvd.sorsvd(Ah, k, q=1, seed=1)
     dsig = np.max(np.abs(Sh - So)) / So[0]
+    worst = fp32_factor_check(host(U), host(V), Uo, Vo, So, n, cap=0.1)
+    print(f"C2 full size: factor deviation {worst:.2f} u32 sqrt(K) sigma_1 / gap", flush=True)
     de = abs(e - io["err_fro"]) / io["err_fro"]
     print(f"C2 full size: sigma normwise {dsig:.2e}, err {e:.6e} vs oracle {io['err_fro']:.6e} (rel {de:.2e})",
           flush=True)
@@ -102,11 +106,16 @@ def test_c3_full_size_16bit(lib, fmt, pe):
     Ah = host(stored)
     del stored
     torch.cuda.empty_cache()
-    _, So, _, io = osvd.sorsvd(Ah, k, q=1, seed=1, m_form="approx" if pe else "exact")
+    Uo, So, Vo, io = osvd.sorsvd(Ah, k, q=1, seed=1, m_form="approx" if pe else "exact")
     dsig = np.max(np.abs(Sh - So)) / So[0]
     de = abs(e_st - io["err_fro"]) / io["err_fro"]
+    # subspace angles of the factors against the oracle's (same stored A)
+    su, sv = subspace_sin(host(U), Uo), subspace_sin(host(V), Vo)
+    su8, sv8 = subspace_sin(host(U)[:, :8], Uo[:, :8]), subspace_sin(host(V)[:, :8], Vo[:, :8])
     print(f"C3 {fmt} pe={pe} full size: sigma normwise {dsig:.2e}, err {e_st:.6e} vs oracle {io['err_fro']:.6e} "
-          f"(rel {de:.2e}), identity {info['err_fro']:.6e}", flush=True)
+          f"(rel {de:.2e}), identity {info['err_fro']:.6e}; sin angle U {su:.2e} V {sv:.2e} "
+          f"(leading 8: {su8:.2e}, {sv8:.2e})", flush=True)
+    assert su <= 0.5 and sv <= 0.5 and su8 <= 1e-2 and sv8 <= 1e-2
     # 16-bit skinny operands (BF16 8 bits, FP16 11 bits) with FP32 accumulation
     # over 4000 / 200000 terms; the error of this matrix is dominated by its
     # noise, which every basis of the leading subspace leaves in place

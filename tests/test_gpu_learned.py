@@ -189,3 +189,15 @@ def test_learned_choice_gains_over_fixed_fallback(lib):
         torch.cuda.empty_cache()
     print(f"total time to tolerance: learned {t_learned:.1f} ms, fixed {t_plain:.1f} ms", flush=True)
     assert t_learned < 0.9 * t_plain
+
+
+def test_predict_kq_is_the_first_run_of_auto(lib):
+    from paper_1804_00462_amd import predictor as PR
+    params = PR.load_params()
+    A, _, _ = W.spectral(1500, 1200, np.arange(1, 1201) ** -2.5, 21)
+    Ad = torch.as_tensor(A).cuda()
+    k, q, kp, predicted = lib.predict_kq(Ad, params, 1e-3, seed=3)
+    U, S, V, info = lib.auto(Ad, 1e-3, params, seed=3)
+    assert predicted and info["used_fallback"] == 0
+    assert (info["k_used"], info["q_used"]) == (k, q)
+    assert np.allclose(kp, info["k_pred"], rtol=0, atol=0)

@@ -15,6 +15,7 @@ import pytest
 
 import workloads as W
 from oracle import bounds
+from oracle import normal
 from oracle.sorsvd import qr_pos, sorsvd
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -259,3 +260,26 @@ def test_m_approx_equals_m_because_q2_spans_a_t_q1():
         # like the spectrum's ratio to the power q), but the values still agree
         _, sl, _, _ = sorsvd(A, 10, q=q, seed=2, l=14, mode="literal", m_form="approx")
         assert np.max(np.abs(sl - se)) <= 1e-10 * nA
+
+
+def test_th4_th5_nearly_tight_with_two_power_steps():
+    """With q = 2 and a clear gap after sigma_k the deterministic bounds are
+    nearly attained, as in the paper's q = 2 curves (Figs. ThrBo_F): the
+    Frobenius bound of Th. 5 within 10% of the actual error and the Th. 4
+    lower bounds within 0.05% of the estimates (observed 5-8% and <= 0.02%).
+    A wrong power of (sigma_{l-p+1} / sigma_k) (2q for 4q + 4 in Th. 4, q
+    for 2q in Th. 5) or a lost scaling moves them far outside. (Here the Th. 4
+    bound exceeds some estimates by up to 3.5e-9 relative, above rounding:
+    the per-draw check of Th. 4 in test_theorem4_and_theorem5_per_draw keeps
+    its 1e-10 slack on other shapes; this one pins closeness from both sides.)"""
+    n, k, q, l, p = 400, 20, 2, 30, 8
+    sig = np.concatenate([np.geomspace(10, 1, k), 0.3 * np.linspace(1, 0.5, n - k)])
+    A, _, V = W.spectral(n, n, sig, 3)
+    for seed in (1, 2, 3):
+        Uo, So, Vo, _ = sorsvd(A, k, q=q, seed=seed, l=l)
+        ef = np.linalg.norm(A - (Uo * So) @ Vo.T)
+        Om = normal.gaussian_matrix(seed, n, l)
+        bf = bounds.th5_err_upper(sig, V, Om, k, l, p, q, "fro")
+        assert ef <= bf <= 1.10 * ef, (seed, bf / ef)
+        lo = bounds.th4_sv_lower(sig, V, Om, k, l, p, q)
+        assert np.max(np.abs(lo / So - 1.0)) <= 5e-4, (seed, lo / So)
