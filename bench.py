@@ -46,8 +46,14 @@ WORKLOADS = {
     "c3pe": (200000, 4000, 64, 1, "bfloat16", 1,
              "C3 with the pass-efficient core matrix (eq. M_approx as T2^T Q2; the last orbit product "
              "takes Q1 split into BF16 hi + lo parts: 2q + 2 = 4 passes over A)"),
+    # wide sketches on C5's matrix (32768 x 32768, sigma_j = j^-1.5, Haar U, V, seed 5); for
+    # kernel profiles of the widths the C5 comparison runs, not in the default extras
+    "c5b": (32768, 32768, 704, 1, "bfloat16", 1,
+            "C5's matrix stored in BF16, k = l = 704, q = 1, refinement, pass-efficient core matrix"),
+    "c5f": (32768, 32768, 1024, 2, "float32", 0,
+            "C5's matrix stored in FP32, k = l = 1024, q = 2 (the top rung of the fixed ladder)"),
 }
-PASS_EFFICIENT = {"c2pe", "c3pe"}
+PASS_EFFICIENT = {"c2pe", "c3pe", "c5b"}
 
 C4_DESC = ("batched SOR-SVD FP32: 512 RPCA-style problems L + S (L = X Y^T, N(0,1) factors of rank r, "
            "S = 5% outliers U[-10, 10]), m ~ U[256, 4096], n ~ U[128, 2048], r ~ U[4, 64] (seed 3), "
@@ -57,6 +63,7 @@ C4_DESC = ("batched SOR-SVD FP32: 512 RPCA-style problems L + S (L = X Y^T, N(0,
 PEAK = {"float32": ("mfma", 157.3, "TFLOP/s"), "float64": ("mfma", 78.6, "TFLOP/s"),
         "bfloat16": ("hbm", 8000.0, "GB/s"), "float16": ("hbm", 8000.0, "GB/s")}
 DTYPE_TAG = {"float32": "f32", "float64": "f64", "bfloat16": "bf16", "float16": "f16"}
+MFMA_PEAK = {"float32": 157.3, "float64": 78.6, "bfloat16": 2500.0, "float16": 2500.0}  # dense, TFLOP/s
 REDUCED = {"c3", "c3h", "c3pe"}  # 16-bit storage: also the error against the FP64 matrix
 
 
@@ -109,6 +116,11 @@ def make_input(name, torch, P, quick=False):
         return Ah, {"col_exp": e}, A64
     if name == "c1":
         return torch.as_tensor(W.c1()).cuda(), {}, None
+    if name in ("c5b", "c5f"):
+        import numpy as np
+        from paper_1804_00462_amd import predictor as PR
+        A64 = PR.eval_matrix(n, np.arange(1, n + 1, dtype=np.float64) ** -1.5, 5)
+        return A64.to(getattr(torch, dname)), {}, A64
     raise ValueError(name)
 
 
@@ -136,14 +148,14 @@ def cpu_baseline(A_host, k, q, seed, budget_s=20.0, max_reps=5):
     t_start = time.perf_counter()
     while len(times) < max_reps:
         t0 = time.perf_counter()
-        osvd.sorsvd(A, k, q=q, seed=seed)
+        osvd.sorsvd(A, k, q=q, seed=seed, explicit=False)  # the error by the identity, as the GPU step
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start > budget_s:
             break
     med = sorted(times)[len(times) // 2]
     return {"value": 1.0 / med, "unit": "SOR-SVD/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{len(times)} full SOR-SVD(s) of the same stored matrix in FP64 numpy/LAPACK "
-                      f"(median {med:.3f} s; includes the oracle's explicit residual)"}
+                      f"(median {med:.3f} s; error by the identity, as the GPU step: no explicit residual)"}
 
 
 def run_workload(name, steps, warmup, torch, P, quick=False):
@@ -178,8 +190,35 @@ def run_workload(name, steps, warmup, torch, P, quick=False):
     ms_per_step = gpu_ms / steps
     log(f"[bench] {name}: {steps} timed steps, {ms_per_step:.3f} ms/step; pass kernel "
         f"{kern_ms / launches * 1e3:.1f} us/launch")
+    # the same step as HIP graph replays (one graph launch per SOR-SVD)
+    graph_ms = None
+    try:
+        S_eager = plan.S.clone()
+        g = plan.capture(A, seed)
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()
+        for _ in range(steps):
+            g.replay()
+        g1.record()
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / steps
+        if not torch.equal(S_eager, plan.S):
+            raise RuntimeError("graph replay differs from the eager run")
+        log(f"[bench] {name}: graph replay {graph_ms:.3f} ms/step")
+        del g
+    except Exception as ex:  # reported, not fatal
+        log(f"[bench] {name}: graph replay not measured ({ex})")
 
-    bound, peak, unit = PEAK[dname]
+    # bound of the pass kernel by its intensity 2 l / b_A (flop per byte of A)
+    # against the ridge of the MFMA peak of its type over 8 TB/s
+    intensity = 2.0 * k / es
+    if intensity >= MFMA_PEAK[dname] * 1e12 / 8e12:
+        bound, peak, unit = "mfma", MFMA_PEAK[dname], "TFLOP/s"
+    else:
+        bound, peak, unit = "hbm", 8000.0, "GB/s"
     avg_launch_s = kern_ms / launches / 1e3
     per_launch_flops = kflops / launches
     per_launch_bytes = kbytes / launches
@@ -200,7 +239,8 @@ def run_workload(name, steps, warmup, torch, P, quick=False):
            "value": round(1000.0 / ms_per_step, 3), "unit": "SOR-SVD/s",
            "hbm_gbps_algorithmic": round(float(m) * n * es * passes / (ms_per_step / 1e3) / 1e9, 1),
            "roofline": roofline, "err_fro": info["err_fro"], "jacobi_sweeps": info["sweeps"],
-           "flags": info["flags"]}
+           "flags": info["flags"],
+           "ms_per_step_graph": round(graph_ms, 4) if graph_ms is not None else None}
     if A64 is not None:
         res["err_vs_fp64"] = error_vs_fp64(A64, plan.U, plan.S, plan.V, torch)
         log(f"[bench] {name}: relative error against the FP64 matrix {res['err_vs_fp64']:.4e}")
@@ -299,36 +339,42 @@ def run_rpca(torch, P, sizes=(1000, 2000, 3000), reps=3):
 
 
 def run_c5(torch, P):
-    """Time to tolerance 1e-3 (relative Frobenius, against the FP64 matrix) on
-    32768 x 32768 A = U diag(sigma) V^T (Haar U, V on the leading 2048 singular
-    values): BF16 storage + learned (k, q) + judge against FP32 storage + the
-    fixed choice (k = 128, q = 2) + judge. sigma_j = j^-2.5 is within reach of
-    widths <= 128; sigma_j = j^-1.5 needs k ~ 645 by the Eckart-Young floor,
-    beyond this build's widths, so both forms report the tolerance as not met."""
+    """The metric's comparison on its configuration: time to tolerance 1e-3
+    (relative Frobenius error against the FP64 matrix) on m = n = 32768,
+    A = U diag(j^-1.5) V^T with Haar U, V over the whole spectrum (seed 5):
+    BF16 storage + learned (k, q) + judge (sorsvd_auto with the network)
+    against FP32 storage + the fixed ladder (256, 2), (512, 2), (1024, 2) +
+    judge (sorsvd_auto without it); the other two combinations for context.
+    The Eckart-Young floor needs k >= 645 here, so the fixed (256, 2) alone
+    cannot meet the tolerance. Also the success rate of the learned first run
+    on 200 held-out spectra (diagonal stand-ins, FP64)."""
+    import numpy as np
     from paper_1804_00462_amd import predictor as PR
     params = PR.load_params()
-    out = {}
     n = 32768
-    j = None
-    import numpy as np
     j = np.arange(1, n + 1, dtype=np.float64)
-    for name, sigma in (("j^-2.5", j ** -2.5), ("j^-1.5", j ** -1.5)):
-        log(f"[bench] c5-shaped {n} x {n}, sigma_j = {name}")
-        A64 = PR.eval_matrix(n, sigma, 7)
+    out = {}
+    for name, sigma in (("j^-1.5", j ** -1.5),):
+        log(f"[bench] c5 {n} x {n}, sigma_j = {name}, full spectrum")
+        t0 = time.perf_counter()
+        A64 = PR.eval_matrix(n, sigma, 5)
+        torch.cuda.synchronize()
+        log(f"[bench] c5 input ready in {time.perf_counter() - t0:.1f} s")
         res = PR.compare(A64, 1e-3, params, log=log, label=f"c5 {name}")
         del A64
         torch.cuda.empty_cache()
         bl, fp = res["bf16_learned"], res["fp32_plain"]
+        keys = ("k_used", "q_used", "used_fallback", "runs", "err", "true_err", "met", "met_true", "k_pred")
         out[name] = {"bf16_learned_ms": round(bl["ms"], 3), "fp32_plain_ms": round(fp["ms"], 3),
                      "speedup": round(fp["ms"] / bl["ms"], 3),
-                     "bf16_learned": {k: bl[k] for k in ("k_used", "q_used", "used_fallback", "runs", "err",
-                                                         "true_err", "met", "met_true")},
-                     "fp32_plain": {k: fp[k] for k in ("k_used", "q_used", "used_fallback", "runs", "err",
-                                                       "true_err", "met", "met_true")},
-                     "fp32_learned_ms": round(res["fp32_learned"]["ms"], 3),
-                     "bf16_plain_ms": round(res["bf16_plain"]["ms"], 3)}
-    return {"workload": "time to relative Frobenius error <= 1e-3 on 32768 x 32768, BF16 + learned (k, q) vs "
-                        "FP32 + fixed (128, 2), both judged", "cases": out}
+                     "bf16_learned": {k: bl[k] for k in keys}, "fp32_plain": {k: fp[k] for k in keys},
+                     "fp32_learned": {k: res["fp32_learned"][k] for k in keys + ("ms",)},
+                     "bf16_plain": {k: res["bf16_plain"][k] for k in keys + ("ms",)}}
+    held = PR.heldout_eval(params, 200, log=log)
+    return {"workload": "time to relative Frobenius error <= 1e-3 against the FP64 matrix on 32768 x 32768, "
+                        "sigma_j = j^-1.5 (whole spectrum, Haar U, V, seed 5): BF16 + learned (k, q) vs FP32 + "
+                        "fixed ladder (256, 2) -> (512, 2) -> (1024, 2), both judged",
+            "cases": out, "heldout": held}
 
 
 def main():

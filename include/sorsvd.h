@@ -11,7 +11,13 @@
  *   - Every matrix pointer is a DEVICE pointer (HIP global memory) unless the
  *     comment says "host". The library never allocates device memory: the
  *     caller passes a workspace of at least the size the matching
- *     *_workspace_bytes() call returns. The library keeps no state between calls.
+ *     *_workspace_bytes() call returns. Results depend only on the arguments.
+ *     Process-wide state, all opt-in: the pass-timing events of
+ *     sorsvd_pass_timing (created and freed by that call, per process), batch
+ *     plans and graphs (sorsvd_batch_create / _graph, freed by the matching
+ *     destroy calls), and the 64 MiB device array that sorsvd_noalloc uses as
+ *     its workspace (per device, until the process ends). The batch autotuner's
+ *     cache file is read and written only when SORSVD_TUNE_CACHE names one.
  *   - `stream` is a hipStream_t (NULL = the default stream). All work is
  *     enqueued on it asynchronously; results are valid once the stream has
  *     completed. Argument errors are detected synchronously, before anything is
@@ -395,6 +401,9 @@ typedef struct sorsvd_auto_info {
   double k_pred[4];        /* network widths 2^y_q before head-room (0 without params) */
   int32_t flags;           /* sorsvd_info.flags of the returned result */
   int32_t reserved;
+  double err_stored;       /* explicit error against the stored A before the
+                              16-bit rounding-noise correction (the judge's
+                              input for BF16 A; equal to err otherwise) */
 } sorsvd_auto_info;
 
 size_t sorsvd_probe_workspace_bytes(int64_t m, int64_t n, int32_t a_type);

@@ -65,11 +65,14 @@ def omega(seed, n, l):
     return gaussian_matrix(seed, n, l, stream=0)
 
 
-def sorsvd(A, k, q=0, seed=0, l=None, mode="canonical", Omega=None, return_all=False, m_form="exact"):
+def sorsvd(A, k, q=0, seed=0, l=None, mode="canonical", Omega=None, return_all=False, m_form="exact",
+           explicit=True):
     """SOR-SVD of A (m x n) to rank k with sketch width l (default l = k) and q power steps.
 
     Returns (U, s, V, info): U m x k, s length k (descending), V n x k, and
-    info = {"err_fro": ||A - U diag(s) V^T||_F / ||A||_F (explicit),
+    info = {"err_fro": ||A - U diag(s) V^T||_F / ||A||_F (explicit; with
+            explicit=False the identity below instead, which skips forming
+            the m x n residual),
             "err_fro_identity": same via ||A||_F^2 - sum s^2 (Th. 2 split),
             "a_fro": ||A||_F}.
     """
@@ -120,9 +123,12 @@ def sorsvd(A, k, q=0, seed=0, l=None, mode="canonical", Omega=None, return_all=F
     a_fro = float(np.linalg.norm(A))
     info = {"a_fro": a_fro}
     if a_fro > 0:
-        R = A - (U * sk[None, :]) @ V.T
-        info["err_fro"] = float(np.linalg.norm(R)) / a_fro
         info["err_fro_identity"] = float(np.sqrt(max(a_fro ** 2 - float(np.sum(sk ** 2)), 0.0))) / a_fro
+        if explicit:
+            R = A - (U * sk[None, :]) @ V.T
+            info["err_fro"] = float(np.linalg.norm(R)) / a_fro
+        else:
+            info["err_fro"] = info["err_fro_identity"]
     else:
         info["err_fro"] = 0.0
         info["err_fro_identity"] = 0.0

@@ -41,7 +41,8 @@ class Problem(ctypes.Structure):
 
 class AutoInfo(ctypes.Structure):
     _fields_ = [("k_used", c_i32), ("q_used", c_i32), ("used_fallback", c_i32), ("runs", c_i32),
-                ("err", c_dbl), ("k_pred", c_dbl * 4), ("flags", c_i32), ("reserved", c_i32)]
+                ("err", c_dbl), ("k_pred", c_dbl * 4), ("flags", c_i32), ("reserved", c_i32),
+                ("err_stored", c_dbl)]
 
 
 class RpcaInfo(ctypes.Structure):

@@ -113,6 +113,22 @@ class Plan:
         check(_lib.load().sorsvd_read_info(_ptr(self.ws), ctypes.byref(out), _stream(stream)), "sorsvd_read_info")
         return _info_dict(out)
 
+    def capture(self, A, seed=0):
+        """The whole launch sequence of run(A, seed) captured in a HIP graph
+        (torch.cuda.CUDAGraph; the sequence holds no host synchronisation, no
+        allocation and no memset node). Replaying it recomputes U, S, V of the
+        current contents of A into this plan's outputs."""
+        torch = _torch()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.run(A, seed)  # outside the capture: first-call set-up (occupancy queries)
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(A, seed)
+        return g
+
 
 def sorsvd(A, k, q=0, seed=0, **opts):
     """Rank-k SOR-SVD of the device matrix A. Returns (U, S, V, info) as FP64 tensors."""
@@ -457,7 +473,8 @@ def auto(A, tol, params=None, seed=0):
         check(st, "sorsvd_auto")
     k = out.k_used
     info = {"k_used": k, "q_used": out.q_used, "used_fallback": out.used_fallback, "runs": out.runs,
-            "err": out.err, "k_pred": list(out.k_pred), "flags": out.flags, "met": st == 0}
+            "err": out.err, "err_stored": out.err_stored, "k_pred": list(out.k_pred), "flags": out.flags,
+            "met": st == 0}
     return U[:, :k], S[:k], V[:, :k], info
 
 

@@ -13,10 +13,10 @@
 // exponents e (A = A_stored diag(2^-e_j)): the residual is then formed in the
 // stored scale (column j of W = S V^T multiplied by 2^e_j before the MFMA, so
 // FP32 sees values of the stored range) and its square, like the rounding
-// noise, weighted by 4^-e_j (exact). Against the matrix before rounding, the
-// approximation error is then estimated as sqrt(e_stored^2 - that sum / ||A||^2):
-// the rounding error is spread over all n singular directions, so only a
-// fraction (k / n)^2 of it is captured by the rank-k approximation.
+// noise, weighted by 4^-e_j (exact). This pass only reports the two sums
+// (err_fro_explicit and a_noise_rel); how much of the noise the rank-k
+// subspaces capture, and so the error against the matrix before rounding, is
+// the caller's estimate (the judge of sorsvd_auto).
 //
 // For k > 128 (W no longer fits LDS) the pass is a tiled product instead: U
 // (m x KP) and W^T = S V^T (KP x n, columns padded to a multiple of 128) are

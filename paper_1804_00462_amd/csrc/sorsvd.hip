@@ -1076,7 +1076,7 @@ static int auto_plan(int64_t m, int64_t n, int32_t a_type, Plan* p) {
   const int64_t kcap = std::min<int64_t>(kMaxLP, std::min(m, n));
   sorsvd_opts o;
   auto_opts(a_type, &o);
-  o.residual = 1;
+  o.residual = a_type == SORSVD_DIAG ? 0 : 1;  // (diagonal stand-ins take no residual pass)
   return make_plan(m, n, kcap, 3, a_type, &o, p);
 }
 
@@ -1101,7 +1101,7 @@ static size_t auto_main_bytes(int64_t m, int64_t n, int32_t a_type) {
   const int64_t kcap = p.k;
   sorsvd_opts o;
   auto_opts(a_type, &o);
-  o.residual = 1;
+  o.residual = a_type == SORSVD_DIAG ? 0 : 1;
   for (int64_t k = 8; k < kcap; k += 8) {
     Plan pk;
     if (make_plan(m, n, k, 3, a_type, &o, &pk) == SORSVD_OK) mx = std::max(mx, pk.total);
@@ -1118,9 +1118,11 @@ size_t sorsvd_auto_workspace_bytes(int64_t m, int64_t n, int32_t a_type) {
 
 // The (k, q) of a run from the network's outputs y_q = log2 of the width
 // that meets the trained tolerance with q power steps: each width gets
-// kAutoMargin head-room (rounded up to a multiple of 8), widths beyond kcap
-// are dropped, and among the rest the q of the least modelled time is taken.
-// k_pred[q] = 2^y_q. Returns whether any width fits.
+// kAutoMargin head-room (rounded up to a multiple of 8) and is capped at
+// kcap; a width predicted beyond 1.5 kcap is dropped (the network's label
+// for "more than the widest sketch" is 2 kcap), and among the rest the q of
+// the least modelled time is taken. k_pred[q] = 2^y_q. Returns whether any
+// width is left.
 static bool choose_kq(int32_t a_type, int64_t m, int64_t n, int64_t kcap, const float yh[4], double k_pred[4],
                       int64_t* k, int* q) {
   // Modelled time of a run of width k with q power steps (seconds), to pick
@@ -1144,8 +1146,8 @@ static bool choose_kq(int32_t a_type, int64_t m, int64_t n, int64_t kcap, const 
   for (int qq = 0; qq < 4; ++qq) {
     k_pred[qq] = yh[qq] == yh[qq] ? std::exp2((double)yh[qq]) : 1e30;
     if (qq < qmin) continue;
-    const double kk = std::ceil(kAutoMargin * k_pred[qq] / 8.0) * 8.0;
-    if (!(kk <= (double)kcap)) continue;
+    if (!(k_pred[qq] <= (double)kcap)) continue;  // the network says even kcap is short
+    const double kk = std::min((double)kcap, std::ceil(kAutoMargin * k_pred[qq] / 8.0) * 8.0);
     const int64_t ki = std::max<int64_t>(1, (int64_t)kk);
     const double cost = model_s((double)ki, qq);
     if (cost < best) {
@@ -1226,6 +1228,7 @@ int sorsvd_auto(const void* A, int64_t lda, int32_t a_type, int64_t m, int64_t n
     SORSVD_TRY(hipMemcpyAsync(&info, workspace, sizeof(info), hipMemcpyDeviceToHost, st));
     SORSVD_TRY(hipStreamSynchronize(st));
     double e = info.err_fro;
+    out->err_stored = o.residual ? info.err_fro_explicit : e;
     if (o.residual) {
       // error against A before rounding: the rounding noise E (expected size
       // a_noise_rel) adds to the stored residual except for the part the rank-k

