@@ -346,18 +346,21 @@ def run_c5(torch, P):
     against FP32 storage + the fixed ladder (256, 2), (512, 2), (1024, 2) +
     judge (sorsvd_auto without it); the other two combinations for context.
     The Eckart-Young floor needs k >= 645 here, so the fixed (256, 2) alone
-    cannot meet the tolerance. Also the success rate of the learned first run
-    on 200 held-out spectra (diagonal stand-ins, FP64)."""
+    cannot meet the tolerance. BF16 storage alone perturbs this matrix by
+    1.66e-3 (relative), so the judge, which sees only the stored values,
+    cannot certify BF16 results at 1e-3 here; the same comparison on
+    sigma_j = j^-2 (seed 6), where it can, follows. Also the success rate of
+    the learned first run on 200 held-out spectra (diagonal stand-ins, FP64)."""
     import numpy as np
     from paper_1804_00462_amd import predictor as PR
     params = PR.load_params()
     n = 32768
     j = np.arange(1, n + 1, dtype=np.float64)
     out = {}
-    for name, sigma in (("j^-1.5", j ** -1.5),):
+    for name, sigma, seed in (("j^-1.5", j ** -1.5, 5), ("j^-2", j ** -2.0, 6)):
         log(f"[bench] c5 {n} x {n}, sigma_j = {name}, full spectrum")
         t0 = time.perf_counter()
-        A64 = PR.eval_matrix(n, sigma, 5)
+        A64 = PR.eval_matrix(n, sigma, seed)
         torch.cuda.synchronize()
         log(f"[bench] c5 input ready in {time.perf_counter() - t0:.1f} s")
         res = PR.compare(A64, 1e-3, params, log=log, label=f"c5 {name}")
@@ -372,8 +375,8 @@ def run_c5(torch, P):
                      "bf16_plain": {k: res["bf16_plain"][k] for k in keys + ("ms",)}}
     held = PR.heldout_eval(params, 200, log=log)
     return {"workload": "time to relative Frobenius error <= 1e-3 against the FP64 matrix on 32768 x 32768, "
-                        "sigma_j = j^-1.5 (whole spectrum, Haar U, V, seed 5): BF16 + learned (k, q) vs FP32 + "
-                        "fixed ladder (256, 2) -> (512, 2) -> (1024, 2), both judged",
+                        "sigma_j = j^-1.5 (whole spectrum, Haar U, V, seed 5; and j^-2, seed 6): BF16 + learned "
+                        "(k, q) vs FP32 + fixed ladder (256, 2) -> (512, 2) -> (1024, 2), both judged",
             "cases": out, "heldout": held}
 
 

@@ -440,6 +440,45 @@ int sorsvd_predict_kq(const void* A, int64_t lda, int32_t a_type, int64_t m, int
                       void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Theorem bounds for one draw of Omega (Sec. IV: Th. 4 and Th. 5,
+ * deterministic in Omega; Th. 6 and Th. 7, expectations over Omega), for a
+ * matrix whose right singular vectors are known (a synthetic A =
+ * U diag(sigma) V^T, or V from a reference SVD). With r = l - p, V1 the first
+ * r right singular vectors, Omega1 = V1^T Omega and Omega2 = V2^T Omega (the
+ * partition of Sec. IV-A); Omega is the FP64 draw that sorsvd() makes with
+ * the same seed (for FP32 / 16-bit A the run uses that draw rounded).
+ *
+ *   V1     device, n x r row-major (ldv >= r): the first r right singular
+ *          vectors of A.
+ *   sigma  host, nsig >= max(r, k) + 1 singular values of A, descending (all
+ *          min(m, n) of them for the Frobenius-norm floor of Th. 1).
+ *   k, q   the rank and power steps of the run; 2 <= p + k <= l <= n.
+ *   th4    host, nullable: k lower bounds on sigma_j(A_hat) (Th. 4).
+ *   th6    host, nullable: k lower bounds on E sigma_j(A_hat) (Th. 6; NaN
+ *          unless p >= 2).
+ *   out    host: ||Omega2||_2, ||Omega1^+||_2 and the error upper bounds of
+ *          Th. 5 and Th. 7 (NaN unless p >= 2) in the Frobenius and 2-norm.
+ *          Th. 5 takes tau = (sigma_k / sigma_{l-p+1}) beta with the power
+ *          method (the printed tau is not dimensionless).
+ * ||Omega2||_2 comes from Omega^T Omega - Omega1^T Omega1 (V orthogonal), so
+ * V2 is never needed; ||Omega1^+||_2 = 1 / sigma_min(Omega1). Workspace:
+ * sorsvd_bounds_workspace_bytes(n, l, p). Synchronises the stream. Returns
+ * SORSVD_EINVAL for bad sizes or a sigma that is not descending and
+ * nonnegative with sigma_k > 0.
+ */
+typedef struct sorsvd_bounds_info {
+  double omega2_norm;      /* ||Omega2||_2 */
+  double omega1_pinv_norm; /* ||Omega1^+||_2 */
+  double th5_fro, th5_2;   /* Th. 5 upper bounds on ||A - A_hat|| */
+  double th7_fro, th7_2;   /* Th. 7 upper bounds on E ||A - A_hat|| */
+} sorsvd_bounds_info;
+
+size_t sorsvd_bounds_workspace_bytes(int64_t n, int64_t l, int64_t p);
+int sorsvd_bounds(const double* V1, int64_t ldv, int64_t n, int64_t l, int64_t p, int64_t k, int32_t q,
+                  uint64_t seed, const double* sigma, int64_t nsig, double* th4, double* th6,
+                  sorsvd_bounds_info* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Robust PCA by the ALM-SOR-SVD iteration (Sec. V, "Robust Principal
  * Component Analysis", Table III): split X = L + S (L low-rank, S sparse) by
  * the inexact augmented-Lagrange-multiplier method with a SOR-SVD of width l

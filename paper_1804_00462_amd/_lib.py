@@ -45,6 +45,11 @@ class AutoInfo(ctypes.Structure):
                 ("err_stored", c_dbl)]
 
 
+class BoundsInfo(ctypes.Structure):
+    _fields_ = [("omega2_norm", c_dbl), ("omega1_pinv_norm", c_dbl), ("th5_fro", c_dbl), ("th5_2", c_dbl),
+                ("th7_fro", c_dbl), ("th7_2", c_dbl)]
+
+
 class RpcaInfo(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("rank", c_i32), ("nnz_s", c_i64), ("xi", c_dbl), ("lam", c_dbl),
                 ("norm2", c_dbl)]
@@ -62,6 +67,9 @@ _SIGS = {
     "sorsvd_read_info": (c_i32, [c_vp, c_vp, c_vp]),
     "sorsvd_predict_kq": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_dbl, c_vp, c_vp, c_vp,
                                   c_vp, c_sz, c_vp]),
+    "sorsvd_bounds_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
+    "sorsvd_bounds": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i64, c_i64, c_i32, c_u64, c_vp, c_i64, c_vp, c_vp,
+                              c_vp, c_vp, c_sz, c_vp]),
     "sorsvd_noalloc": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_i64, c_i32, c_u64,
                                c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "sorsvd_pack_f16": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),

@@ -5,8 +5,11 @@ computation runs in the library's kernels. Names follow the C entry points.
 """
 import ctypes
 
+import numpy as np
+
 from . import _lib
-from ._lib import SORSVD_BF16, SORSVD_DIAG, SORSVD_F16, SORSVD_F32, SORSVD_F64, AutoInfo, Info, Opts, Problem, check
+from ._lib import (SORSVD_BF16, SORSVD_DIAG, SORSVD_F16, SORSVD_F32, SORSVD_F64, AutoInfo, BoundsInfo, Info,
+                   Opts, Problem, check)
 
 
 def _torch():
@@ -498,6 +501,33 @@ def predict_kq(A, params, tol=1e-3, seed=0):
     if st not in (0, -6):
         check(st, "sorsvd_predict_kq")
     return int(k.value), int(q.value), list(kp), st == 0
+
+
+def bounds(V1, sigma, k, l, p, q=0, seed=0):
+    """Th. 4 - Th. 7 for the Omega of seed `seed`: V1 (n x (l - p), FP64 on the
+    device) the leading right singular vectors of A, sigma (host, descending)
+    its singular values. Returns a dict with omega2_norm, omega1_pinv_norm,
+    th4 (k), th5_fro, th5_2, th6 (k), th7_fro, th7_2."""
+    torch = _torch()
+    lib = _lib.load()
+    _check_matrix(V1)
+    if V1.dtype != torch.float64:
+        raise TypeError("bounds takes FP64 V1")
+    n = V1.shape[0]
+    sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64))
+    nbytes = int(lib.sorsvd_bounds_workspace_bytes(n, l, p))
+    if nbytes == 0:
+        raise _lib.SorsvdError(-1, "sorsvd_bounds_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=V1.device)
+    th4 = np.zeros(k)
+    th6 = np.zeros(k)
+    out = BoundsInfo()
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib.sorsvd_bounds(_ptr(V1), V1.stride(0), n, l, p, k, q, seed, sig.ctypes.data_as(dp), sig.size,
+                            th4.ctypes.data_as(dp), th6.ctypes.data_as(dp), ctypes.byref(out), _ptr(ws), nbytes,
+                            _stream()), "sorsvd_bounds")
+    return {"omega2_norm": out.omega2_norm, "omega1_pinv_norm": out.omega1_pinv_norm, "th4": th4,
+            "th5_fro": out.th5_fro, "th5_2": out.th5_2, "th6": th6, "th7_fro": out.th7_fro, "th7_2": out.th7_2}
 
 
 def rpca(X, l, q=1, seed=0, tol=1e-7, max_iter=100):

@@ -171,7 +171,45 @@ __global__ void __launch_bounds__(256) k_zero_lower(double* __restrict__ R, int 
   if (idx < l * l && idx % l < idx / l) R[idx] = 0.0;
 }
 
+// C (rows x cols, ldc) = A - B (both rows x cols, lda / ldb); FP64.
+__global__ void __launch_bounds__(256)
+k_sub_f64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B, int64_t ldb, int64_t rows,
+          int cols, double* __restrict__ C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t r = idx / cols;
+  const int c = (int)(idx % cols);
+  C[r * ldc + c] = A[r * lda + c] - B[r * ldb + c];
+}
+
+// dst (cols x rows, ldd) = src^T, src rows x cols (lds); FP64.
+__global__ void __launch_bounds__(256)
+k_transpose_f64(const double* __restrict__ src, int64_t lds, int64_t rows, int cols, double* __restrict__ dst,
+                int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t r = idx % rows;
+  const int c = (int)(idx / rows);
+  dst[(int64_t)c * ldd + r] = src[r * lds + c];
+}
+
 // ------------------------------------------------------------------ launchers
+
+hipError_t launch_sub_f64(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t rows, int cols,
+                          double* C, int64_t ldc, hipStream_t st) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_f64, dim3((unsigned)ceil_div(rows * cols, 256)), dim3(256), 0, st, A, lda, B, ldb, rows,
+                     cols, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_f64(const double* src, int64_t lds, int64_t rows, int cols, double* dst, int64_t ldd,
+                                hipStream_t st) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)ceil_div(rows * cols, 256)), dim3(256), 0, st, src, lds, rows,
+                     cols, dst, ldd);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero_lower(double* R, int l, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_lower, dim3((unsigned)ceil_div((int64_t)l * l, 256)), dim3(256), 0, st, R, l);

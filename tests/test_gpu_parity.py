@@ -64,11 +64,12 @@ def fp32_factor_check(U, V, Uo, Vo, So, K, c=64.0, cap=1e-2):
     gaps[1:] = np.minimum(gaps[1:], d)
     unit = 2.0 ** -24 * np.sqrt(K) * So[0]
     bound = c * unit / gaps
-    ok = bound < cap
+    ok = (bound < cap) & np.isfinite(gaps)   # k = 1: no neighbour known, no gap
     worst = 0.0
     for X, Xo in ((U, Uo), (V, Vo)):
         dev = np.abs(align_signs(X, Xo) - Xo).max(axis=0)
-        assert np.all(dev[ok] <= bound[ok]), (np.nonzero(dev[ok] > bound[ok])[0], dev[ok].max())
+        assert np.all(dev[ok] <= bound[ok]), (np.nonzero(dev[ok] > bound[ok])[0], dev[ok].max(),
+                                              "c needed", float(np.max(dev[ok] * gaps[ok] / unit)))
         if ok.any():
             worst = max(worst, float(np.max(dev[ok] * gaps[ok] / unit)))
     return worst
