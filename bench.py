@@ -68,24 +68,36 @@ REDUCED = {"c3", "c3h", "c3pe"}  # 16-bit storage: also the error against the FP
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_skinny_f32_c2_traffic.md")
-TRAFFIC_SOURCES = ["common.hpp", "skinny_body.hpp", "gemm.hip"]
+# counter summaries of the pass kernels (FETCH_SIZE + WRITE_SIZE per launch)
+# and the sources they were taken from
+TRAFFIC = {
+    "c2": ("k_skinny_f32_c2_traffic.md", ["common.hpp", "skinny_body.hpp", "gemm.hip"]),
+    "c3": ("bf16_passes_c3_traffic.md", ["common.hpp", "half16.hpp", "h16_body.hpp", "gemm_bf16.hip"]),
+}
 
 
-def measured_traffic():
-    """HBM bytes per pass launch from the committed counter summary, or None if
-    the pass kernel's sources changed since the counters were taken."""
+def source_hash(sources):
     import hashlib
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(HERE, "paper_1804_00462_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per pass launch from the committed counter summary of this
+    workload, or None if there is none or the pass kernel's sources changed
+    since the counters were taken."""
+    if name not in TRAFFIC:
+        return None
+    fname, sources = TRAFFIC[name]
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(os.path.join(HERE, "profiles", fname)).read()
     except OSError:
         return None
     vals = dict(line.split(":", 1) for line in text.splitlines()
                 if line.startswith(("traffic_bytes_per_launch:", "source_sha256_16:")))
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        h.update(open(os.path.join(HERE, "paper_1804_00462_amd", "csrc", f), "rb").read())
-    if vals.get("source_sha256_16", "").split()[0:1] != [h.hexdigest()[:16]]:
+    if vals.get("source_sha256_16", "").split()[0:1] != [source_hash(sources)]:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -226,7 +238,7 @@ def run_workload(name, steps, warmup, torch, P, quick=False):
         achieved = per_launch_bytes / avg_launch_s / 1e9
     else:
         achieved = per_launch_flops / avg_launch_s / 1e12
-    traffic = measured_traffic() if name == "c2" else None
+    traffic = measured_traffic(name)
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "pass kernel over A (sketch, orbit, projection products)",

@@ -370,25 +370,29 @@ void sorsvd_batch_destroy(sorsvd_batch* b);
  *   backward and train_step keep them there between their kernels).
  *
  * sorsvd_auto: probe -> network -> (k, q) -> SOR-SVD -> judge -> fallback.
- *   For each q the network's width is taken with 25% head-room, rounded up to
- *   a multiple of 8, and kept if it fits min(128, m, n); among those the (k, q)
- *   with the least modelled pass time P max(1, k / k_ridge) wins (k_ridge 312
- *   for BF16, 39 otherwise; P = 2q + 3 passes, 2q + 2 for BF16 A, whose runs
- *   take the refinement split and the pass-efficient core matrix, as with
- *   opts.refine = opts.pass_efficient = 1). Judge: the error identity
+ *   For each q the network's width is taken with 25% head-room (60% for BF16
+ *   A), rounded up to a multiple of 8 and capped at min(1024, m, n); a q whose
+ *   raw prediction exceeds that cap is dropped. Among the rest the (k, q) of
+ *   the least modelled run time wins: P passes (P = 2q + 3, 2q + 2 for BF16 A,
+ *   whose runs take the refinement split and the pass-efficient core matrix,
+ *   as with opts.refine = opts.pass_efficient = 1), each the larger of its
+ *   bytes at 5 TB/s and its flops at the MFMA rate reached, plus the FP64
+ *   Cholesky QRs and ~1e-11 k^3 s of core SVD. Judge: the error identity
  *   (FP32/FP64), or for BF16 the explicit residual corrected for the rounding
  *   of A to BF16: sqrt(err_fro_explicit^2 - (1 - 2 rho) a_noise_rel^2) with
- *   rho = min(1, 4 k (m^-1/2 + n^-1/2)^2), an allowance for the share of the
- *   rounding noise a rank-k fit absorbs (four times the i.i.d. bound, since
- *   BF16 rounding follows |a_ij|), so that the judge errs on the safe side.
- *   BF16 runs take q >= 1 (with q = 0 the BF16 rounding of the skinny operand
- *   leaves a subspace error near 1e-3). If the judge
- *   rejects, or no predicted width fits, the fallback k = min(128, m, n),
- *   q = 2 runs and is judged. params = NULL skips the network (fallback only).
- *   With the network, every run starts from the probe: Omega is nested in its
- *   width and Cholesky QR keeps column prefixes, so the leading k columns of
- *   the probe's Q are Q1 of the run's first sketch (one pass and one QR fewer).
- *   U, V need ldu, ldv >= min(128, m, n) (the first k_used columns are the
+ *   rho = min(1, 2.5 k (m^-1/2 + n^-1/2)^2), an allowance for the share of
+ *   the rounding noise a rank-k fit absorbs (2.5 times the i.i.d. share;
+ *   measured shares near the tolerance stay below 1.9 times it), so that the
+ *   judge errs on the safe side. BF16 runs take q >= 1 (with q = 0 the BF16
+ *   rounding of the skinny operand leaves a subspace error near 1e-3). If the
+ *   judge rejects, or no predicted width fits, the fixed ladder (256, 2),
+ *   (512, 2), (1024, 2) (widths capped at min(m, n)) runs until the judge
+ *   accepts. params = NULL skips the network (the ladder only).
+ *   With the network, the first run starts from the probe: Omega is nested in
+ *   its width and Cholesky QR keeps column prefixes, so the leading k columns
+ *   of the probe's Q are Q1 of the run's first sketch (one pass and one QR
+ *   fewer) when k <= 128.
+ *   U, V need ldu, ldv >= min(1024, m, n) (the first k_used columns are the
  *   result), S as many entries. Synchronous: waits for `stream`. Returns
  *   SORSVD_OK, or SORSVD_ETOL with the fallback's result left in U, S, V.
  *   Workspace: sorsvd_auto_workspace_bytes(m, n, a_type).

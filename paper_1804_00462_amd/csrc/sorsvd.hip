@@ -1228,7 +1228,11 @@ int sorsvd_mlp_train_step(float* params, float* m, float* v, const float* X, con
   return sorsvd_mlp_adam(params, grad, m, v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
 }
 
-static constexpr double kAutoMargin = 1.25;  // head-room on the predicted width
+static constexpr double kAutoMargin = 1.25;      // head-room on the predicted width
+// BF16: more head-room, since the judge certifies a BF16 result only below the
+// tolerance minus its rounding-noise allowance (the labels are the widths at
+// which the true error reaches the tolerance)
+static constexpr double kAutoMarginBF16 = 1.6;
 static constexpr int64_t kAutoFallbackK = 256;  // first rung of the fixed ladder
 static constexpr int kAutoFallbackQ = 2;
 static constexpr double kNoiseShare = 2.5;   // BF16 judge: captured rounding-noise allowance / i.i.d. share
@@ -1290,10 +1294,11 @@ size_t sorsvd_auto_workspace_bytes(int64_t m, int64_t n, int32_t a_type) {
 
 // The (k, q) of a run from the network's outputs y_q = log2 of the width
 // that meets the trained tolerance with q power steps: each width gets
-// kAutoMargin head-room (rounded up to a multiple of 8) and is capped at
-// kcap; a width predicted beyond 1.5 kcap is dropped (the network's label
-// for "more than the widest sketch" is 2 kcap), and among the rest the q of
-// the least modelled time is taken. k_pred[q] = 2^y_q. Returns whether any
+// kAutoMargin head-room (kAutoMarginBF16 for BF16 A; rounded up to a
+// multiple of 8) and is capped at kcap; a width predicted beyond kcap is
+// dropped (the network then says kcap is short for that q; its label for
+// "more than the widest sketch" is 2 kcap), and among the rest the q of the
+// least modelled time is taken. k_pred[q] = 2^y_q. Returns whether any
 // width is left.
 static bool choose_kq(int32_t a_type, int64_t m, int64_t n, int64_t kcap, const float yh[4], double k_pred[4],
                       int64_t* k, int* q) {
@@ -1319,7 +1324,8 @@ static bool choose_kq(int32_t a_type, int64_t m, int64_t n, int64_t kcap, const 
     k_pred[qq] = yh[qq] == yh[qq] ? std::exp2((double)yh[qq]) : 1e30;
     if (qq < qmin) continue;
     if (!(k_pred[qq] <= (double)kcap)) continue;  // the network says even kcap is short
-    const double kk = std::min((double)kcap, std::ceil(kAutoMargin * k_pred[qq] / 8.0) * 8.0);
+    const double margin = a_type == SORSVD_BF16 ? kAutoMarginBF16 : kAutoMargin;
+    const double kk = std::min((double)kcap, std::ceil(margin * k_pred[qq] / 8.0) * 8.0);
     const int64_t ki = std::max<int64_t>(1, (int64_t)kk);
     const double cost = model_s((double)ki, qq);
     if (cost < best) {

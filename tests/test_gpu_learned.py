@@ -193,7 +193,7 @@ def test_bf16_learned_beats_fp32_plain_to_tolerance(lib):
     p16 = PR.load_params("bf16")
     n, tol = 32768, 1e-3
     j = np.arange(1, n + 1, dtype=np.float64)
-    for name, sigma, seed in (("j^-2.0", j ** -2.0, 6), ("j^-2.5", j ** -2.5, 8), ("0.99^j", 0.99 ** (j - 1), 9)):
+    for name, sigma, seed in (("j^-2.0", j ** -2.0, 6), ("j^-2.5", j ** -2.5, 8), ("j^-1.8", j ** -1.8, 9)):
         A64 = PR.eval_matrix(n, sigma, seed)
         Ab = A64.to(torch.bfloat16)
         Ub, Sb, Vb, ib = PR.time_to_tolerance(Ab, tol, p16, seed=2, reps=3)
