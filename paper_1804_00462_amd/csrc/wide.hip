@@ -429,9 +429,11 @@ k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, in
   };
   const int bp = player(blockIdx.x, t, nbe), bq = player(nbe - 1 - blockIdx.x, t, nbe);
   auto gcol = [&](int c) { return c < B ? bp * B + c : bq * B + (c - B); };
-  for (int e = tid; e < NL * ldc; e += 256) {
-    const int c = e / ldc, r = e % ldc;
-    Ms[e] = Mc[(int64_t)gcol(c) * ldc + r];
+  // (column by column: no division by the runtime column length per element)
+#pragma unroll 1
+  for (int c = 0; c < NL; ++c) {
+    const double* src = Mc + (int64_t)gcol(c) * ldc;
+    for (int r = tid; r < ldc; r += 256) Ms[c * ldc + r] = src[r];
   }
   for (int e = tid; e < NL * NL; e += 256) Ws[e] = (e / NL == e % NL) ? 1.0 : 0.0;
   if (tid == 0) s_rot = 0;
@@ -447,18 +449,36 @@ k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, in
     }
     double* mp = Ms + p * ldc;
     double* mq = Ms + q * ldc;
-    double al = 0.0, be = 0.0, ga = 0.0;
-    for (int r = gl; r < ldc; r += TPP) {
-      const double x = mp[r], y = mq[r];
-      al = fma(x, x, al);
-      be = fma(y, y, be);
-      ga = fma(x, y, ga);
+    // two partial sums per quantity (shorter FMA chains), combined in a
+    // fixed order; then a butterfly over the group's lanes: DPP inside rows
+    // of 16 lanes, one cross-row exchange for 32-lane groups. Every lane of
+    // the group ends with the same bits (each step adds two equal-order sums).
+    double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
+    int r = gl;
+    for (; r + TPP < ldc; r += 2 * TPP) {
+      const double x0 = mp[r], y0 = mq[r], x1 = mp[r + TPP], y1 = mq[r + TPP];
+      al0 = fma(x0, x0, al0);
+      be0 = fma(y0, y0, be0);
+      ga0 = fma(x0, y0, ga0);
+      al1 = fma(x1, x1, al1);
+      be1 = fma(y1, y1, be1);
+      ga1 = fma(x1, y1, ga1);
     }
-#pragma unroll
-    for (int off = TPP / 2; off >= 1; off >>= 1) {  // butterfly: every lane of the group gets the same bits
-      al += __shfl_xor(al, off, kWave);
-      be += __shfl_xor(be, off, kWave);
-      ga += __shfl_xor(ga, off, kWave);
+    if (r < ldc) {
+      const double x0 = mp[r], y0 = mq[r];
+      al0 = fma(x0, x0, al0);
+      be0 = fma(y0, y0, be0);
+      ga0 = fma(x0, y0, ga0);
+    }
+    double al = al0 + al1, be = be0 + be1, ga = ga0 + ga1;
+    static_assert(TPP == 16 || TPP == 32, "lanes per pair");
+    al = sum16(al);
+    be = sum16(be);
+    ga = sum16(ga);
+    if constexpr (TPP == 32) {
+      al += __shfl_xor(al, 16, kWave);
+      be += __shfl_xor(be, 16, kWave);
+      ga += __shfl_xor(ga, 16, kWave);
     }
     if (ga * ga > tol2 * (al * be)) {
       const double zeta = (be - al) / (2.0 * ga);
@@ -480,9 +500,10 @@ k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, in
     __syncthreads();
   }
   if (rotated && gl == 0) s_rot = 1;
-  for (int e = tid; e < NL * ldc; e += 256) {
-    const int c = e / ldc, r = e % ldc;
-    Mc[(int64_t)gcol(c) * ldc + r] = Ms[e];
+#pragma unroll 1
+  for (int c = 0; c < NL; ++c) {
+    double* dst = Mc + (int64_t)gcol(c) * ldc;
+    for (int r = tid; r < ldc; r += 256) dst[r] = Ms[c * ldc + r];
   }
   __syncthreads();
   if (s_rot) {
