@@ -148,22 +148,23 @@ __device__ __attribute__((always_inline)) inline void skinny_tile(const T* A, in
       }
     }
   };
+  // Skinny rows of a step: thread t stages row t / 8 of it, columns
+  // (t % 8) XPT .. + XPT - 1, so one base address serves all of a thread's
+  // loads and LDS stores (per-element addresses cost ~60 registers). Rows
+  // past k1 (last step only) are read clamped and stored as zeros.
+  static_assert(KS * 8 == 256 && XPT * 8 == LP, "one row of the step per 8 threads");
+  const int xrow = threadIdx.x / 8, xcol = (threadIdx.x % 8) * XPT;
   auto load_x = [&](T (&xr)[XPT], int64_t kb) {
+    const int64_t kk = kb + xrow;
+    const T* src = X + (kk < k1 ? kk : k1 - 1) * ldx + xcol;
 #pragma unroll
-    for (int i = 0; i < XPT; ++i) {
-      const int idx = threadIdx.x + 256 * i;
-      const int r = idx / LP, c = idx % LP;
-      const int64_t kk = kb + r;
-      xr[i] = (kk < k1) ? X[kk * ldx + c] : T(0);
-    }
+    for (int i = 0; i < XPT; ++i) xr[i] = src[i];
   };
-
-  auto store_x = [&](const T (&xr)[XPT], T* buf) {
+  auto store_x = [&](const T (&xr)[XPT], T* buf, int64_t kb) {
+    const bool in = kb + xrow < k1;
+    T* dst = buf + xrow * LPS + xcol;
 #pragma unroll
-    for (int i = 0; i < XPT; ++i) {
-      const int idx = threadIdx.x + 256 * i;
-      buf[(idx / LP) * LPS + idx % LP] = xr[i];
-    }
+    for (int i = 0; i < XPT; ++i) dst[i] = in ? xr[i] : T(0);
   };
 
   // A fragments PD steps ahead (FP32 by default two, to cover the HBM latency
@@ -178,7 +179,7 @@ __device__ __attribute__((always_inline)) inline void skinny_tile(const T* A, in
   if (k0 < k1) {
     load_a(a, k0);
     load_x(xr, k0);
-    store_x(xr, xb);
+    store_x(xr, xb, k0);
     if (PD == 2 && k0 + KS < k1) load_a(an, k0 + KS);
   }
   __syncthreads();
@@ -226,7 +227,7 @@ __device__ __attribute__((always_inline)) inline void skinny_tile(const T* A, in
     if (more) {
       // the other buffer was last read in the previous step, which every wave
       // finished before the barrier that ended it
-      store_x(xr, xn);
+      store_x(xr, xn, kb + KS);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll

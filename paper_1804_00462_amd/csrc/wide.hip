@@ -381,7 +381,7 @@ struct WideJacDims {
 WideJacDims wjac_dims(int l) {
   WideJacDims d;
   d.ldc = (int)round_up(l, 32);
-  d.B = ((size_t)32 * d.ldc + 32 * 32) * 8 <= 150 * 1024 ? 16 : 8;
+  d.B = ((size_t)32 * d.ldc + 2 * 32 * 32 + 32) * 8 <= 150 * 1024 ? 16 : 8;
   const int nb = (int)ceil_div(l, d.B);
   d.nbe = nb + (nb & 1);
   if (d.nbe < 2) d.nbe = 2;
@@ -415,12 +415,15 @@ __global__ void __launch_bounds__(256)
 k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, int nbe, int t, int sweep,
             int* __restrict__ cnt, const int* __restrict__ conv, double tol2) {
   if (*conv) return;
-  constexpr int NL = 2 * B, TPP = 256 / B;
+  constexpr int NL = 2 * B, NP = NL / 2, NT = NL / 16;  // columns, pairs per round, 16-column tiles
   extern __shared__ double sm[];
   double* Ms = sm;              // NL columns of ldc
-  double* Ws = sm + NL * ldc;   // W, column-major: W(r, c) = Ws[c NL + r]
+  double* Gs = sm + NL * ldc;   // Gram matrix of the columns, row-major NL x NL
+  double* Ws = Gs + NL * NL;    // W, column-major: W(r, c) = Ws[c NL + r]
+  double* Cs = Ws + NL * NL;    // (c, s) of the round's pairs
+  double* Gp = Cs + 2 * NP;     // per-wave partial Gram (NL = 16: the waves split the rows)
   __shared__ int s_rot;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave, li = lane % 16, g = lane / 16;
   auto player = [](int pos, int step, int n) {
     if (pos == 0) return 0;
     int x = pos - 1 + step;
@@ -429,7 +432,7 @@ k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, in
   };
   const int bp = player(blockIdx.x, t, nbe), bq = player(nbe - 1 - blockIdx.x, t, nbe);
   auto gcol = [&](int c) { return c < B ? bp * B + c : bq * B + (c - B); };
-  // (column by column: no division by the runtime column length per element)
+  // columns to LDS (column by column: no division per element)
 #pragma unroll 1
   for (int c = 0; c < NL; ++c) {
     const double* src = Mc + (int64_t)gcol(c) * ldc;
@@ -438,90 +441,131 @@ k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, in
   for (int e = tid; e < NL * NL; e += 256) Ws[e] = (e / NL == e % NL) ? 1.0 : 0.0;
   if (tid == 0) s_rot = 0;
   __syncthreads();
-  const int grp = tid / TPP, gl = tid % TPP;
+  // Gram matrix G = X^T X on FP64 MFMA (16 x 16 x 4): lane (li, g) feeds
+  // X(k0 + g, col) as both operands. NL = 16: one tile, the four waves take
+  // a quarter of the rows each and the partial tiles are added in wave
+  // order; NL = 32: wave w forms tile (w / 2, w % 2) over all rows.
+  {
+    f64x4 acc = f64x4{0, 0, 0, 0};
+    int ti, tj, r0, r1;
+    if constexpr (NT == 1) {
+      ti = tj = 0;
+      r0 = w * (ldc / 4);
+      r1 = r0 + ldc / 4;
+    } else {
+      ti = w / 2;
+      tj = w % 2;
+      r0 = 0;
+      r1 = ldc;
+    }
+    const double* xa = Ms + (16 * ti + li) * ldc;
+    const double* xb = Ms + (16 * tj + li) * ldc;
+    for (int kb = r0; kb < r1; kb += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[kb + g], xb[kb + g], acc, 0, 0, 0);
+    if constexpr (NT == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Gp[w * 256 + (4 * r + g) * 16 + li] = acc[r];
+      __syncthreads();
+      const double v = (Gp[tid] + Gp[256 + tid]) + (Gp[512 + tid] + Gp[768 + tid]);
+      Gs[tid] = v;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Gs[(16 * ti + 4 * r + g) * NL + 16 * tj + li] = acc[r];
+    }
+  }
+  __syncthreads();
+  // One round-robin sweep of rotations on G (the rotations one-sided Jacobi
+  // would apply to the columns: G is their Gram matrix, updated as
+  // G <- J^T G J), accumulated in W; the NP pairs of a round are disjoint.
   bool rotated = false;
   for (int step = 0; step < NL - 1; ++step) {
-    int p = player(grp, step, NL), q = player(NL - 1 - grp, step, NL);
-    if (p > q) {
-      const int x = p;
-      p = q;
-      q = x;
-    }
-    double* mp = Ms + p * ldc;
-    double* mq = Ms + q * ldc;
-    // two partial sums per quantity (shorter FMA chains), combined in a
-    // fixed order; then a butterfly over the group's lanes: DPP inside rows
-    // of 16 lanes, one cross-row exchange for 32-lane groups. Every lane of
-    // the group ends with the same bits (each step adds two equal-order sums).
-    double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
-    int r = gl;
-    for (; r + TPP < ldc; r += 2 * TPP) {
-      const double x0 = mp[r], y0 = mq[r], x1 = mp[r + TPP], y1 = mq[r + TPP];
-      al0 = fma(x0, x0, al0);
-      be0 = fma(y0, y0, be0);
-      ga0 = fma(x0, y0, ga0);
-      al1 = fma(x1, x1, al1);
-      be1 = fma(y1, y1, be1);
-      ga1 = fma(x1, y1, ga1);
-    }
-    if (r < ldc) {
-      const double x0 = mp[r], y0 = mq[r];
-      al0 = fma(x0, x0, al0);
-      be0 = fma(y0, y0, be0);
-      ga0 = fma(x0, y0, ga0);
-    }
-    double al = al0 + al1, be = be0 + be1, ga = ga0 + ga1;
-    static_assert(TPP == 16 || TPP == 32, "lanes per pair");
-    al = sum16(al);
-    be = sum16(be);
-    ga = sum16(ga);
-    if constexpr (TPP == 32) {
-      al += __shfl_xor(al, 16, kWave);
-      be += __shfl_xor(be, 16, kWave);
-      ga += __shfl_xor(ga, 16, kWave);
-    }
-    if (ga * ga > tol2 * (al * be)) {
-      const double zeta = (be - al) / (2.0 * ga);
-      const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double c = 1.0 / sqrt(1.0 + tt * tt);
-      const double s = c * tt;
-      for (int r = gl; r < ldc; r += TPP) {
-        const double x = mp[r], y = mq[r];
-        mp[r] = c * x - s * y;
-        mq[r] = s * x + c * y;
+    if (tid < NP) {
+      int p = player(tid, step, NL), q = player(NL - 1 - tid, step, NL);
+      if (p > q) {
+        const int x = p;
+        p = q;
+        q = x;
       }
-      for (int r = gl; r < NL; r += TPP) {
-        const double x = Ws[p * NL + r], y = Ws[q * NL + r];
-        Ws[p * NL + r] = c * x - s * y;
-        Ws[q * NL + r] = s * x + c * y;
+      const double al = Gs[p * NL + p], be = Gs[q * NL + q], ga = Gs[p * NL + q];
+      double c = 1.0, sn = 0.0;
+      if (ga * ga > tol2 * (al * be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        c = 1.0 / sqrt(1.0 + tt * tt);
+        sn = c * tt;
+        rotated = true;
       }
-      rotated = true;
+      Cs[2 * tid] = c;
+      Cs[2 * tid + 1] = sn;
+    }
+    __syncthreads();
+    // columns p, q of G and W: x_p <- c x_p - s x_q, x_q <- s x_p + c x_q
+    for (int e = tid; e < NP * NL; e += 256) {
+      const int pr = e / NL, r = e % NL;
+      int p = player(pr, step, NL), q = player(NL - 1 - pr, step, NL);
+      if (p > q) {
+        const int x = p;
+        p = q;
+        q = x;
+      }
+      const double c = Cs[2 * pr], sn = Cs[2 * pr + 1];
+      if (sn != 0.0) {
+        const double gp = Gs[r * NL + p], gq = Gs[r * NL + q];
+        Gs[r * NL + p] = c * gp - sn * gq;
+        Gs[r * NL + q] = sn * gp + c * gq;
+        const double wp = Ws[p * NL + r], wq = Ws[q * NL + r];
+        Ws[p * NL + r] = c * wp - sn * wq;
+        Ws[q * NL + r] = sn * wp + c * wq;
+      }
+    }
+    __syncthreads();
+    // rows p, q of G
+    for (int e = tid; e < NP * NL; e += 256) {
+      const int pr = e / NL, r = e % NL;
+      int p = player(pr, step, NL), q = player(NL - 1 - pr, step, NL);
+      if (p > q) {
+        const int x = p;
+        p = q;
+        q = x;
+      }
+      const double c = Cs[2 * pr], sn = Cs[2 * pr + 1];
+      if (sn != 0.0) {
+        const double gp = Gs[p * NL + r], gq = Gs[q * NL + r];
+        Gs[p * NL + r] = c * gp - sn * gq;
+        Gs[q * NL + r] = sn * gp + c * gq;
+      }
     }
     __syncthreads();
   }
-  if (rotated && gl == 0) s_rot = 1;
-#pragma unroll 1
-  for (int c = 0; c < NL; ++c) {
-    double* dst = Mc + (int64_t)gcol(c) * ldc;
-    for (int r = tid; r < ldc; r += 256) dst[r] = Ms[c * ldc + r];
-  }
+  if (rotated) s_rot = 1;
   __syncthreads();
-  if (s_rot) {
-    // V columns of the pair <- (those columns) W, row by row
-    for (int r = tid; r < l; r += 256) {
-      double v[NL];
+  if (!s_rot) return;  // the columns (and V) stay as they are
+  // X <- X W and V <- V W, row by row
+  for (int r = tid; r < ldc; r += 256) {
+    double x[NL];
 #pragma unroll
-      for (int c = 0; c < NL; ++c) v[c] = Vc[(int64_t)gcol(c) * ldc + r];
+    for (int c = 0; c < NL; ++c) x[c] = Ms[c * ldc + r];
 #pragma unroll 1
-      for (int j = 0; j < NL; ++j) {  // (not unrolled: W stays in LDS instead of being hoisted into registers)
-        double a = 0.0;
+    for (int j = 0; j < NL; ++j) {  // (not unrolled: W stays in LDS instead of being hoisted into registers)
+      double a = 0.0;
 #pragma unroll
-        for (int c = 0; c < NL; ++c) a = fma(v[c], Ws[j * NL + c], a);
-        Vc[(int64_t)gcol(j) * ldc + r] = a;
-      }
+      for (int c = 0; c < NL; ++c) a = fma(x[c], Ws[j * NL + c], a);
+      Mc[(int64_t)gcol(j) * ldc + r] = a;
     }
-    if (tid == 0) atomicAdd(&cnt[sweep], 1);
   }
+  for (int r = tid; r < l; r += 256) {
+    double v[NL];
+#pragma unroll
+    for (int c = 0; c < NL; ++c) v[c] = Vc[(int64_t)gcol(c) * ldc + r];
+#pragma unroll 1
+    for (int j = 0; j < NL; ++j) {
+      double a = 0.0;
+#pragma unroll
+      for (int c = 0; c < NL; ++c) a = fma(v[c], Ws[j * NL + c], a);
+      Vc[(int64_t)gcol(j) * ldc + r] = a;
+    }
+  }
+  if (tid == 0) atomicAdd(&cnt[sweep], 1);
 }
 
 __global__ void __launch_bounds__(64)
@@ -601,7 +645,8 @@ hipError_t launch_jacobi_wide(const double* M, int LPm, int l, int k, int max_sw
   const int64_t tot = (int64_t)ncp * d.ldc;
   hipLaunchKernelGGL(k_wjac_init, dim3((unsigned)std::min<int64_t>(1024, ceil_div(tot, 256))), dim3(256), 0, st, M,
                      LPm, l, trans ? 1 : 0, ncp, d.ldc, Mc, Vc, cnt, max_sweeps);
-  const size_t shm = ((size_t)2 * d.B * d.ldc + 4 * d.B * d.B) * 8;
+  // columns, G, W, (c, s) per pair, and the per-wave partial Gram (B = 8)
+  const size_t shm = ((size_t)2 * d.B * d.ldc + 8 * d.B * d.B + 2 * d.B + (d.B == 8 ? 4 * 256 : 0)) * 8;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int t = 0; t < d.nbe - 1; ++t) {
       if (d.B == 16)
