@@ -45,7 +45,9 @@ k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
   const int64_t k0 = (int64_t)s * kchunk;
   const int64_t k1 = min(K, k0 + kchunk);
   const int64_t base = (int64_t)tile * (64 * RT);
-  skinny_tile<T, TRANS, RT, CT>(A, lda, OUT, k0, k1, X + c0, ldx, base, vec_ok,
+  // FP32 A^T Y: A fragments one step ahead (157 instead of 176 VGPRs at CT = 7:
+  // three waves per SIMD); FP32 A X: two
+  skinny_tile<T, TRANS, RT, CT, (sizeof(T) == 4 && !TRANS) ? 2 : 1>(A, lda, OUT, k0, k1, X + c0, ldx, base, vec_ok,
                                 Tout ? nullptr : P + (int64_t)s * OUT * ldp + c0, Tout ? Tout + c0 : nullptr, ldp,
                                 (normp && cb == 0) ? normp + u : nullptr, Xs, red, tri, ldp, c0);
 }

@@ -432,11 +432,20 @@ k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, in
   };
   const int bp = player(blockIdx.x, t, nbe), bq = player(nbe - 1 - blockIdx.x, t, nbe);
   auto gcol = [&](int c) { return c < B ? bp * B + c : bq * B + (c - B); };
-  // columns to LDS (column by column: no division per element)
-#pragma unroll 1
-  for (int c = 0; c < NL; ++c) {
-    const double* src = Mc + (int64_t)gcol(c) * ldc;
-    for (int r = tid; r < ldc; r += 256) Ms[c * ldc + r] = src[r];
+  // columns to LDS: a thread loads its rows of all NL columns before storing
+  // any (2 NL loads in flight per thread for B = 8; ldc is a multiple of 32)
+  constexpr int RR = NL == 16 ? 2 : 1;
+  for (int r = tid; r < ldc; r += 256 * RR) {
+    double v[RR][NL];
+#pragma unroll
+    for (int u = 0; u < RR; ++u)
+#pragma unroll
+      for (int c = 0; c < NL; ++c) v[u][c] = r + 256 * u < ldc ? Mc[(int64_t)gcol(c) * ldc + r + 256 * u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < RR; ++u)
+      if (r + 256 * u < ldc)
+#pragma unroll
+        for (int c = 0; c < NL; ++c) Ms[c * ldc + r + 256 * u] = v[u][c];
   }
   for (int e = tid; e < NL * NL; e += 256) Ws[e] = (e / NL == e % NL) ? 1.0 : 0.0;
   if (tid == 0) s_rot = 0;
@@ -540,29 +549,46 @@ k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, in
   if (rotated) s_rot = 1;
   __syncthreads();
   if (!s_rot) return;  // the columns (and V) stay as they are
-  // X <- X W and V <- V W, row by row
-  for (int r = tid; r < ldc; r += 256) {
-    double x[NL];
+  // X <- X W (X from LDS) and V <- V W (V from global) on FP64 MFMA: wave w
+  // takes the 16-row tiles w, w + 4, ..., four at a time; a lane holds
+  // A(r0 + li, 4 s + g) of the four tiles for the NL / 4 contraction steps s
+  // before any of their outputs is stored (V is read and written in place,
+  // and the loads of four tiles are in flight together).
+  constexpr int TB = 4;  // row tiles per batch of loads
+  for (int rb = 16 * w; rb < ldc; rb += 64 * TB) {
+    double xa[TB][NL / 4], va[TB][NL / 4];
 #pragma unroll
-    for (int c = 0; c < NL; ++c) x[c] = Ms[c * ldc + r];
-#pragma unroll 1
-    for (int j = 0; j < NL; ++j) {  // (not unrolled: W stays in LDS instead of being hoisted into registers)
-      double a = 0.0;
+    for (int tb = 0; tb < TB; ++tb) {
+      const int r0 = rb + 64 * tb;
+      if (r0 < ldc) {
 #pragma unroll
-      for (int c = 0; c < NL; ++c) a = fma(x[c], Ws[j * NL + c], a);
-      Mc[(int64_t)gcol(j) * ldc + r] = a;
+        for (int s4 = 0; s4 < NL / 4; ++s4) {
+          xa[tb][s4] = Ms[(4 * s4 + g) * ldc + r0 + li];
+          va[tb][s4] = Vc[(int64_t)gcol(4 * s4 + g) * ldc + r0 + li];
+        }
+      }
     }
-  }
-  for (int r = tid; r < l; r += 256) {
-    double v[NL];
 #pragma unroll
-    for (int c = 0; c < NL; ++c) v[c] = Vc[(int64_t)gcol(c) * ldc + r];
-#pragma unroll 1
-    for (int j = 0; j < NL; ++j) {
-      double a = 0.0;
+    for (int tb = 0; tb < TB; ++tb) {
+      const int r0 = rb + 64 * tb;
+      if (r0 >= ldc) break;
 #pragma unroll
-      for (int c = 0; c < NL; ++c) a = fma(v[c], Ws[j * NL + c], a);
-      Vc[(int64_t)gcol(j) * ldc + r] = a;
+      for (int ct = 0; ct < NT; ++ct) {
+        f64x4 ax = f64x4{0, 0, 0, 0}, av = f64x4{0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < NL / 4; ++s4) {
+          const double b = Ws[(16 * ct + li) * NL + 4 * s4 + g];  // W(4 s + g, 16 ct + li)
+          ax = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[tb][s4], b, ax, 0, 0, 0);
+          av = __builtin_amdgcn_mfma_f64_16x16x4f64(va[tb][s4], b, av, 0, 0, 0);
+        }
+        double* xo = Mc + (int64_t)gcol(16 * ct + li) * ldc + r0;
+        double* vo = Vc + (int64_t)gcol(16 * ct + li) * ldc + r0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          xo[4 * r + g] = ax[r];
+          vo[4 * r + g] = av[r];
+        }
+      }
     }
   }
   if (tid == 0) atomicAdd(&cnt[sweep], 1);
