@@ -311,6 +311,22 @@ __host__ __device__ inline size_t jacobi_lds(int l, bool want_v, bool* v_lds) {
   return jac_vpad_fits(l) ? 2 * mbytes : mbytes + ((size_t)l * l + 1) * 8;
 }
 
+// (c, s) of the pair rotation above for gamma != 0, with t in one division:
+// multiplying the numerator and the denominator of t by 2 |gamma| gives
+// t = sign(zeta) 2 |gamma| / (|d| + sqrt(d^2 + 4 gamma^2)), d = beta - alpha,
+// evaluated on d and 2 gamma scaled by the same power of two (the squares can
+// neither overflow nor underflow, and t does not change); sign(zeta) = +1
+// for d = 0. c = rsqrt(1 + t^2) with 1 + t^2 in [1, 2].
+__device__ inline void jac_rotation(double al, double be, double ga, double& c, double& s) {
+  const double d = be - al, g2 = 2.0 * ga;
+  const int e = ilogb(fmax(fabs(d), fabs(g2)));
+  const double ds = ldexp(d, -e), gs = ldexp(g2, -e);
+  const double t0 = fabs(gs) / (fabs(ds) + sqrt(fma(ds, ds, gs * gs)));
+  const double t = (d == 0.0 || (d > 0.0) == (ga > 0.0)) ? t0 : -t0;
+  c = rsqrt(fma(t, t, 1.0));
+  s = c * t;
+}
+
 // Min is given as nparts partial sums (stride pstride elements), added in
 // order. tol2 = tol^2 (the main path takes tol = sqrt(l) 2^-52).
 //
@@ -423,7 +439,7 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
         int ipl = 0, iql = 0;
         if (WANT_V) {
           // read before the rotation is formed, so that the latency overlaps
-          // the divisions and square roots
+          // the division and square roots
 #pragma unroll
           for (int i = 0; i < NRB - 1; ++i) {
             vx[i] = Vc[p * vld + gl + 8 * i];
@@ -436,10 +452,8 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
           vxl = Vc[ipl];
           vyl = Vc[iql];
         }
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double s = c * t;
+        double c, s;
+        jac_rotation(al, be, ga, c, s);
         if (lg) *lg = double2{c, s};
 #pragma unroll
         for (int i = 0; i < NRB; ++i) {

@@ -363,13 +363,16 @@ hipError_t launch_chol_wide(double* G, int LP, int l, int64_t rows, int mode, do
 // in global memory (Mc, V in Vc, column stride ldc >= l, rows >= l zero). A
 // sweep pairs the blocks by the round-robin order (nbe - 1 steps of nbe / 2
 // disjoint block pairs; block 0 stays, the others move one place per step).
-// Per step one workgroup takes each block pair: its 2B columns go to LDS,
-// where one round-robin sweep of pair rotations runs over them (the
-// rotation of the one-workgroup kernel: zeta = (beta - alpha) / (2 gamma),
-// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2),
-// s = c t, applied when gamma^2 > tol^2 alpha beta), while the product W of
-// the rotations (2B x 2B) is accumulated; then the columns go back and the
-// matching columns of V are multiplied by W. Every pair of columns meets at
+// Per step one workgroup takes each block pair: its 2B columns go to LDS and
+// their Gram matrix G is formed; one round-robin sweep of pair rotations runs
+// on G (the rotation of the one-workgroup kernel, jac_rotation, applied when
+// gamma^2 > tol^2 alpha beta, as G <- J^T G J), while the product W of the
+// rotations (2B x 2B) is accumulated; then the columns are multiplied by W
+// and W is published. V is not touched by these workgroups: the same launch
+// carries further workgroups that multiply the columns of V of the previous
+// step's block pairs by that step's W (V is read by no step, so its update
+// can trail by one launch and runs on CUs the block pairs leave idle; one
+// launch after the last step applies the last W). Every pair of columns meets at
 // least once per sweep. A sweep in which no workgroup rotated ends the
 // iteration (the later launches return at once); then sigma_j = |m_j|,
 // U~_j = m_j / sigma_j, V~_j = v_j, in descending order (ties: lower index).
@@ -381,7 +384,7 @@ struct WideJacDims {
 WideJacDims wjac_dims(int l) {
   WideJacDims d;
   d.ldc = (int)round_up(l, 32);
-  d.B = ((size_t)32 * d.ldc + 2 * 32 * 32 + 32) * 8 <= 150 * 1024 ? 16 : 8;
+  d.B = ((size_t)32 * d.ldc + 2 * 32 * 32) * 8 <= 150 * 1024 ? 16 : 8;
   const int nb = (int)ceil_div(l, d.B);
   d.nbe = nb + (nb & 1);
   if (d.nbe < 2) d.nbe = 2;
@@ -389,39 +392,110 @@ WideJacDims wjac_dims(int l) {
 }
 
 // Scratch of launch_jacobi_wide: Mc, Vc (nbe B x ldc each), the singular
-// values (l), the per-sweep rotation counters (up to kWideMaxSweeps) and the
-// convergence word.
+// values (l), the W of every block pair for two consecutive steps (2 x nbe/2
+// x (2B)^2), the per-sweep rotation counters (up to kWideMaxSweeps), the
+// convergence word, and the step tags of the published W (2 x nbe/2).
 constexpr int kWideMaxSweeps = 64;
 size_t jacobi_wide_bytes(int l) {
   const WideJacDims d = wjac_dims(l);
-  return ((size_t)2 * d.nbe * d.B * d.ldc + l) * 8 + ((size_t)kWideMaxSweeps + 64) * 4;
+  const size_t npair = (size_t)d.nbe / 2, nl = 2 * (size_t)d.B;
+  return ((size_t)2 * d.nbe * d.B * d.ldc + l + 2 * npair * nl * nl) * 8 + ((size_t)kWideMaxSweeps + 64) * 4 +
+         2 * npair * 4;
 }
 
 __global__ void __launch_bounds__(256)
 k_wjac_init(const double* __restrict__ M, int LPm, int l, int trans, int ncp, int ldc, double* __restrict__ Mc,
-            double* __restrict__ Vc, int* __restrict__ cnt, int max_sweeps) {
+            double* __restrict__ Vc, int* __restrict__ cnt, int max_sweeps, int* __restrict__ wtag, int ntag) {
   const int64_t tot = (int64_t)ncp * ldc;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
     const int j = (int)(e / ldc), i = (int)(e % ldc);
     Mc[e] = (i < l && j < l) ? M[trans ? (int64_t)j * LPm + i : (int64_t)i * LPm + j] : 0.0;
     Vc[e] = (i == j && j < l) ? 1.0 : 0.0;
   }
-  if (blockIdx.x == 0)
+  if (blockIdx.x == 0) {
     for (int s = threadIdx.x; s <= max_sweeps; s += 256) cnt[s] = 0;  // cnt[max_sweeps]: convergence word
+    for (int s = threadIdx.x; s < ntag; s += 256) wtag[s] = 0;         // no W published yet
+  }
 }
 
+// V <- V W for the block pair pr of step tp (W column-major, from the step's
+// published buffer), rows [r0, r1) in 16-row tiles: wave w takes the tiles
+// w, w + 4, ..., four at a time, all their loads in flight before any store;
+// the product as (V W)^T = W^T V^T, as for the columns (128-byte stores).
+template <int B>
+__device__ void wjac_apply_v(double* __restrict__ Vc, int ldc, int nbe, int pr, int tp,
+                             const double* __restrict__ W, int r0, int r1) {
+  constexpr int NL = 2 * B, NT = NL / 16, TB = 4;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, li = lane % 16, g = lane / 16;
+  auto player = [](int pos, int step, int n) {
+    if (pos == 0) return 0;
+    int x = pos - 1 + step;
+    if (x >= n - 1) x -= n - 1;
+    return 1 + x;
+  };
+  const int bp = player(pr, tp, nbe), bq = player(nbe - 1 - pr, tp, nbe);
+  auto gcol = [&](int c) { return c < B ? bp * B + c : bq * B + (c - B); };
+  double wb[NT][NL / 4];
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int s4 = 0; s4 < NL / 4; ++s4) wb[ct][s4] = W[(16 * ct + li) * NL + 4 * s4 + g];  // W(4 s + g, 16 ct + li)
+  for (int rb = r0 + 16 * w; rb < r1; rb += 64 * TB) {
+    double va[TB][NL / 4];
+#pragma unroll
+    for (int tb = 0; tb < TB; ++tb) {
+      const int rt = rb + 64 * tb;
+      if (rt < r1) {
+#pragma unroll
+        for (int s4 = 0; s4 < NL / 4; ++s4) va[tb][s4] = Vc[(int64_t)gcol(4 * s4 + g) * ldc + rt + li];
+      }
+    }
+#pragma unroll
+    for (int tb = 0; tb < TB; ++tb) {
+      const int rt = rb + 64 * tb;
+      if (rt >= r1) break;
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        f64x4 av = f64x4{0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < NL / 4; ++s4) av = __builtin_amdgcn_mfma_f64_16x16x4f64(wb[ct][s4], va[tb][s4], av, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Vc[(int64_t)gcol(16 * ct + 4 * r + g) * ldc + rt + li] = av[r];
+      }
+    }
+  }
+}
+
+// One launch per step t of sweep `sweep` (global step s = sweep (nbe - 1) + t).
+// Workgroups [0, xparts) take the block pairs of step s (xparts = nbe / 2, or
+// 0 for the launch that only applies the last W); workgroup xparts + pr
+// vchunks + ch applies the W of pair pr of step s - 1 to row chunk ch of V,
+// if that step published it: W of step s goes to buffer s % 2 of Wg with tag
+// s + 1 in wtag (tags are unique within a run and cleared at its start, so a
+// buffer left from step s - 2 never matches).
 template <int B>
 __global__ void __launch_bounds__(256)
 k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, int nbe, int t, int sweep,
-            int* __restrict__ cnt, const int* __restrict__ conv, double tol2) {
-  if (*conv) return;
+            int* __restrict__ cnt, const int* __restrict__ conv, double tol2, double* __restrict__ Wg,
+            int* __restrict__ wtag, int xparts, int vchunks) {
   constexpr int NL = 2 * B, NP = NL / 2, NT = NL / 16;  // columns, pairs per round, 16-column tiles
+  const int npair = nbe / 2, gs = sweep * (nbe - 1) + t;
+  if ((int)blockIdx.x >= xparts) {
+    const int vb = (int)blockIdx.x - xparts, pr = vb / vchunks, ch = vb % vchunks;
+    const int pb = (gs - 1) & 1;
+    if (gs == 0 || wtag[pb * npair + pr] != gs) return;
+    const int crow = (int)round_up(ceil_div(ldc, vchunks), 16);
+    const int r0 = ch * crow, r1 = min(ldc, r0 + crow);
+    if (r0 < r1)
+      wjac_apply_v<B>(Vc, ldc, nbe, pr, t == 0 ? nbe - 2 : t - 1, Wg + ((size_t)pb * npair + pr) * NL * NL, r0, r1);
+    return;
+  }
+  if (*conv) return;
   extern __shared__ double sm[];
   double* Ms = sm;              // NL columns of ldc
   double* Gs = sm + NL * ldc;   // Gram matrix of the columns, row-major NL x NL
   double* Ws = Gs + NL * NL;    // W, column-major: W(r, c) = Ws[c NL + r]
-  double* Cs = Ws + NL * NL;    // (c, s) of the round's pairs
-  double* Gp = Cs + 2 * NP;     // per-wave partial Gram (NL = 16: the waves split the rows)
+  double* Gp = Ws + NL * NL;    // per-wave partial Gram (NL = 16: the waves split the rows)
   __shared__ int s_rot;
   const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave, li = lane % 16, g = lane / 16;
   auto player = [](int pos, int step, int n) {
@@ -485,113 +559,102 @@ k_wjac_step(double* __restrict__ Mc, double* __restrict__ Vc, int ldc, int l, in
   __syncthreads();
   // One round-robin sweep of rotations on G (the rotations one-sided Jacobi
   // would apply to the columns: G is their Gram matrix, updated as
-  // G <- J^T G J), accumulated in W; the NP pairs of a round are disjoint.
-  bool rotated = false;
-  for (int step = 0; step < NL - 1; ++step) {
-    if (tid < NP) {
-      int p = player(tid, step, NL), q = player(NL - 1 - tid, step, NL);
+  // G <- J^T G J), accumulated in W <- W J; the NP pairs of a round are
+  // disjoint. Wave 0 alone runs it. Lane b takes the 2 x 2 blocks (pair i,
+  // pair j) with j = b % NP and i = b / NP, b / NP + 64 / NP, ...: it forms
+  // the rotation of pair j itself (every lane with the same j gets the same
+  // bits) and takes that of pair i from lane i, then rotates its blocks of G
+  // by both (columns by pair j, rows by pair i) and its blocks of W by pair
+  // j. The blocks cover G and W once. A wave performs its LDS accesses in
+  // order, so a round only waits for its own LDS writes before the next
+  // round reads them (no workgroup barrier inside the sweep).
+  if (w == 0) {
+    constexpr int NI = NP * NP / kWave;  // blocks per lane
+    auto wave_lds_sync = [] { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); };
+    auto pair_of = [&](int i, int step, int& p, int& q) {
+      p = player(i, step, NL);
+      q = player(NL - 1 - i, step, NL);
       if (p > q) {
         const int x = p;
         p = q;
         q = x;
       }
-      const double al = Gs[p * NL + p], be = Gs[q * NL + q], ga = Gs[p * NL + q];
-      double c = 1.0, sn = 0.0;
+    };
+    const int j = lane % NP;
+    bool rotated = false;
+    for (int step = 0; step < NL - 1; ++step) {
+      int pj, qj, pi[NI], qi[NI];
+      pair_of(j, step, pj, qj);
+      const double al = Gs[pj * NL + pj], be = Gs[qj * NL + qj], ga = Gs[pj * NL + qj];
+      double g[NI][4], wv[NI][4];
+#pragma unroll
+      for (int u = 0; u < NI; ++u) {
+        pair_of(lane / NP + u * (kWave / NP), step, pi[u], qi[u]);
+        g[u][0] = Gs[pi[u] * NL + pj];
+        g[u][1] = Gs[pi[u] * NL + qj];
+        g[u][2] = Gs[qi[u] * NL + pj];
+        g[u][3] = Gs[qi[u] * NL + qj];
+        wv[u][0] = Ws[pj * NL + pi[u]];
+        wv[u][1] = Ws[qj * NL + pi[u]];
+        wv[u][2] = Ws[pj * NL + qi[u]];
+        wv[u][3] = Ws[qj * NL + qi[u]];
+      }
+      double cj = 1.0, sj = 0.0;
       if (ga * ga > tol2 * (al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        c = 1.0 / sqrt(1.0 + tt * tt);
-        sn = c * tt;
+        jac_rotation(al, be, ga, cj, sj);
         rotated = true;
       }
-      Cs[2 * tid] = c;
-      Cs[2 * tid + 1] = sn;
+#pragma unroll
+      for (int u = 0; u < NI; ++u) {
+        const int src = lane / NP + u * (kWave / NP);  // a lane whose j is pair i
+        const double ci = __shfl(cj, src), si = __shfl(sj, src);
+        if (si == 0.0 && sj == 0.0) continue;
+        const double a0 = cj * g[u][0] - sj * g[u][1], b0 = sj * g[u][0] + cj * g[u][1];  // row p_i
+        const double a1 = cj * g[u][2] - sj * g[u][3], b1 = sj * g[u][2] + cj * g[u][3];  // row q_i
+        Gs[pi[u] * NL + pj] = ci * a0 - si * a1;
+        Gs[qi[u] * NL + pj] = si * a0 + ci * a1;
+        Gs[pi[u] * NL + qj] = ci * b0 - si * b1;
+        Gs[qi[u] * NL + qj] = si * b0 + ci * b1;
+        if (sj != 0.0) {  // W(r, p_j), W(r, q_j) for rows r = p_i, q_i
+          Ws[pj * NL + pi[u]] = cj * wv[u][0] - sj * wv[u][1];
+          Ws[qj * NL + pi[u]] = sj * wv[u][0] + cj * wv[u][1];
+          Ws[pj * NL + qi[u]] = cj * wv[u][2] - sj * wv[u][3];
+          Ws[qj * NL + qi[u]] = sj * wv[u][2] + cj * wv[u][3];
+        }
+      }
+      wave_lds_sync();
     }
-    __syncthreads();
-    // columns p, q of G and W: x_p <- c x_p - s x_q, x_q <- s x_p + c x_q
-    for (int e = tid; e < NP * NL; e += 256) {
-      const int pr = e / NL, r = e % NL;
-      int p = player(pr, step, NL), q = player(NL - 1 - pr, step, NL);
-      if (p > q) {
-        const int x = p;
-        p = q;
-        q = x;
-      }
-      const double c = Cs[2 * pr], sn = Cs[2 * pr + 1];
-      if (sn != 0.0) {
-        const double gp = Gs[r * NL + p], gq = Gs[r * NL + q];
-        Gs[r * NL + p] = c * gp - sn * gq;
-        Gs[r * NL + q] = sn * gp + c * gq;
-        const double wp = Ws[p * NL + r], wq = Ws[q * NL + r];
-        Ws[p * NL + r] = c * wp - sn * wq;
-        Ws[q * NL + r] = sn * wp + c * wq;
-      }
-    }
-    __syncthreads();
-    // rows p, q of G
-    for (int e = tid; e < NP * NL; e += 256) {
-      const int pr = e / NL, r = e % NL;
-      int p = player(pr, step, NL), q = player(NL - 1 - pr, step, NL);
-      if (p > q) {
-        const int x = p;
-        p = q;
-        q = x;
-      }
-      const double c = Cs[2 * pr], sn = Cs[2 * pr + 1];
-      if (sn != 0.0) {
-        const double gp = Gs[p * NL + r], gq = Gs[q * NL + r];
-        Gs[p * NL + r] = c * gp - sn * gq;
-        Gs[q * NL + r] = sn * gp + c * gq;
-      }
-    }
-    __syncthreads();
+    if (__any(rotated) && lane == 0) s_rot = 1;
   }
-  if (rotated) s_rot = 1;
   __syncthreads();
   if (!s_rot) return;  // the columns (and V) stay as they are
-  // X <- X W (X from LDS) and V <- V W (V from global) on FP64 MFMA: wave w
-  // takes the 16-row tiles w, w + 4, ..., four at a time; a lane holds
-  // A(r0 + li, 4 s + g) of the four tiles for the NL / 4 contraction steps s
-  // before any of their outputs is stored (V is read and written in place,
-  // and the loads of four tiles are in flight together).
-  constexpr int TB = 4;  // row tiles per batch of loads
-  for (int rb = 16 * w; rb < ldc; rb += 64 * TB) {
-    double xa[TB][NL / 4], va[TB][NL / 4];
+  // X <- X W (X from LDS) on FP64 MFMA, as (X W)^T = W^T X^T so that a
+  // lane's four outputs are one column's rows and each store instruction
+  // writes four columns x 16 rows (128-byte runs): wave w takes the 16-row
+  // tiles w, w + 4, ...
+  for (int r0 = 16 * w; r0 < ldc; r0 += 64) {
+    double xa[NL / 4];
 #pragma unroll
-    for (int tb = 0; tb < TB; ++tb) {
-      const int r0 = rb + 64 * tb;
-      if (r0 < ldc) {
+    for (int s4 = 0; s4 < NL / 4; ++s4) xa[s4] = Ms[(4 * s4 + g) * ldc + r0 + li];
 #pragma unroll
-        for (int s4 = 0; s4 < NL / 4; ++s4) {
-          xa[tb][s4] = Ms[(4 * s4 + g) * ldc + r0 + li];
-          va[tb][s4] = Vc[(int64_t)gcol(4 * s4 + g) * ldc + r0 + li];
-        }
+    for (int ct = 0; ct < NT; ++ct) {
+      f64x4 ax = f64x4{0, 0, 0, 0};
+#pragma unroll
+      for (int s4 = 0; s4 < NL / 4; ++s4) {
+        const double b = Ws[(16 * ct + li) * NL + 4 * s4 + g];  // W(4 s + g, 16 ct + li)
+        ax = __builtin_amdgcn_mfma_f64_16x16x4f64(b, xa[s4], ax, 0, 0, 0);
       }
-    }
 #pragma unroll
-    for (int tb = 0; tb < TB; ++tb) {
-      const int r0 = rb + 64 * tb;
-      if (r0 >= ldc) break;
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) {
-        f64x4 ax = f64x4{0, 0, 0, 0}, av = f64x4{0, 0, 0, 0};
-#pragma unroll
-        for (int s4 = 0; s4 < NL / 4; ++s4) {
-          const double b = Ws[(16 * ct + li) * NL + 4 * s4 + g];  // W(4 s + g, 16 ct + li)
-          ax = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[tb][s4], b, ax, 0, 0, 0);
-          av = __builtin_amdgcn_mfma_f64_16x16x4f64(va[tb][s4], b, av, 0, 0, 0);
-        }
-        double* xo = Mc + (int64_t)gcol(16 * ct + li) * ldc + r0;
-        double* vo = Vc + (int64_t)gcol(16 * ct + li) * ldc + r0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          xo[4 * r + g] = ax[r];
-          vo[4 * r + g] = av[r];
-        }
-      }
+      for (int r = 0; r < 4; ++r) Mc[(int64_t)gcol(16 * ct + 4 * r + g) * ldc + r0 + li] = ax[r];
     }
   }
-  if (tid == 0) atomicAdd(&cnt[sweep], 1);
+  // publish W for the next launch's V workgroups
+  double* Wo = Wg + ((size_t)(gs & 1) * npair + blockIdx.x) * NL * NL;
+  for (int e = tid; e < NL * NL; e += 256) Wo[e] = Ws[e];
+  if (tid == 0) {
+    wtag[(gs & 1) * npair + blockIdx.x] = gs + 1;
+    atomicAdd(&cnt[sweep], 1);
+  }
 }
 
 __global__ void __launch_bounds__(64)
@@ -664,26 +727,36 @@ hipError_t launch_jacobi_wide(const double* M, int LPm, int l, int k, int max_sw
   double* Mc = reinterpret_cast<double*>(scratch);
   double* Vc = Mc + (size_t)ncp * d.ldc;
   double* sig = Vc + (size_t)ncp * d.ldc;
-  int* cnt = reinterpret_cast<int*>(sig + l);
+  const int npair = d.nbe / 2;
+  double* Wg = sig + l;
+  int* cnt = reinterpret_cast<int*>(Wg + (size_t)2 * npair * (2 * d.B) * (2 * d.B));
   const int* conv = cnt + max_sweeps;
+  int* wtag = cnt + kWideMaxSweeps + 64;
+  // row chunks of V per block pair: the V workgroups fill the CUs the
+  // npair block-pair workgroups leave (one workgroup per CU: the LDS of the
+  // block pairs is sized for one), chunks of at least 64 rows
+  const int vchunks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(d.ldc, 64), (256 - npair) / npair));
   const double tol2 = tol > 0.0 ? tol * tol : (double)l * 0x1p-104;
   DevInfo* di = (DevInfo*)info;
   const int64_t tot = (int64_t)ncp * d.ldc;
   hipLaunchKernelGGL(k_wjac_init, dim3((unsigned)std::min<int64_t>(1024, ceil_div(tot, 256))), dim3(256), 0, st, M,
-                     LPm, l, trans ? 1 : 0, ncp, d.ldc, Mc, Vc, cnt, max_sweeps);
-  // columns, G, W, (c, s) per pair, and the per-wave partial Gram (B = 8)
-  const size_t shm = ((size_t)2 * d.B * d.ldc + 8 * d.B * d.B + 2 * d.B + (d.B == 8 ? 4 * 256 : 0)) * 8;
+                     LPm, l, trans ? 1 : 0, ncp, d.ldc, Mc, Vc, cnt, max_sweeps, wtag, 2 * npair);
+  // columns, G, W and the per-wave partial Gram (B = 8)
+  const size_t shm = ((size_t)2 * d.B * d.ldc + 8 * d.B * d.B + (d.B == 8 ? 4 * 256 : 0)) * 8;
+  auto step = [&](int xparts, int t, int sw) {
+    const dim3 grid((unsigned)(xparts + npair * vchunks));
+    if (d.B == 16)
+      hipLaunchKernelGGL(k_wjac_step<16>, grid, dim3(256), shm, st, Mc, Vc, d.ldc, l, d.nbe, t, sw, cnt, conv, tol2,
+                         Wg, wtag, xparts, vchunks);
+    else
+      hipLaunchKernelGGL(k_wjac_step<8>, grid, dim3(256), shm, st, Mc, Vc, d.ldc, l, d.nbe, t, sw, cnt, conv, tol2,
+                         Wg, wtag, xparts, vchunks);
+  };
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    for (int t = 0; t < d.nbe - 1; ++t) {
-      if (d.B == 16)
-        hipLaunchKernelGGL(k_wjac_step<16>, dim3((unsigned)(d.nbe / 2)), dim3(256), shm, st, Mc, Vc, d.ldc, l, d.nbe,
-                           t, sw, cnt, conv, tol2);
-      else
-        hipLaunchKernelGGL(k_wjac_step<8>, dim3((unsigned)(d.nbe / 2)), dim3(256), shm, st, Mc, Vc, d.ldc, l, d.nbe,
-                           t, sw, cnt, conv, tol2);
-    }
+    for (int t = 0; t < d.nbe - 1; ++t) step(npair, t, sw);
     hipLaunchKernelGGL(k_wjac_sweep_end, dim3(1), dim3(64), 0, st, cnt, sw, max_sweeps, di);
   }
+  step(0, 0, max_sweeps);  // V by the W of the last step
   hipLaunchKernelGGL(k_wjac_norms, dim3((unsigned)l), dim3(256), 0, st, Mc, d.ldc, l, sig);
   hipLaunchKernelGGL(k_wjac_out, dim3((unsigned)l), dim3(256), 0, st, Mc, Vc, d.ldc, l, k, sig, Ut, sv, Vt, ldk);
   return hipGetLastError();
