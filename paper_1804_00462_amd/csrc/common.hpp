@@ -59,6 +59,13 @@ __device__ inline uint4 load_stream16(const void* p) {
 }
 
 // Sum over a full wavefront (64 lanes); every lane gets the total.
+// v of lane `lane` (uniform), through two scalar reads.
+__device__ inline double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);

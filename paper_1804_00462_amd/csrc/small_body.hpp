@@ -45,166 +45,202 @@ struct DevInfo {  // mirrors sorsvd_info
 // eliminates nothing and its column of R^{-1} is zero (flag bit 2).
 
 // LDL^T elimination of the l x l SPD matrix G (+ shift on the diagonal),
-// carrying W = L^{-1} (unit lower triangular) in the strict lower part of each
-// row: step j subtracts f_a = S[j][a] / S[j][j] times row j from every row
-// a > j, on the trailing upper part (columns >= a) and on W's columns 0..j.
-// The pivots d_j stay on the diagonal. Then R = D^{1/2} L^T and
-// R^{-1} = L^{-T} D^{-1/2} = W^T D^{-1/2}.
+// carrying W = L^{-1} (unit lower triangular): step j subtracts
+// f_a = S[j][a] / S[j][j] times row j from every row a > j, on the trailing
+// upper part (columns >= a) and on W's columns 0..j. Row a holds W[a][c] for
+// c < a and S[a][c] for c >= a (the pivots d_a on the diagonal). Then
+// R = D^{1/2} L^T and R^{-1} = L^{-T} D^{-1/2} = W^T D^{-1/2}.
 //
-// Dataflow form: wave w holds rows a = w + 16 i in registers (lane holds
-// columns lane and lane + 64) and finishes them in increasing order, each by
-// applying the steps j < a in order from the published rows j (left-looking:
-// the same operations in the same order as the row-by-row elimination). A
-// finished row is published to LDS with 1 in place of its pivot d_a (the
-// unit diagonal of W, which is what the later steps subtract) and with
-// 1/d_a beside it, and a counter of published
-// rows is raised; rows finish in index order, so the chain costs one step and
-// one hand-off per row instead of a workgroup barrier per step. Every wait is
-// bounded: after ~1e6 polls a wave stops waiting and the result is flagged as
-// a breakdown.
-constexpr int kCholWaves = kSmallThreads / 64;
-constexpr int kCholRowsPerWave = (128 + kCholWaves - 1) / kCholWaves;  // l <= 128
+// Blocked in panels of 16 rows over X, the matrix padded to lp = 16
+// ceil(l / 16) with the identity (its pivots are 1 and it meets no other
+// row). Per panel J = [j0, j0 + 16), with M[j][a] = S[j][a] / d_j taken from
+// the final row j (the trailing matrix is symmetric, so the multiplier of
+// row a at step j is row j's entry at column a):
+//   1. wave 0 runs the 16 steps on the 16 x 16 diagonal block (each lane
+//      holds a 2 x 2 tile of it; the pivot is read from its lane, the
+//      multipliers and the row subtracted come by lane shuffles; no
+//      barrier);
+//   2. every other column c of the panel rows receives the same steps: they
+//      act on the rows J as left multiplication by L11^{-1}, which is the
+//      W part of the diagonal block after step 1 (row j's entry at c is S
+//      for c >= j0 + 16 and W for c < j0), so X[J][c] <- W11 X[J][c] on
+//      FP64 MFMA;
+//   3. the rows below the panel receive all 16 steps at once on FP64 MFMA:
+//      X[a][c] -= sum_j M[j][a] Y[j][c] over 16 x 16 tiles, where Y[j] is
+//      row j with its W part taken as W[j][c] (c < j), 1 (c = j), 0 (j < c
+//      < j0 + 16); only the S part (c >= a) and the W part (c < j0 + 16) of
+//      a row are written (its entries j0 + 16 <= c < a are W entries of
+//      later panels, still zero).
+// The pivots are checked against 1e-13 of G's diagonal after the factor
+// (check), or a pivot that is not positive is dropped at its step (after
+// the shift).
+constexpr int kCholP = 16;  // panel height
+__host__ __device__ inline int chol_lp(int l) { return (l + kCholP - 1) & ~(kCholP - 1); }
+__host__ __device__ inline int chol_ldx(int l) { return chol_lp(l) + 8; }  // LDS row stride (bank spread)
 
-struct CholRows {
-  double v[kCholRowsPerWave][2];
-};
-
-__device__ inline double chol_gval(const double* __restrict__ G, int nparts, int64_t pstride, int LP, int r,
-                                   int c) {
-  double v = 0.0;
-  for (int p = 0; p < nparts; ++p) v += G[p * pstride + r * LP + c];
-  return v;
-}
-
-// check: a pivot below 1e-13 of the original diagonal sets *retry (every
-// wave finishes its rows regardless, so that no wait is left open). Pub: LDS
-// of l * l doubles; pinv: l doubles; *nready and *retry zero on entry.
-__device__ inline void ldl_flow(const double* __restrict__ G, int nparts, int64_t pstride, int LP, int l,
-                                double shift, const double* d0, bool check, double* Pub, double* pinv,
-                                int* nready, int* retry, DevInfo* info, CholRows& R) {
-  // (the wave index through readfirstlane: known uniform, so that row and
-  // step bounds live in scalar registers and the loops are not divergent)
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
-  bool bail = false;
-  int known = 0;  // rows known to be published
-  // this wave's rows of G (upper part), the parts added in order: all loads of
-  // a part are issued before the first is used (entries outside the upper
-  // part read a valid address and are dropped)
+// X (lp x ldx), dinv (lp), d0 (lp: G's diagonal, 1 on the padding; written
+// here when fill_d0), *retry zero on entry.
+constexpr int kCholLoad = 8;  // entries of X per thread and batch of loads
+__device__ __forceinline__ void ldl_blocked(const double* __restrict__ G, int nparts, int64_t pstride, int LP,
+                                            int l, double shift, double* __restrict__ d0, bool fill_d0, bool check,
+                                            double* X, double* dinv, int* retry, DevInfo* info) {
+  const int lp = chol_lp(l), ldx = chol_ldx(l), nt = lp / kCholP;
+  const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+  // X: G's upper part (+ shift), zero below, the identity on the padding; the
+  // parts are added in order, the loads of a batch of kCholLoad entries per
+  // thread issued before any is used (entries outside the upper part read a
+  // valid address and are dropped)
+  for (int e0 = 0; e0 < lp * lp; e0 += kSmallThreads * kCholLoad) {
+    double v[kCholLoad];
+    int off[kCholLoad];
 #pragma unroll
-  for (int i = 0; i < kCholRowsPerWave; ++i)
+    for (int i = 0; i < kCholLoad; ++i) {
+      const int e = e0 + tid + kSmallThreads * i, a = e / lp, c = e % lp;
+      const bool in = e < lp * lp && a < l && c < l && c >= a;
+      off[i] = in ? a * LP + c : 0;
+      v[i] = G[off[i]];
+    }
+    for (int p = 1; p < nparts; ++p)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) R.v[i][h] = 0.0;
-  for (int p = 0; p < nparts; ++p) {
-    double gv[kCholRowsPerWave][2];
+      for (int i = 0; i < kCholLoad; ++i) v[i] += G[p * pstride + off[i]];
 #pragma unroll
-    for (int i = 0; i < kCholRowsPerWave; ++i)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int a = w + kCholWaves * i, c = lane + 64 * h;
+    for (int i = 0; i < kCholLoad; ++i) {
+      const int e = e0 + tid + kSmallThreads * i, a = e / lp, c = e % lp;
+      if (e < lp * lp) {
         const bool in = a < l && c < l && c >= a;
-        gv[i][h] = G[p * pstride + (in ? a * LP + c : 0)];
+        if (fill_d0 && a == c) d0[a] = in ? v[i] : 1.0;
+        X[a * ldx + c] = in ? v[i] + (a == c ? shift : 0.0) : (a == c ? 1.0 : 0.0);
       }
-#pragma unroll
-    for (int i = 0; i < kCholRowsPerWave; ++i)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int a = w + kCholWaves * i, c = lane + 64 * h;
-        if (a < l && c < l && c >= a) R.v[i][h] += gv[i][h];
-      }
-  }
-#pragma unroll
-  for (int i = 0; i < kCholRowsPerWave; ++i)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int a = w + kCholWaves * i;
-      if (a < l && lane + 64 * h == a) R.v[i][h] += shift;
-    }
-#pragma unroll
-  for (int i = 0; i < kCholRowsPerWave; ++i) {
-    const int a = w + kCholWaves * i;
-    if (a < l) {
-    // steps j < a in chunks of published rows: the multipliers f_j of a chunk
-    // (at most 64) are read at once, one per lane, and broadcast from there
-    bool ge_a[2];
-    int cc[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      ge_a[h] = lane + 64 * h >= a;
-      cc[h] = min(lane + 64 * h, l - 1);  // clamped column: loads stay in row t
-    }
-    int j = 0;
-    while (j < a) {
-      if (j >= known) {
-        int spins = 0;
-        while (!bail) {
-          known = __builtin_amdgcn_readfirstlane(
-              __hip_atomic_load(nready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
-          if (known > j) break;
-          if (spins > 64) __builtin_amdgcn_s_sleep(1);  // poll tightly for a while first
-          if (++spins > (1 << 20)) bail = true;
-        }
-        if (bail) known = a;
-      }
-      const int jend = min(min(known, a), j + 64);
-      const int jl = j + lane;
-      const double fv = jl < jend ? Pub[jl * l + a] * pinv[jl] : 0.0;
-      const int flo = __double2loint(fv), fhi = __double2hiint(fv);
-      // published row t holds W[t][c] (c < t), 1 (c = t), S[t][c] (c > t):
-      // lane c < a takes it for c <= t, lane c >= a always. Loads and FMAs
-      // are unconditional with the mask on the multiplier (v - 0 p = v), and
-      // the loads of four steps are issued before their FMAs.
-      double v0 = R.v[i][0], v1 = R.v[i][1];
-      int t = j;
-      for (; t + 4 <= jend; t += 4) {
-        double p0[4], p1[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          p0[u] = Pub[(t + u) * l + cc[0]];
-          p1[u] = Pub[(t + u) * l + cc[1]];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double f = __hiloint2double(__builtin_amdgcn_readlane(fhi, t + u - j),
-                                            __builtin_amdgcn_readlane(flo, t + u - j));
-          v0 = fma(-((lane <= t + u || ge_a[0]) ? f : 0.0), p0[u], v0);
-          v1 = fma(-((lane + 64 <= t + u || ge_a[1]) ? f : 0.0), p1[u], v1);
-        }
-      }
-      for (; t < jend; ++t) {
-        const double f = __hiloint2double(__builtin_amdgcn_readlane(fhi, t - j), __builtin_amdgcn_readlane(flo, t - j));
-        v0 = fma(-((lane <= t || ge_a[0]) ? f : 0.0), Pub[t * l + cc[0]], v0);
-        v1 = fma(-((lane + 64 <= t || ge_a[1]) ? f : 0.0), Pub[t * l + cc[1]], v1);
-      }
-      R.v[i][0] = v0;
-      R.v[i][1] = v1;
-      j = jend;
-    }
-    // row a is final: its pivot, then publish
-    const double dsrc = a < 64 ? R.v[i][0] : R.v[i][1];
-    const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(dsrc), a % 64),
-                                      __builtin_amdgcn_readlane(__double2loint(dsrc), a % 64));
-    double dinv = 1.0 / d;
-    if (check) {
-      if (!(d > 1e-13 * d0[a]) && lane == 0) *retry = 1;
-    } else if (!(d > 0.0)) {  // not positive after the shift (or NaN): drop column a
-      if (lane == 0) atomicOr(&info->flags, kFlagQrBreakdown);
-      dinv = 0.0;
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int c = lane + 64 * h;
-      if (c < l) Pub[a * l + c] = c == a ? 1.0 : R.v[i][h];
-    }
-    if (lane == 0) pinv[a] = dinv;
-    __hip_atomic_store(nready, a + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
-  if (bail && lane == 0) atomicOr(&info->flags, kFlagQrBreakdown);
+  __syncthreads();
+  for (int k = 0; k < nt; ++k) {
+    const int j0 = kCholP * k, j1 = j0 + kCholP;
+    // 1. the diagonal block, wave 0: lane (r2, c2) = (lane / 8, lane % 8)
+    // holds rows j0 + 2 r2 + {0, 1}, columns j0 + 2 c2 + {0, 1}
+    if (w == 0) {
+      const int r2 = lane / 8, c2 = lane % 8;
+      double x[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) x[a][b] = X[(j0 + 2 * r2 + a) * ldx + j0 + 2 * c2 + b];
+      double mydi = 0.0;  // lane j: 1 / d of step j
+#pragma unroll
+      for (int j = 0; j < kCholP; ++j) {
+        const int jr = j / 2, jb = j % 2;
+        const double d = readlane_f64(x[jb][jb], 8 * jr + jr);
+        // 1 / d: the hardware estimate and two Newton steps (a pivot that is
+        // not positive is checked after the factor, or dropped here)
+        double di = __builtin_amdgcn_rcp(d);
+        di = fma(di, fma(-d, di, 1.0), di);
+        di = fma(di, fma(-d, di, 1.0), di);
+        if (!check && !(d > 0.0)) {  // not positive after the shift (or NaN): drop column j0 + j
+          if (lane == 0) atomicOr(&info->flags, kFlagQrBreakdown);
+          di = 0.0;
+        }
+        if (lane == j) mydi = di;
+        // row j at my rows' columns (the multipliers: S[j][i] = S[i][j]) and
+        // at my columns (the row subtracted)
+        double f[2], rj[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          f[a] = __shfl(x[jb][a], 8 * jr + r2, kWave) * di;
+          rj[a] = __shfl(x[jb][a], 8 * jr + c2, kWave);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int i = 2 * r2 + a;
+          if (i > j) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              const int c = 2 * c2 + b;
+              const double y = (c >= i || c < j) ? rj[b] : (c == j ? 1.0 : 0.0);
+              x[a][b] = fma(-f[a], y, x[a][b]);
+            }
+          }
+        }
+      }
+      if (lane < kCholP) dinv[j0 + lane] = mydi;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) X[(j0 + 2 * r2 + a) * ldx + j0 + 2 * c2 + b] = x[a][b];
+    }
+    __syncthreads();
+    const int li = lane % 16, g = lane / 16;
+    // 2. the other columns of the panel rows receive the panel's steps: the
+    // steps on rows J are left multiplication by W11 = L11^{-1}, the W part
+    // of the diagonal block (unit diagonal), so X[J][c] <- W11 X[J][c], one
+    // 16-column tile per wave on FP64 MFMA
+    for (int it = w; it < nt - 1; it += kSmallThreads / kWave) {
+      const int c0 = kCholP * (it < k ? it : it + 1);
+      double bv[4], av[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = 4 * s + g;
+        bv[s] = X[(j0 + kk) * ldx + c0 + li];
+        av[s] = li > kk ? X[(j0 + li) * ldx + j0 + kk] : (li == kk ? 1.0 : 0.0);  // W11[li][kk]
+      }
+      f64x4 acc = f64x4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) X[(j0 + 4 * r4 + g) * ldx + c0 + li] = acc[r4];
+    }
+    __syncthreads();
+    if (k == nt - 1) break;
+    // 3. the rows below the panel: tiles (ta, tc), ta > k, tc <= k (W part)
+    // or tc >= ta (S part), dealt round-robin to the waves; a tile's loads
+    // are all issued before its products
+    {
+      int ntile = 0;
+      for (int ta = k + 1; ta < nt; ++ta) ntile += (k + 1) + (nt - ta);
+      for (int it = w; it < ntile; it += kSmallThreads / kWave) {
+        int ta = k + 1, rem = it;
+        for (;;) {
+          const int n = (k + 1) + (nt - ta);
+          if (rem < n) break;
+          rem -= n;
+          ++ta;
+        }
+        const int tc = rem <= k ? rem : ta + (rem - (k + 1));
+        const int a0 = kCholP * ta, c0 = kCholP * tc, c = c0 + li;
+        f64x4 acc;
+        double am[4], bm[4];
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) acc[r4] = X[(a0 + 4 * r4 + g) * ldx + c];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int j = j0 + 4 * s + g;
+          am[s] = -X[j * ldx + a0 + li] * dinv[j];  // -M[j][a0 + li]
+          const double xb = X[j * ldx + c];
+          bm[s] = (tc < k || c < j || c >= j1) ? xb : (c == j ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(am[s], bm[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int a = a0 + 4 * r4 + g;
+          if (c < j1 || c >= a) X[a * ldx + c] = acc[r4];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // the unshifted factor: every pivot (the final diagonal) against 1e-13 of
+  // G's diagonal
+  if (check)
+    for (int j = tid; j < l; j += kSmallThreads)
+      if (!(X[j * ldx + j] > 1e-13 * d0[j])) *retry = 1;
+  __syncthreads();
 }
 
-// LDS of the Cholesky body: published rows, 1/d, the diagonal of G, and two
-// counters.
-__host__ __device__ inline size_t chol_lds(int l) { return ((size_t)l * l + 2 * l) * 8 + 16; }
+// LDS of the Cholesky body: X, 1/d, the diagonal of G and the retry word.
+__host__ __device__ inline size_t chol_lds(int l) {
+  const size_t lp = chol_lp(l);
+  return (lp * chol_ldx(l) + 2 * lp) * 8 + 16;
+}
 
 // G is given as nparts partial sums (stride pstride elements), added here in
 // order; sm: LDS of chol_lds(l) bytes.
@@ -212,51 +248,41 @@ __device__ inline void chol_inv_body(const double* __restrict__ G, int nparts, i
                                      int l, int64_t rows, int mode, double* __restrict__ Rinv,
                                      int* __restrict__ skip3, DevInfo* __restrict__ info, double* sm) {
   if (mode == 2 && *skip3) return;
-  double* Pub = sm;             // l x l: published final rows
-  double* pinv = sm + l * l;    // l: 1 / d
-  double* d0 = pinv + l;        // l: diagonal of G
-  int* nready = reinterpret_cast<int*>(d0 + l);
-  int* retry = nready + 1;
+  const int lp = chol_lp(l), ldx = chol_ldx(l);
+  double* X = sm;                        // lp x ldx
+  double* dinv = X + (size_t)lp * ldx;   // lp: 1 / d (0: dropped)
+  double* d0 = dinv + lp;                // lp: diagonal of G
+  int* retry = reinterpret_cast<int*>(d0 + lp);
   const int tid = threadIdx.x;
-  for (int i = tid; i < l; i += kSmallThreads) d0[i] = chol_gval(G, nparts, pstride, LP, i, i);
-  if (tid == 0) { *nready = 0; *retry = 0; }
+  if (tid == 0) *retry = 0;
   __syncthreads();
-  CholRows R;
-  ldl_flow(G, nparts, pstride, LP, l, 0.0, d0, true, Pub, pinv, nready, retry, info, R);
-  __syncthreads();
+  ldl_blocked(G, nparts, pstride, LP, l, 0.0, d0, true, true, X, dinv, retry, info);
   bool shifted = false;
   if (*retry) {
     double tr = 0.0;
     for (int i = 0; i < l; ++i) tr += d0[i];
     const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 0x1p-53 * tr;
     __syncthreads();
-    if (tid == 0) *nready = 0;
-    __syncthreads();
-    ldl_flow(G, nparts, pstride, LP, l, shift, d0, false, Pub, pinv, nready, retry, info, R);
+    ldl_blocked(G, nparts, pstride, LP, l, shift, d0, false, false, X, dinv, retry, info);
     shifted = true;
   }
   if (tid == 0) {
     if (shifted) *skip3 = 0;
     else if (mode == 0) *skip3 = 1;
   }
-  // R^{-1}[r][c] = W[c][r] / sqrt(d_c) for r < c, 1 / sqrt(d_c) on the diagonal;
-  // a dropped column (d_c not positive) is zero. Zeros first, then each wave
-  // writes the columns of its rows.
-  for (int i = tid; i < LP * LP; i += kSmallThreads) Rinv[i] = 0.0;
+  // R^{-1}[r][c] = W[c][r] / sqrt(d_c) for r < c, 1 / sqrt(d_c) on the
+  // diagonal, zero below and outside l; a dropped column (d_c not positive)
+  // is zero. 1 / sqrt(d_c) first (into dinv, no longer needed).
+  for (int c = tid; c < lp; c += kSmallThreads) {
+    const double dc = X[c * ldx + c];
+    dinv[c] = dc > 0.0 ? 1.0 / sqrt(dc) : 0.0;
+  }
   __syncthreads();
-  const int w = tid / 64, lane = tid % 64;
-#pragma unroll
-  for (int i = 0; i < kCholRowsPerWave; ++i) {
-    const int c = w + kCholWaves * i;  // row c of the factor = column c of R^{-1}
-    if (c >= l) continue;
-    const double dc = __shfl(c < 64 ? R.v[i][0] : R.v[i][1], c % 64, kWave);
-    const double isd = dc > 0.0 ? 1.0 / sqrt(dc) : 0.0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int r = lane + 64 * h;
-      if (r < c) Rinv[r * LP + c] = R.v[i][h] * isd;
-      else if (r == c) Rinv[r * LP + c] = isd;
-    }
+  for (int e = tid; e < LP * LP; e += kSmallThreads) {
+    const int r = e / LP, c = e % LP;
+    double v = 0.0;
+    if (r <= c && c < l) v = r == c ? dinv[c] : X[c * ldx + r] * dinv[c];
+    Rinv[e] = v;
   }
 }
 

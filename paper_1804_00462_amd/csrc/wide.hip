@@ -25,12 +25,6 @@ __device__ inline bool gate_off(const int* skip, const int* need) {
   return (skip && *skip) || (need && !*need);
 }
 
-__device__ inline double readlane_f64(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-
 // A 64 x 64 block (rows r0.., columns c0..) of an LP x LP matrix into LDS
 // (row stride kWLd), zero outside the buffer.
 __device__ inline void load_block64(const double* __restrict__ M, int LP, int r0, int c0, double* S) {
