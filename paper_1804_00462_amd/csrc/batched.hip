@@ -263,10 +263,11 @@ __global__ void __launch_bounds__(256) k_bcast(const BProb* __restrict__ probs, 
     Xc[i] = TA(Q[i]);
 }
 
-__global__ void __launch_bounds__(kSmallThreads) k_bchol(const BProb* __restrict__ probs, int which, int mode,
+__global__ void __launch_bounds__(kSmallThreads) k_bchol(const BProb* __restrict__ probs,
+                                                         const int32_t* __restrict__ order, int which, int mode,
                                                          int qiter) {
   extern __shared__ double sm[];
-  const BProb& P = probs[blockIdx.x];
+  const BProb& P = probs[order[blockIdx.x]];
   if (qiter >= 0 && qiter >= P.q) return;
   const int nparts = which == 2 ? P.gch_n : P.gch_m;
   const int64_t rows = which == 2 ? P.n : P.m;
@@ -276,9 +277,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_bchol(const BProb* __restrict
 
 // One workgroup per problem; the row-block count follows the problem's l.
 template <bool V_LDS>
-__global__ void __launch_bounds__(kJacThreads) k_bjacobi(const BProb* __restrict__ probs, int max_sweeps) {
+__global__ void __launch_bounds__(kJacThreads) k_bjacobi(const BProb* __restrict__ probs,
+                                                          const int32_t* __restrict__ order, int max_sweeps) {
   extern __shared__ double sm[];
-  const BProb& P = probs[blockIdx.x];
+  const BProb& P = probs[order[blockIdx.x]];
   const double tol2 = (double)P.l * 0x1p-104;
 #define SOR_BJAC(R)                                                                                          \
   case R:                                                                                                    \
@@ -412,9 +414,25 @@ struct sorsvd_batch {
   // work lists [mode][rt - 1][CT - 1]; rt only varies for passes over A; CT = LP / 16
   // (KP / 16 for the lifts): one launch per non-empty list
   std::vector<BItem> items[M_COUNT][2][8];
-  size_t off_table = 0, off_omega = 0, off_items[M_COUNT][2][8] = {}, total = 0;
+  // problems by descending l (the cost of the one-workgroup steps grows as
+  // l^3): workgroup i of those launches takes problem order[i], so that the
+  // largest start first
+  std::vector<int32_t> order;
+  size_t off_table = 0, off_omega = 0, off_order = 0, off_items[M_COUNT][2][8] = {}, total = 0;
   Cfg cfg[3];                            // passes: sketch, orbit, projection
   bool uploaded = false;
+  // side streams of the CT groups of a step and their fork / join events
+  // (made at the first run, on the device current then)
+  mutable hipStream_t aux[8] = {};
+  mutable hipEvent_t ev_fork = nullptr, ev_join[8] = {};
+  mutable bool forked = false;
+  ~sorsvd_batch() {
+    for (int c = 0; c < 8; ++c) {
+      if (aux[c]) hipStreamDestroy(aux[c]);
+      if (ev_join[c]) hipEventDestroy(ev_join[c]);
+    }
+    if (ev_fork) hipEventDestroy(ev_fork);
+  }
 };
 
 namespace {
@@ -486,18 +504,67 @@ const BItem* dev_items(const sorsvd_batch* b, void* ws, int mode, int r, int c) 
   return reinterpret_cast<const BItem*>((char*)ws + b->off_items[mode][r][c]);
 }
 
+// The launches of the CT groups of one step are independent (disjoint
+// problems): the first non-empty group runs on the call's stream, the others
+// on side streams forked from it and joined back before the step ends, so
+// that their tails overlap. Under stream capture this records a fork / join
+// of graph nodes. Per problem the arithmetic is the same as on one stream.
+struct GroupFork {
+  const sorsvd_batch* b;
+  hipStream_t st;
+  int ngroups = 0, used = 0;
+  bool joined[8] = {};
+  hipError_t err = hipSuccess;
+  GroupFork(const sorsvd_batch* bb, hipStream_t s, int ng) : b(bb), st(s), ngroups(ng) {
+    if (ngroups > 1) err = hipEventRecord(b->ev_fork, st);
+  }
+  hipStream_t stream(int ci) {
+    if (ngroups <= 1 || used++ == 0) return st;
+    if (err == hipSuccess) err = hipStreamWaitEvent(b->aux[ci], b->ev_fork, 0);
+    joined[ci] = true;
+    return b->aux[ci];
+  }
+  hipError_t join() {
+    for (int c = 0; c < 8 && err == hipSuccess; ++c)
+      if (joined[c]) {
+        err = hipEventRecord(b->ev_join[c], b->aux[c]);
+        if (err == hipSuccess) err = hipStreamWaitEvent(st, b->ev_join[c], 0);
+      }
+    return err;
+  }
+};
+
+int nonempty_groups(const sorsvd_batch* b, int mode, int r) {
+  int n = 0;
+  for (int ci = 0; ci < 8; ++ci) n += b->items[mode][r][ci].empty() ? 0 : 1;
+  return n;
+}
+
+hipError_t make_fork_streams(const sorsvd_batch* b) {
+  if (b->forked) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  for (int c = 0; c < 8 && e == hipSuccess; ++c) {
+    e = hipStreamCreateWithFlags(&b->aux[c], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) b->forked = true;
+  return e;
+}
+
 // One pass over A of every problem (one launch per CT group). timed: bracket
 // the launches with the library's pass-timing events (when timing is on).
 template <typename TA>
 int launch_pass(const sorsvd_batch* b, void* ws, int mode, int qiter, const Cfg& c, bool timed, hipStream_t st) {
   if (b->a_type == SORSVD_DIAG) {  // A = diag(sigma): one element-wise launch per LP group
+    GroupFork fk(b, st, nonempty_groups(b, mode, 0));
     for (int ci = 0; ci < 8; ++ci) {
       const int n = (int)b->items[mode][0][ci].size();
       if (n == 0) continue;
-      hipLaunchKernelGGL(k_bdiag, dim3((unsigned)std::min(2048, n)), dim3(256), 0, st, dev_table(b, ws),
+      hipLaunchKernelGGL(k_bdiag, dim3((unsigned)std::min(2048, n)), dim3(256), 0, fk.stream(ci), dev_table(b, ws),
                          dev_items(b, ws, mode, 0, ci), n, mode, qiter, (mode == M_SKETCH && qiter < 0) ? 1 : 0);
       SORSVD_TRY(hipGetLastError());
     }
+    SORSVD_TRY(fk.join());
     return SORSVD_OK;
   }
   // FP64 tiles are 64 rows only (128-row FP64 tiles do not fit the registers)
@@ -514,6 +581,7 @@ int launch_pass(const sorsvd_batch* b, void* ws, int mode, int qiter, const Cfg&
       }
     e1 = pass_timer_begin(st, bytes, flops);
   }
+  GroupFork fk(b, st, nonempty_groups(b, mode, r));
   for (int ci = 0; ci < 8; ++ci) {
     const int n = (int)b->items[mode][r][ci].size();
     if (n == 0) continue;
@@ -521,21 +589,22 @@ int launch_pass(const sorsvd_batch* b, void* ws, int mode, int qiter, const Cfg&
     const BItem* it = dev_items(b, ws, mode, r, ci);
     const BProb* probs = dev_table(b, ws);
     const bool tn = mode == M_ORBIT;
+    const hipStream_t gs = fk.stream(ci);
     switch ((ci + 1) * 4 + (tn ? 2 : 0) + (rt - 1)) {
 #define SORSVD_LP(C)                                                                                          \
   case C * 4 + 0:                                                                                             \
-    hipLaunchKernelGGL((k_bpass<TA, false, 1, C>), grid, dim3(256), (tile_lds<TA, C>()), st, probs, it, n, mode, qiter,   \
+    hipLaunchKernelGGL((k_bpass<TA, false, 1, C>), grid, dim3(256), (tile_lds<TA, C>()), gs, probs, it, n, mode, qiter,   \
                        want_norm);                                                                            \
     break;                                                                                                    \
   case C * 4 + 1:                                                                                             \
-    hipLaunchKernelGGL((k_bpass<TA, false, sizeof(TA) == 8 ? 1 : 2, C>), grid, dim3(256), (tile_lds<TA, C>()), st, probs, \
+    hipLaunchKernelGGL((k_bpass<TA, false, sizeof(TA) == 8 ? 1 : 2, C>), grid, dim3(256), (tile_lds<TA, C>()), gs, probs, \
                        it, n, mode, qiter, want_norm);                                                        \
     break;                                                                                                    \
   case C * 4 + 2:                                                                                             \
-    hipLaunchKernelGGL((k_bpass<TA, true, 1, C>), grid, dim3(256), (tile_lds<TA, C>()), st, probs, it, n, mode, qiter, 0); \
+    hipLaunchKernelGGL((k_bpass<TA, true, 1, C>), grid, dim3(256), (tile_lds<TA, C>()), gs, probs, it, n, mode, qiter, 0); \
     break;                                                                                                    \
   case C * 4 + 3:                                                                                             \
-    hipLaunchKernelGGL((k_bpass<TA, true, sizeof(TA) == 8 ? 1 : 2, C>), grid, dim3(256), (tile_lds<TA, C>()), st, probs,  \
+    hipLaunchKernelGGL((k_bpass<TA, true, sizeof(TA) == 8 ? 1 : 2, C>), grid, dim3(256), (tile_lds<TA, C>()), gs, probs,  \
                        it, n, mode, qiter, 0);                                                                \
     break;
       SORSVD_CT_CASES(SORSVD_LP)
@@ -543,6 +612,7 @@ int launch_pass(const sorsvd_batch* b, void* ws, int mode, int qiter, const Cfg&
     }
     SORSVD_TRY(hipGetLastError());
   }
+  SORSVD_TRY(fk.join());
   if (e1) SORSVD_TRY(hipEventRecord(e1, st));
   return SORSVD_OK;
 }
@@ -550,16 +620,18 @@ int launch_pass(const sorsvd_batch* b, void* ws, int mode, int qiter, const Cfg&
 // mode: M_GRAM1 / M_GRAM2 / M_PGRAM, M_APPLY1 / M_APPLY2, M_LIFTU / M_LIFTV.
 int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int step, hipStream_t st) {
   const BProb* probs = dev_table(b, ws);
+  GroupFork fk(b, st, nonempty_groups(b, mode, 0));
   for (int ci = 0; ci < 8; ++ci) {
     const int n = (int)b->items[mode][0][ci].size();
     if (n == 0) continue;
+    const hipStream_t gs = fk.stream(ci);
     const dim3 grid((unsigned)std::min(2048, n));
     const BItem* it = dev_items(b, ws, mode, 0, ci);
     if (mode == M_GRAM1 || mode == M_GRAM2 || mode == M_PGRAM) {
       switch (ci + 1) {
 #define SORSVD_LP(C)                                                                                                \
   case C:                                                                                                           \
-    hipLaunchKernelGGL(k_bgram<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, mode, qiter, step);              \
+    hipLaunchKernelGGL(k_bgram<C>, grid, dim3(256), (tile_lds<double, C>()), gs, probs, it, n, mode, qiter, step);              \
     break;
         SORSVD_CT_CASES(SORSVD_LP)
 #undef SORSVD_LP
@@ -569,7 +641,7 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int step, h
       switch (ci + 1) {
 #define SORSVD_LP(C)                                                                                                \
   case C:                                                                                                           \
-    hipLaunchKernelGGL(k_bapply<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, which, qiter, step);            \
+    hipLaunchKernelGGL(k_bapply<C>, grid, dim3(256), (tile_lds<double, C>()), gs, probs, it, n, which, qiter, step);            \
     break;
         SORSVD_CT_CASES(SORSVD_LP)
 #undef SORSVD_LP
@@ -579,7 +651,7 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int step, h
       switch (ci + 1) {
 #define SORSVD_LP(C)                                                                                                \
   case C:                                                                                                           \
-    hipLaunchKernelGGL(k_blift<C>, grid, dim3(256), (tile_lds<double, C>()), st, probs, it, n, which);                           \
+    hipLaunchKernelGGL(k_blift<C>, grid, dim3(256), (tile_lds<double, C>()), gs, probs, it, n, which);                           \
     break;
         SORSVD_CT_CASES(SORSVD_LP)
 #undef SORSVD_LP
@@ -587,16 +659,19 @@ int launch_f64(const sorsvd_batch* b, void* ws, int mode, int qiter, int step, h
     }
     SORSVD_TRY(hipGetLastError());
   }
+  SORSVD_TRY(fk.join());
   return SORSVD_OK;
 }
 
 template <typename TA>
 int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
   const BProb* probs = dev_table(b, ws);
+  const int32_t* order = reinterpret_cast<const int32_t*>((char*)ws + b->off_order);
   const unsigned np = (unsigned)b->count;
   const dim3 g2((unsigned)std::max<int64_t>(1, (b->max_elems + kElemsPerBlock - 1) / kElemsPerBlock), np);
   const size_t chol_shm = chol_lds(b->max_l);
   int rc;
+  SORSVD_TRY(make_fork_streams(b));
 
   hipLaunchKernelGGL((k_bclear<TA>), g2, dim3(256), 0, st, probs);
   SORSVD_TRY(hipGetLastError());
@@ -611,7 +686,7 @@ int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
     for (int it = 0; it < 3; ++it) {
       int r;
       if ((r = launch_f64(b, ws, gmode, qiter, it, st))) return r;
-      hipLaunchKernelGGL(k_bchol, dim3(np), dim3(kSmallThreads), chol_shm, st, probs, which, it, qiter);
+      hipLaunchKernelGGL(k_bchol, dim3(np), dim3(kSmallThreads), chol_shm, st, probs, order, which, it, qiter);
       SORSVD_TRY(hipGetLastError());
       if ((r = launch_f64(b, ws, amode, qiter, it, st))) return r;
     }
@@ -648,9 +723,9 @@ int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
   bool v_lds = false;
   const size_t jshm = jacobi_lds(b->max_l, true, &v_lds);
   if (v_lds)
-    hipLaunchKernelGGL(k_bjacobi<true>, dim3(np), dim3(kJacThreads), jshm, st, probs, b->max_sweeps);
+    hipLaunchKernelGGL(k_bjacobi<true>, dim3(np), dim3(kJacThreads), jshm, st, probs, order, b->max_sweeps);
   else
-    hipLaunchKernelGGL(k_bjacobi<false>, dim3(np), dim3(kJacThreads), jshm, st, probs, b->max_sweeps);
+    hipLaunchKernelGGL(k_bjacobi<false>, dim3(np), dim3(kJacThreads), jshm, st, probs, order, b->max_sweeps);
   SORSVD_TRY(hipGetLastError());
   // lift (Alg. 3 step 7) and the sign convention
   if ((rc = launch_f64(b, ws, M_LIFTU, -1, 0, st))) return rc;
@@ -773,11 +848,17 @@ int sorsvd_batch_create(int32_t count, const sorsvd_problem* probs, int32_t a_ty
     b->max_omega = std::max<int64_t>(b->max_omega, u.n * l);
   }
   build_items(b);
+  b->order.resize(count);
+  for (int i = 0; i < count; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int32_t x, int32_t y) { return b->probs[x].l > b->probs[y].l; });
   size_t off = 0;
   b->off_table = off;
   off += align256(sizeof(BProb) * count);
   b->off_omega = off;
   off += align256(sizeof(OmegaJob) * count);
+  b->off_order = off;
+  off += align256(sizeof(int32_t) * count);
   for (int mode = 0; mode < M_COUNT; ++mode)
     for (int r = 0; r < 2; ++r)
       for (int c = 0; c < 8; ++c) {
@@ -842,6 +923,8 @@ int sorsvd_batch_upload(sorsvd_batch* b, void* ws, size_t ws_bytes, void* stream
   SORSVD_TRY(hipMemcpyAsync(base + b->off_table, b->probs.data(), sizeof(BProb) * b->count,
                             hipMemcpyHostToDevice, st));
   SORSVD_TRY(hipMemcpyAsync(base + b->off_omega, b->omega.data(), sizeof(OmegaJob) * b->count,
+                            hipMemcpyHostToDevice, st));
+  SORSVD_TRY(hipMemcpyAsync(base + b->off_order, b->order.data(), sizeof(int32_t) * b->count,
                             hipMemcpyHostToDevice, st));
   for (int mode = 0; mode < M_COUNT; ++mode)
     for (int r = 0; r < 2; ++r)
