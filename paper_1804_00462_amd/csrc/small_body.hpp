@@ -299,11 +299,14 @@ __device__ inline void chol_inv_body(const double* __restrict__ G, int nparts, i
 // Then sigma_j = |m_j|, U~_j = m_j / sigma_j, V~_j = v_j, sorted descending;
 // the first k are written (Ut, and Vt if WANT_V: l x k, ld ldk; s: k).
 //
-// One workgroup of kJacThreads. Each pair is handled by a group of 8 lanes;
-// lane g of a group holds rows g, g + 8, ... of the two columns in registers
-// for the step (NRB of them, a compile-time row-block count), and the three
-// dot products are reduced with DPP. The step cost is VALU issue on one CU,
-// so the layout avoids per-row masks: M lives in LDS column-major with its
+// One workgroup of kJacThreads. Each pair is handled by a group of GL lanes
+// (16 for widths 33 .. 64, else 8: the pairs of a step then fill two waves
+// per SIMD, which hide each other's latency; at widths above 64 groups of 8
+// already do, and groups of 4 (one wave per SIMD) are slower); lane g of a
+// group holds rows g, g + GL, ... of the two columns in registers for the
+// step (8 NRB / GL of them, NRB a compile-time row-block count), and the
+// three dot products are reduced with DPP. The step cost is VALU issue on one
+// CU, so the layout avoids per-row masks: M lives in LDS column-major with its
 // columns padded with zero rows to ldm = 8 NRB (rotations keep them zero).
 // V, when wanted, lives in LDS when it fits: column stride ldm, or, where
 // only the unpadded form fits, stride l followed by one dummy word that takes
@@ -380,9 +383,11 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
   // singular values: after M (and V) in LDS, or in the unused global scratch
   double* sig = V_LDS ? Vg : sm + (size_t)l * ldm;
   __shared__ int s_rot;
+  constexpr int GL = (NRB == 6 || NRB == 8) ? 16 : 8;  // lanes per pair
+  constexpr int RPL = ldm / GL;                         // rows per lane
   const int tid = threadIdx.x;
-  const int grp = tid / 8, gl = tid % 8;
-  constexpr int ngroups = kJacThreads / 8;
+  const int grp = tid / GL, gl = tid % GL;
+  constexpr int ngroups = kJacThreads / GL;
 
   // M (row-major, ld LP, as nparts partial sums added in order) into LDS
   // column-major with rows l .. ldm - 1 zero: read row-major (a wave reads
@@ -447,13 +452,17 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
         if (p > q) { int t = p; p = q; q = t; }
         double* mp = Mc + p * ldm + gl;
         double* mq = Mc + q * ldm + gl;
-        double x[NRB], y[NRB];
+        double x[RPL], y[RPL];
 #pragma unroll
-        for (int i = 0; i < NRB; ++i) { x[i] = mp[8 * i]; y[i] = mq[8 * i]; }
+        for (int i = 0; i < RPL; ++i) { x[i] = mp[GL * i]; y[i] = mq[GL * i]; }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int i = 0; i < NRB; ++i) { al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i]; }
-        al = sum8(al); be = sum8(be); ga = sum8(ga);
+        for (int i = 0; i < RPL; ++i) { al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i]; }
+        if constexpr (GL == 16) {
+          al = sum16(al); be = sum16(be); ga = sum16(ga);
+        } else {
+          al = sum8(al); be = sum8(be); ga = sum8(ga);
+        }
         if (!(ga * ga > tol2 * (al * be))) {  // orthogonal enough (or zero column)
           if (lg) *lg = double2{1.0, 0.0};
           continue;
@@ -461,17 +470,17 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
         // V: the row blocks before the last one are whole; in the last one
         // (registers vxl, vyl) rows past l go to the dummy word when V's
         // columns are not padded
-        double vx[NRB], vy[NRB], vxl = 0.0, vyl = 0.0;
+        double vx[RPL], vy[RPL], vxl = 0.0, vyl = 0.0;
         int ipl = 0, iql = 0;
         if (WANT_V) {
           // read before the rotation is formed, so that the latency overlaps
           // the division and square roots
 #pragma unroll
-          for (int i = 0; i < NRB - 1; ++i) {
-            vx[i] = Vc[p * vld + gl + 8 * i];
-            vy[i] = Vc[q * vld + gl + 8 * i];
+          for (int i = 0; i < RPL - 1; ++i) {
+            vx[i] = Vc[p * vld + gl + GL * i];
+            vy[i] = Vc[q * vld + gl + GL * i];
           }
-          const int rl = gl + 8 * (NRB - 1);
+          const int rl = gl + GL * (RPL - 1);
           const bool okl = !vtail || rl < l;
           ipl = okl ? p * vld + rl : vdummy;
           iql = okl ? q * vld + rl : vdummy;
@@ -482,15 +491,15 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
         jac_rotation(al, be, ga, c, s);
         if (lg) *lg = double2{c, s};
 #pragma unroll
-        for (int i = 0; i < NRB; ++i) {
-          mp[8 * i] = c * x[i] - s * y[i];
-          mq[8 * i] = s * x[i] + c * y[i];
+        for (int i = 0; i < RPL; ++i) {
+          mp[GL * i] = c * x[i] - s * y[i];
+          mq[GL * i] = s * x[i] + c * y[i];
         }
         if (WANT_V) {
 #pragma unroll
-          for (int i = 0; i < NRB - 1; ++i) {
-            Vc[p * vld + gl + 8 * i] = c * vx[i] - s * vy[i];
-            Vc[q * vld + gl + 8 * i] = s * vx[i] + c * vy[i];
+          for (int i = 0; i < RPL - 1; ++i) {
+            Vc[p * vld + gl + GL * i] = c * vx[i] - s * vy[i];
+            Vc[q * vld + gl + GL * i] = s * vx[i] + c * vy[i];
           }
           Vc[ipl] = c * vxl - s * vyl;
           Vc[iql] = s * vxl + c * vyl;
@@ -507,28 +516,29 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
     info->sweeps = sweep + (sweep < max_sweeps ? 1 : 0);
     if (sweep >= max_sweeps) atomicOr(&info->flags, kFlagNoConv);
   }
-  // column norms -> singular values
-  for (int c = grp; c < l; c += ngroups) {
+  // column norms -> singular values (groups of 8 lanes from here on)
+  const int g8 = tid / 8, l8 = tid % 8;
+  for (int c = g8; c < l; c += kJacThreads / 8) {
     double a = 0.0;
-    for (int r = gl; r < l; r += 8) a += Mc[c * ldm + r] * Mc[c * ldm + r];
+    for (int r = l8; r < l; r += 8) a += Mc[c * ldm + r] * Mc[c * ldm + r];
     a = sum8(a);
-    if (gl == 0) sig[c] = sqrt(a);
+    if (l8 == 0) sig[c] = sqrt(a);
   }
   __syncthreads();
   // rank of each column in descending order (ties: lower index first)
-  for (int c = grp; c < l; c += ngroups) {
+  for (int c = g8; c < l; c += kJacThreads / 8) {
     const double sc = sig[c];
     int rank = 0;
-    for (int i = gl; i < l; i += 8) rank += (sig[i] > sc || (sig[i] == sc && i < c)) ? 1 : 0;
+    for (int i = l8; i < l; i += 8) rank += (sig[i] > sc || (sig[i] == sc && i < c)) ? 1 : 0;
     for (int off = 4; off >= 1; off >>= 1) rank += __shfl_xor(rank, off, kWave);
     if (rank < k) {
       const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
-      for (int r = gl; r < l; r += 8) {
+      for (int r = l8; r < l; r += 8) {
         Ut[r * ldk + rank] = Mc[c * ldm + r] * inv;
         if (WANT_V) Vt[r * ldk + rank] = Vc[c * vld + r];
       }
-      if (gl == 0) sv[rank] = sc;
-      if (!WANT_V && vperm && gl == 0) vperm[rank] = c;
+      if (l8 == 0) sv[rank] = sc;
+      if (!WANT_V && vperm && l8 == 0) vperm[rank] = c;
     }
   }
 }
