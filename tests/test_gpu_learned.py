@@ -108,7 +108,10 @@ def test_batched_diagonal_equals_single(lib):
     for i, (s, (k, q)) in enumerate(zip(sig, specs)):
         _, S, _, info = lib.sorsvd_diag(s, k, q=q, seed=5 + i)
         assert torch.allclose(b.S[i], S, rtol=0, atol=1e-12)
-        assert abs(infos[i]["err_fro"] - info["err_fro"]) <= 1e-10
+        # the Th. 2 identity e^2 = 1 - sum_j s_j^2 / ||A||_F^2 is a difference
+        # of O(1) terms: two runs that round their s_j differently agree in
+        # e^2 to a few k u, not in e (which divides that by 2 e)
+        assert abs(infos[i]["err_fro"] ** 2 - info["err_fro"] ** 2) <= 4 * k * 2.0 ** -52
 
 
 def test_auto_fallback_and_judge(lib):
