@@ -84,6 +84,31 @@ def test_wide_core_svd_against_lapack(lib, l, k):
     assert np.abs(Mtx @ Vt - Ut * s[None, :]).max() < 1e-12 * s[0]
 
 
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_wide_truncated_sweeps_keep_v_consistent(lib, sweeps):
+    """A sweep cap that stops the block Jacobi early: the columns X = M V and V
+    carry the same rotations whatever the convergence (V receives each step's
+    W one launch later, and one launch after the last step), so A V - U diag(s)
+    = (I - P_Q1) A V is as small as in the converged run of the same draw
+    (it is the sketch's own approximation error; a W left out of V would
+    leave errors of the order of its rotation angle times s_1), and V stays
+    orthonormal."""
+    m, n, l = 600, 500, 200
+    sigma = 0.8 ** np.arange(n, dtype=np.float64)
+    A, _, _ = W.spectral(m, n, sigma, 12)
+
+    def relation_error(**opts):
+        U, S, V, info = lib.sorsvd(dev(A), l, q=0, seed=3, l=l, **opts)
+        U, S, V = host(U), host(S), host(V)
+        assert np.abs(V.T @ V - np.eye(l)).max() < 1e-12
+        return np.abs(A @ V - U * S[None, :]).max() / S[0], info
+
+    e_full, _ = relation_error()
+    e_cut, info = relation_error(max_sweeps=sweeps)
+    assert info["sweeps"] <= sweeps
+    assert e_cut <= 10 * e_full + 1e-12, (e_cut, e_full)
+
+
 def test_wide_core_svd_diagonal_is_a_permutation(lib):
     """Orthogonal columns: after the QR preconditioning (which reproduces a
     diagonal M to rounding) no rotation is needed, and V is the permutation
