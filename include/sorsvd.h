@@ -14,8 +14,8 @@
  *     *_workspace_bytes() call returns. Results depend only on the arguments.
  *     Process-wide state, all opt-in: the pass-timing events of
  *     sorsvd_pass_timing (created and freed by that call, per process), batch
- *     plans and graphs (sorsvd_batch_create / _graph, freed by the matching
- *     destroy calls), and the 64 MiB device array that sorsvd_noalloc uses as
+ *     plans with their side streams and graphs (sorsvd_batch_create / _graph,
+ *     freed by the matching destroy calls), and the 64 MiB device array that sorsvd_noalloc uses as
  *     its workspace (per device, until the process ends). The batch autotuner's
  *     cache file is read and written only when SORSVD_TUNE_CACHE names one.
  *   - `stream` is a hipStream_t (NULL = the default stream). All work is
@@ -310,7 +310,12 @@ int sorsvd_batch_upload(sorsvd_batch* b, void* workspace, size_t ws_bytes, void*
 
 /* Enqueue the whole batch on `stream`: Omega, 2q + 3 passes over each A with
  * their Cholesky QRs, projection, core SVDs, lifts, sign convention and the
- * result records. Problems with smaller q sit out the later power steps. */
+ * result records. Problems with smaller q sit out the later power steps.
+ * The launches of one step that serve problems of different sketch widths
+ * run on side streams of the plan, forked from `stream` and joined back to it
+ * before the next step (the plan creates them at its first run, on the
+ * device current then, and frees them with the plan); the work is complete
+ * when `stream` is. */
 int sorsvd_batch_run(const sorsvd_batch* b, void* workspace, void* stream);
 
 /* Launch configuration of the three pass kinds (sketch, orbit, projection):
@@ -342,7 +347,8 @@ int sorsvd_graph_destroy(void* graph_exec);
 /* Number of problems of a plan (0 for NULL). */
 int32_t sorsvd_batch_count(const sorsvd_batch* b);
 
-/* Free a plan (NULL is allowed). Does not touch device memory. */
+/* Free a plan and its side streams (NULL is allowed). Does not touch device
+ * memory. */
 void sorsvd_batch_destroy(sorsvd_batch* b);
 
 /*
