@@ -185,8 +185,10 @@ k_bgram(const BProb* __restrict__ probs, const BItem* __restrict__ items, int ni
     const int64_t rows = mode == M_GRAM2 ? P.n : P.m;
     const int64_t r0 = (int64_t)I.chunk * kGramRows;
     const int64_t r1 = min(rows, r0 + kGramRows);
+    // (T^T T: only its upper triangle, which the Cholesky factor reads)
     skinny_tile<double, true, 1, CT>(T, P.LP, P.LP, r0, r1, Y, P.LP, I.base, 1, nullptr,
-                                     P.gpart + (int64_t)I.chunk * P.LP * P.LP, P.LP, nullptr, Xs, red);
+                                     P.gpart + (int64_t)I.chunk * P.LP * P.LP, P.LP, nullptr, Xs, red,
+                                     mode == M_PGRAM ? 0 : 2);
   }
 }
 

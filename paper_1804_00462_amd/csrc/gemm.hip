@@ -45,6 +45,18 @@ k_skinny(const T* A, int64_t lda, int64_t OUT, int64_t K,
   const int64_t k0 = (int64_t)s * kchunk;
   const int64_t k1 = min(K, k0 + kchunk);
   const int64_t base = (int64_t)tile * (64 * RT);
+  if constexpr (sizeof(T) == 8 && TRANS) {
+    if (tri == 2 && c0 + CB <= base) {
+      // the whole tile lies below the diagonal of A^T A, of which only the
+      // upper triangle is wanted: zeros, with no pass over the rows
+      double* out = Tout ? Tout : P + (int64_t)s * OUT * ldp;
+      for (int e = threadIdx.x; e < 64 * RT * CB; e += 256) {
+        const int64_t r = base + e / CB;
+        if (r < OUT) out[r * ldp + c0 + e % CB] = 0.0;
+      }
+      return;
+    }
+  }
   // FP32 A^T Y: A fragments one step ahead (157 instead of 176 VGPRs at CT = 7:
   // three waves per SIMD); FP32 A X: two
   skinny_tile<T, TRANS, RT, CT, (sizeof(T) == 4 && !TRANS) ? 2 : 1>(A, lda, OUT, k0, k1, X + c0, ldx, base, vec_ok,
@@ -275,16 +287,18 @@ hipError_t launch_skinny(bool trans, const T* A, int64_t lda, int64_t OUT, int64
 }
 
 // With Tout != null and nsplit == 1 the kernel writes the FP64 result itself.
-// tri: X is upper triangular (see skinny_tile); not with ncb > 1 in place
-// (launch_apply_tri_blocks). ncb: column blocks of X and of the output (LP is
-// their total width).
+// tri = 1: X is upper triangular (see skinny_tile); not with ncb > 1 in place
+// (launch_apply_tri_blocks). tri = 2 (trans, X = A): only the upper triangle
+// of A^T A is formed. ncb: column blocks of X and of the output (LP is their
+// total width).
 hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
                              const double* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              double* P, double* normp, const int* skipflag, hipStream_t st,
-                             double* Tout, bool tri, int ncb) {
-  if (tri && ncb > 1 && Tout == A) return hipErrorInvalidValue;
+                             double* Tout, int tri, int ncb) {
+  if (tri == 1 && ncb > 1 && Tout == A) return hipErrorInvalidValue;
+  if (tri == 2 && (!trans || X != A)) return hipErrorInvalidValue;
   return launch_skinny<double>(trans, A, lda, OUT, K, X, ldx, LP, kchunk, nsplit, P, normp, skipflag,
-                               nsplit == 1 ? Tout : nullptr, st, tri ? 1 : 0, ncb);
+                               nsplit == 1 ? Tout : nullptr, st, tri, ncb);
 }
 
 hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OUT, int64_t K,

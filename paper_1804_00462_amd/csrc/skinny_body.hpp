@@ -97,7 +97,10 @@ constexpr int xs_elems() { return 2 * 4 * Traits<T>::VK * (CT * kTile + 2); }
 // upper triangular (X[k][c0 + c] = 0 for k > c0 + c, as R^{-1}, where X is
 // the column block starting at column c0 of the whole operand), so the MFMAs
 // of a step whose contraction indices all lie below a 16-column output tile
-// are skipped (their products are exact zeros). ldp: row stride of the
+// are skipped (their products are exact zeros). tri = 2 (FP64 A^T A, X = A):
+// only the upper triangle of the product is wanted (the Cholesky factor reads
+// no other), so the MFMAs of the 16 x 16 output tiles wholly below the
+// diagonal are skipped and those tiles are left zero. ldp: row stride of the
 // partial sums P (the width of the whole output when X is one column block).
 // Epi (optional): called as epi(orow, c, value) for every output row orow <
 // OUT and column c of the tile instead of storing it (Tout and P unused).
@@ -220,7 +223,13 @@ __device__ __attribute__((always_inline)) inline void skinny_tile(const T* A, in
         if constexpr (sizeof(T) == 8 && !TRANS)
           if (tri && kb - c0 >= (int64_t)(ct + 1) * kTile) continue;
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Tr::mfma(a[rt][j], bq[j & 1][ct], acc[rt][ct]);
+        for (int rt = 0; rt < RT; ++rt) {
+          // (tri = 2, A^T A: the 16 x 16 output tiles wholly below the
+          // diagonal are not formed; only the upper triangle is read)
+          if constexpr (sizeof(T) == 8 && TRANS)
+            if (tri == 2 && c0 + (int64_t)(ct + 1) * kTile <= base + (int64_t)(w * RT + rt) * kTile) continue;
+          acc[rt][ct] = Tr::mfma(a[rt][j], bq[j & 1][ct], acc[rt][ct]);
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
     }

@@ -23,7 +23,7 @@ namespace sor {
 hipError_t launch_skinny_f64(bool trans, const double* A, int64_t lda, int64_t OUT, int64_t K,
                              const double* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              double* P, double* normp, const int* skipflag, hipStream_t st,
-                             double* Tout = nullptr, bool tri = false, int ncb = 1);
+                             double* Tout = nullptr, int tri = 0, int ncb = 1);
 hipError_t launch_skinny_f32(bool trans, const float* A, int64_t lda, int64_t OUT, int64_t K,
                              const float* X, int64_t ldx, int LP, int64_t kchunk, int nsplit,
                              float* P, double* normp, const int* skipflag, hipStream_t st,
@@ -412,7 +412,7 @@ int tsqr_inplace(const Plan& p, double* T, int64_t rows, const Split& gram, void
     if (!final && it == 1) continue;
     const int* skip = it == 2 ? skip3 : nullptr;
     SORSVD_TRY(launch_skinny_f64(true, T, LP, LP, rows, T, LP, LP, gram.kchunk, gram.nsplit, P,
-                                 nullptr, skip, st, nullptr, false, p.ncb));
+                                 nullptr, skip, st, nullptr, 2, p.ncb));  // upper triangle of T^T T
     SORSVD_TRY(launch_reduce_f64(P, LP, LP, gram.nsplit, G, LP, LP, st, skip));
     if (p.wide) {
       SORSVD_TRY(launch_chol_wide(G, LP, (int)p.l, rows, it, Rinv, skip3, info, at<void>(ws, p.off_wchol), st));
