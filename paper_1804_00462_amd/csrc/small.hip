@@ -27,29 +27,19 @@ k_jacobi(const double* __restrict__ Min, int LP, int l, int k, int max_sweeps, d
 // of V starts as e_r and receives, step by step, the rotations of that step's
 // disjoint column pairs, (v_p, v_q) <- (c v_p - s v_q, s v_p + c v_q), p < q:
 // the sequence the columns of M received. Then Vt[r][j] = V[r][vperm[j]].
-// A wave owns one row, held in registers in round-robin position order: lane
-// pr holds positions pr and lp - 1 - pr, which are exactly the pair it
-// rotates at every step. Between steps position 0 stays and the others move
-// one place along the ring (the player at position x + 1 comes to x, the one
-// at 1 to lp - 1): one DPP wave shift per operand. After whole sweeps
-// positions and columns coincide again. The waves of a workgroup share the
-// coefficients, staged through LDS kVapChunk steps at a time: the next chunk
-// is loaded into registers while the current one is applied.
+// A wave owns one row and follows the pair order of jac_slot: lane s is slot
+// s and holds, for a level, the entry of its stationary column (a) and of
+// its current moving column (b); between steps the moving entries pass from
+// slot g + 1 to slot g of each block (a lane gather), and at the end of a
+// level (when after R steps every moving entry is back at its first slot)
+// the row goes through LDS to the next level's slots. The waves of a
+// workgroup share the coefficients, staged through LDS kVapChunk steps at a
+// time: the next chunk is loaded into registers while the current one is
+// applied.
 constexpr int kVapWaves = 4;
 constexpr int kVapChunk = 32;
 constexpr int kVapLoads = kVapChunk * kWave / (kWave * kVapWaves);
 constexpr int kVapGroup = 8;
-
-// Whole-wave shifts by one lane (DPP wave_shl:1 / wave_shr:1): lane i
-// receives v of lane i + 1, resp. i - 1; the lane with no source keeps v.
-template <int CTRL> __device__ inline double wave_shift(double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
-  const uint32_t slo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
-  const uint32_t shi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((uint64_t)shi << 32) | slo));
-}
-constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
 
 __global__ void __launch_bounds__(64 * kVapWaves)
 k_jacobi_vapply(const double2* __restrict__ rlog, const int* __restrict__ vperm, const DevInfo* __restrict__ info,
@@ -58,45 +48,64 @@ k_jacobi_vapply(const double2* __restrict__ rlog, const int* __restrict__ vperm,
   __shared__ double rows[kVapWaves][128];
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int r = blockIdx.x * kVapWaves + w;
-  const int lp = (l + 1) & ~1, npairs = lp / 2, steps = lp - 1;
+  const int ng = jac_groups(l), nst = jac_sweep_steps(l), nlev = jac_levels(l);
   const int sweeps = min(info->sweeps, max_sweeps);
-  const int64_t T = (int64_t)sweeps * steps;
-  const bool act = lane < npairs;
-  double a = (act && r == lane) ? 1.0 : 0.0;            // position lane
-  double b = (act && r == lp - 1 - lane) ? 1.0 : 0.0;   // position lp - 1 - lane
+  const int64_t T = (int64_t)sweeps * nst;
+  double* R = rows[w];
+  for (int j = lane; j < 128; j += kWave) R[j] = (j == r) ? 1.0 : 0.0;
+  __syncthreads();
   if (T > 0) {  // uniform
-    // chunk entry e = s * kWave + pr: coefficients of pair pr at step t0 + s.
-    // Addresses are clamped so that every load is unconditional (entries past
-    // the log, and those of lanes beyond the pairs, are never used: a lane
-    // past the pairs never passes its registers to a lane of a pair)
-    const int64_t tlast = T - 1;
-    auto load_entry = [&](int64_t t0, int j) {
-      const int e = threadIdx.x + j * 64 * kVapWaves;
-      return rlog[min(t0 + e / kWave, tlast) * npairs + min(e % kWave, npairs - 1)];
+    // level state (uniform: level d, its step j and length H) and this
+    // lane's slot in it
+    int d = 0, j = 0, H = jac_level_steps(l, 0);
+    JacSlot sl = jac_slot(l, 0, H, lane);
+    bool live = lane < ng;
+    double a = 0.0, b = 0.0;
+    auto enter = [&]() {
+      sl = jac_slot(l, d, H, lane);
+      a = (live && sl.g < sl.a) ? R[sl.p] : 0.0;
+      b = (live && sl.g < sl.m) ? R[sl.s1 + sl.g] : 0.0;
     };
-    int step = 0;
+    enter();
+    // chunk entry e = s * kWave + slot: coefficients of that slot at step
+    // t0 + s. Addresses are clamped so that every load is unconditional
+    // (entries past the log, and slots past the groups, are never used)
+    const int64_t tlast = T - 1;
+    auto load_entry = [&](int64_t t0, int jj) {
+      const int e = threadIdx.x + jj * 64 * kVapWaves;
+      return rlog[min(t0 + e / kWave, tlast) * ng + min(e % kWave, ng - 1)];
+    };
     auto apply = [&](const double2 cs) {
-      // columns at this lane's positions (position 0 holds column 0)
-      int pa = 0;
-      if (lane > 0) {
-        pa = lane - 1 + step;
-        pa = 1 + (pa >= steps ? pa - steps : pa);
+      if (j < sl.R) {  // the block's ring is still turning
+        int mi = sl.g + j;
+        if (mi >= sl.R) mi -= sl.R;
+        if (live && sl.g < sl.a && mi < sl.m) {
+          const double c = cs.x, s = cs.y, x = a, y = b;
+          a = c * x - s * y;
+          b = s * x + c * y;
+        }
       }
-      int pb = lp - 2 - lane + step;
-      pb = 1 + (pb >= steps ? pb - steps : pb);
-      const double c = cs.x, s = pa < pb ? cs.y : -cs.y;
-      const double x = a, y = b;
-      a = c * x - s * y;
-      b = s * x + c * y;
-      const double from_up = wave_shift<kDppWaveShl1>(a), from_down = wave_shift<kDppWaveShr1>(b);
-      const double na = lane == 0 ? a : (lane == npairs - 1 ? b : from_up);
-      const double nb = lane == 0 ? (npairs == 1 ? b : from_up) : from_down;
-      a = na;
-      b = nb;
-      if (++step == steps) step = 0;
+      // moving entries from slot g + 1 to slot g (ring of R slots)
+      int src = sl.g + 1;
+      if (src >= sl.R) src = 0;
+      src = lane - sl.g + src;
+      const double nb = __shfl(b, live ? src : lane, kWave);
+      if (live && j < sl.R && sl.g < sl.R) b = nb;
+      if (++j == H) {
+        // after R steps every moving entry is back at slot g: the row to LDS,
+        // then the next level's slots
+        if (live && sl.g < sl.a) R[sl.p] = a;
+        if (live && sl.g < sl.m) R[sl.s1 + sl.g] = b;
+        __syncthreads();
+        j = 0;
+        if (++d == nlev) d = 0;
+        H = jac_level_steps(l, d);
+        enter();
+        __syncthreads();
+      }
     };
 #pragma unroll
-    for (int j = 0; j < kVapLoads; ++j) cbuf[0][threadIdx.x + j * 64 * kVapWaves] = load_entry(0, j);
+    for (int jj = 0; jj < kVapLoads; ++jj) cbuf[0][threadIdx.x + jj * 64 * kVapWaves] = load_entry(0, jj);
     __syncthreads();
     const int64_t nch = ceil_div(T, (int64_t)kVapChunk);
     for (int64_t ch = 0; ch < nch; ++ch) {
@@ -105,7 +114,7 @@ k_jacobi_vapply(const double2* __restrict__ rlog, const int* __restrict__ vperm,
       // that the loads need no branch
       double2 st[kVapLoads];
 #pragma unroll
-      for (int j = 0; j < kVapLoads; ++j) st[j] = load_entry((ch + 1) * kVapChunk, j);
+      for (int jj = 0; jj < kVapLoads; ++jj) st[jj] = load_entry((ch + 1) * kVapChunk, jj);
       const double2* cb = cbuf[buf] + lane;
       if ((ch + 1) * kVapChunk <= T) {
         // coefficients read from LDS a group of kVapGroup steps ahead of use
@@ -128,16 +137,11 @@ k_jacobi_vapply(const double2* __restrict__ rlog, const int* __restrict__ vperm,
         for (int s = 0; s < ns; ++s) apply(cb[s * kWave]);
       }
 #pragma unroll
-      for (int j = 0; j < kVapLoads; ++j) cbuf[buf ^ 1][threadIdx.x + j * 64 * kVapWaves] = st[j];
+      for (int jj = 0; jj < kVapLoads; ++jj) cbuf[buf ^ 1][threadIdx.x + jj * 64 * kVapWaves] = st[jj];
       __syncthreads();
     }
   }
-  double* R = rows[w];
-  if (act) {
-    R[lane] = a;
-    R[lp - 1 - lane] = b;
-  }
-  __syncthreads();
+  // T is a whole number of sweeps: the row is in R (written at the last level end)
   if (r < l)
     for (int j = lane; j < k; j += kWave) Vt[r * ldk + j] = R[vperm[j]];
 }
@@ -303,8 +307,7 @@ static void launch_jacobi_nrb(int nrb, size_t shm, hipStream_t st, const double*
 // Bytes of the rotation log of a core SVD of width l with up to max_sweeps
 // sweeps, plus the permutation (see jacobi_body).
 size_t jacobi_log_bytes(int l, int max_sweeps) {
-  const int lp = (l + 1) & ~1;
-  return (size_t)max_sweeps * (lp - 1) * (lp / 2) * sizeof(double2) + 128 * sizeof(int);
+  return (size_t)max_sweeps * jac_sweep_steps(l) * jac_groups(l) * sizeof(double2) + 128 * sizeof(int);
 }
 
 // Whether the core SVD of width l rebuilds V from the rotation log: for
@@ -327,9 +330,8 @@ hipError_t launch_jacobi(const double* M, int LP, int l, int k, int max_sweeps, 
   if (want_v && rlog && jacobi_uses_log(l)) {
     bool v_lds = false;
     const size_t shm = jacobi_lds(l, false, &v_lds);
-    const int lp = (l + 1) & ~1;
     double2* lg = reinterpret_cast<double2*>(rlog);
-    int* perm = reinterpret_cast<int*>(lg + (size_t)max_sweeps * (lp - 1) * (lp / 2));
+    int* perm = reinterpret_cast<int*>(lg + (size_t)max_sweeps * jac_sweep_steps(l) * jac_groups(l));
     launch_jacobi_nrb<false, false>(nrb, shm, st, M, LP, l, k, max_sweeps, tol2, Ut, sv, Vt, ldk, Vg, di, lg, perm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -293,8 +293,8 @@ __device__ inline void chol_inv_body(const double* __restrict__ G, int nparts, i
 // gamma = m_p . m_q, zeta = (beta - alpha) / (2 gamma),
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = c t,
 // m_p <- c m_p - s m_q, m_q <- s m_p + c m_q (and the same on V), which makes
-// the pair orthogonal. A sweep visits every pair once in round-robin order
-// (l' - 1 steps of l'/2 disjoint pairs, l' = l rounded up to even); sweeps
+// the pair orthogonal. A sweep visits every pair once, in steps of disjoint
+// pairs (the order of jac_slot below); sweeps
 // stop when no pair had |gamma| > tol sqrt(alpha beta), or after max_sweeps.
 // Then sigma_j = |m_j|, U~_j = m_j / sigma_j, V~_j = v_j, sorted descending;
 // the first k are written (Ut, and Vt if WANT_V: l x k, ld ldk; s: k).
@@ -303,9 +303,18 @@ __device__ inline void chol_inv_body(const double* __restrict__ G, int nparts, i
 // (16 for widths 33 .. 64, else 8: the pairs of a step then fill two waves
 // per SIMD, which hide each other's latency; at widths above 64 groups of 8
 // already do, and groups of 4 (one wave per SIMD) are slower); lane g of a
-// group holds rows g, g + GL, ... of the two columns in registers for the
-// step (8 NRB / GL of them, NRB a compile-time row-block count), and the
-// three dot products are reduced with DPP. The step cost is VALU issue on one
+// group holds rows g, g + GL, ... of its columns in registers (8 NRB / GL of
+// them, NRB a compile-time row-block count), and the dot products are
+// reduced with DPP. A group keeps its stationary column (and that column of
+// V) in registers for a whole level of the order and reads and writes only
+// the moving column at each step: one column through LDS per pair and step
+// instead of two (LDS traffic, not arithmetic, sets the step time). When V is not in LDS, alpha and beta are
+// not formed at every step: the squared column norms are computed at the
+// start of each sweep and carried through it by the exact update of a
+// rotation (alpha - t gamma, beta + t gamma), recomputed from the rotated
+// column where that update cancels (the scheme of Drmac and Veselic's
+// one-sided Jacobi SVD), which leaves one dot product per pair and step.
+// The step cost is VALU issue on one
 // CU, so the layout avoids per-row masks: M lives in LDS column-major with its
 // columns padded with zero rows to ldm = 8 NRB (rotations keep them zero).
 // V, when wanted, lives in LDS when it fits: column stride ldm, or, where
@@ -321,6 +330,17 @@ __host__ __device__ constexpr int jac_nrb(int l) {
   return l <= 8 ? 1 : l <= 16 ? 2 : l <= 32 ? 4 : l <= 48 ? 6 : l <= 64 ? 8 : l <= 80 ? 10 : l <= 104 ? 13 : 16;
 }
 __host__ __device__ constexpr int jac_ldm(int l) { return 8 * jac_nrb(l); }
+// Lane groups of the Jacobi workgroup (one pair slot each): 8 lanes per
+// group, 16 for the row-block counts 6 and 8.
+__host__ __device__ constexpr int jac_groups(int l) {
+  return kJacThreads / ((jac_nrb(l) == 6 || jac_nrb(l) == 8) ? 16 : 8);
+}
+// Column stride of M in LDS when V is not there: with groups of 8 lanes
+// (every row-block count but 6 and 8) ldm rounded up to 16 doubles, so that
+// column starts fall on bank 0 (see jacobi_body); else ldm.
+__host__ __device__ constexpr int jac_mstride(int l) {
+  return (jac_nrb(l) == 6 || jac_nrb(l) == 8) ? jac_ldm(l) : ((jac_ldm(l) + 15) & ~15);
+}
 // Column stride of the global scratch Vg (LP x this): holds V with padded
 // columns, or the singular values.
 __host__ __device__ constexpr int jac_vg_ld(int l) { return jac_ldm(l) > ((l + 15) & ~15) ? jac_ldm(l) : ((l + 15) & ~15); }
@@ -336,8 +356,58 @@ __host__ __device__ inline bool jac_vtail_fits(int l) {
 __host__ __device__ inline size_t jacobi_lds(int l, bool want_v, bool* v_lds) {
   const size_t mbytes = (size_t)l * jac_ldm(l) * 8;
   *v_lds = want_v && (jac_vpad_fits(l) || jac_vtail_fits(l));
-  if (!*v_lds) return mbytes + (size_t)l * 8;  // M and the singular values
+  if (!*v_lds) return (size_t)l * jac_mstride(l) * 8 + (size_t)l * 8;  // M and the singular values
   return jac_vpad_fits(l) ? 2 * mbytes : mbytes + ((size_t)l * l + 1) * 8;
+}
+
+// Pair order of a sweep, shared by the Jacobi kernel and the V replay. Level
+// d (for 2^d < l) cuts the columns into the 2^(d+1) ranges
+// J(d + 1, i) = [ceil(i l / 2^(d+1)), ceil((i + 1) l / 2^(d+1))); in block
+// b < 2^d every column of range 2b (stationary) meets every column of range
+// 2b + 1 (moving): slot g of the block keeps stationary column g for the
+// whole level and meets moving column (g + j) mod R at step j, R the larger
+// range size, so that the moving columns pass from slot g + 1 to slot g
+// between steps. The level takes H = ceil(l / 2^(d+1)) steps (the largest R),
+// block b owns slots b H .. b H + R - 1 (2^d H <= 64 for l <= 128, <= 32
+// for l <= 64). Two columns meet at the first level that puts them in
+// different ranges, so a sweep meets every pair once: sum_d H steps, 127 at
+// l = 128, 102 at l = 100 (round-robin takes l - 1 or l), each with at most
+// one pair per slot.
+struct JacSlot {
+  int p;   // stationary column (valid when g < a)
+  int s1;  // first moving column
+  int a;   // stationary columns of the block
+  int m;   // moving columns of the block
+  int R;   // ring length max(a, m) (0: slot outside every block)
+  int g;   // position in the block
+};
+__host__ __device__ inline int jac_levels(int l) {
+  int d = 0;
+  while ((1 << d) < l) ++d;
+  return d;
+}
+__host__ __device__ inline int jac_level_steps(int l, int d) { return (l + (2 << d) - 1) >> (d + 1); }
+__host__ __device__ inline int jac_sweep_steps(int l) {
+  int n = 0;
+  for (int d = 0; (1 << d) < l; ++d) n += jac_level_steps(l, d);
+  return n;
+}
+__host__ __device__ inline JacSlot jac_slot(int l, int d, int H, int slot) {
+  JacSlot r;
+  const int b = slot / H;
+  r.g = slot - b * H;
+  if (b >= (1 << d)) {
+    r.p = r.s1 = r.a = r.m = r.R = 0;
+    return r;
+  }
+  const int sh = d + 1, rnd = (1 << sh) - 1;
+  const int s0 = (2 * b * l + rnd) >> sh, s1 = ((2 * b + 1) * l + rnd) >> sh, e1 = ((2 * b + 2) * l + rnd) >> sh;
+  r.a = s1 - s0;
+  r.m = e1 - s1;
+  r.R = r.a > r.m ? r.a : r.m;
+  r.p = s0 + r.g;
+  r.s1 = s1;
+  return r;
 }
 
 // (c, s) of the pair rotation above for gamma != 0, with t in one division:
@@ -345,28 +415,46 @@ __host__ __device__ inline size_t jacobi_lds(int l, bool want_v, bool* v_lds) {
 // t = sign(zeta) 2 |gamma| / (|d| + sqrt(d^2 + 4 gamma^2)), d = beta - alpha,
 // evaluated on d and 2 gamma scaled by the same power of two (the squares can
 // neither overflow nor underflow, and t does not change); sign(zeta) = +1
-// for d = 0. c = rsqrt(1 + t^2) with 1 + t^2 in [1, 2].
-__device__ inline void jac_rotation(double al, double be, double ga, double& c, double& s) {
+// for d = 0. c = rsqrt(1 + t^2) with 1 + t^2 in [1, 2], then (c, s) scaled
+// to unit length.
+__device__ inline void jac_rotation(double al, double be, double ga, double& c, double& s, double& t) {
   const double d = be - al, g2 = 2.0 * ga;
   const int e = ilogb(fmax(fabs(d), fabs(g2)));
   const double ds = ldexp(d, -e), gs = ldexp(g2, -e);
   const double t0 = fabs(gs) / (fabs(ds) + sqrt(fma(ds, ds, gs * gs)));
-  const double t = (d == 0.0 || (d > 0.0) == (ga > 0.0)) ? t0 : -t0;
+  t = (d == 0.0 || (d > 0.0) == (ga > 0.0)) ? t0 : -t0;
   c = rsqrt(fma(t, t, 1.0));
   s = c * t;
+  // one Newton step towards c^2 + s^2 = 1 (eu = c^2 + s^2 - 1 with one
+  // rounding of c^2 - 1): the reciprocal square root's error would otherwise
+  // enter every rotation with the same sign and grow the columns' norms
+  const double eu = fma(s, s, fma(c, c, -1.0));
+  const double f = fma(-0.5, eu, 1.0);
+  c *= f;
+  s *= f;
 }
+__device__ inline void jac_rotation(double al, double be, double ga, double& c, double& s) {
+  double t;
+  jac_rotation(al, be, ga, c, s, t);
+}
+
+// Below this ratio of a carried squared column norm to its value before the
+// rotation, the norm is recomputed from the rotated column (the update
+// subtracts nearly equal numbers there).
+constexpr double kJacNormKeep = 0.1;
 
 // Min is given as nparts partial sums (stride pstride elements), added in
 // order. tol2 = tol^2 (the main path takes tol = sqrt(l) 2^-52).
 //
 // rlog != null (with WANT_V false): V is not kept here. Instead the (c, s)
 // of every pair of every step is written to rlog (double2, (1, 0) where the
-// pair was not rotated; entry (sweep (lp - 1) + step) npairs + pr), and the
+// slot had no pair or did not rotate it; entry (sweep S + step) G + slot,
+// S = jac_sweep_steps(l), G = jac_groups(l)), and the
 // column of rank j < k to vperm[j]: every row of V receives the same
 // sequence of column rotations, so k_jacobi_vapply rebuilds V afterwards, one
 // row per wave and many rows at once, instead of moving V through this one
 // CU's LDS at every step (which doubles its LDS traffic). rlog holds
-// max_sweeps (lp - 1) npairs entries.
+// max_sweeps S G entries.
 template <bool V_LDS, bool WANT_V, int NRB>
 __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, int64_t pstride, int LP,
                                    int l, int k, int max_sweeps, double tol2, double* __restrict__ Ut,
@@ -375,16 +463,28 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
                                    double2* __restrict__ rlog = nullptr, int* __restrict__ vperm = nullptr) {
   static_assert(WANT_V || !V_LDS, "V in LDS only when wanted");
   constexpr int ldm = 8 * NRB;
+  constexpr int GL = (NRB == 6 || NRB == 8) ? 16 : 8;  // lanes per pair
+  constexpr int RPL = ldm / GL;                         // rows per lane
+  // Column stride of M: ldm, or with V out of LDS and groups of 8 lanes,
+  // ldm rounded up to 16 doubles (jac_mstride): every column then starts on
+  // bank 0, and the odd group of each 16-lane half-row takes its row blocks
+  // one block later (register i holds row block i + 1, the last one block
+  // 0), so the two groups that one LDS cycle serves always use the two
+  // opposite 16-bank halves, whatever their columns are
+  constexpr bool SWZ = !V_LDS && GL == 8;
+  constexpr int cst = SWZ ? ((ldm + 15) & ~15) : ldm;
   const bool vtail = V_LDS && !jac_vpad_fits(l);  // V columns unpadded (stride l)
-  double* Mc = sm;                              // column-major: Mc[c * ldm + r]
+  double* Mc = sm;                              // column-major: Mc[c * cst + r]
   double* Vc = V_LDS ? sm + (size_t)l * ldm : Vg;
   const int vld = vtail ? l : ldm;              // column stride of V
   const int vdummy = l * vld;                   // (vtail) the dummy word
   // singular values: after M (and V) in LDS, or in the unused global scratch
-  double* sig = V_LDS ? Vg : sm + (size_t)l * ldm;
+  double* sig = V_LDS ? Vg : sm + (size_t)l * cst;
+  // Squared column norms carried through a sweep when V is not in LDS (in
+  // the singular values' LDS words, which are written only after the sweeps)
+  constexpr bool CARRY = !V_LDS;
+  double* nrm = sig;
   __shared__ int s_rot;
-  constexpr int GL = (NRB == 6 || NRB == 8) ? 16 : 8;  // lanes per pair
-  constexpr int RPL = ldm / GL;                         // rows per lane
   const int tid = threadIdx.x;
   const int grp = tid / GL, gl = tid % GL;
   constexpr int ngroups = kJacThreads / GL;
@@ -416,7 +516,7 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
 #pragma unroll
       for (int u = 0; u < kMLoad; ++u) {
         const int i = i0 + tid + kJacThreads * u;
-        if (i < tot) Mc[(i % l) * ldm + i / l] = mv[u];
+        if (i < tot) Mc[(i % l) * cst + i / l] = mv[u];
       }
     }
   }
@@ -427,86 +527,142 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
     }
   __syncthreads();
 
-  const int lp = (l + 1) & ~1;
-  const int npairs = lp / 2;
+  const int nlev = jac_levels(l);
+  const int nst = jac_sweep_steps(l);
+  // offset of register i's row block (rotated by one block in odd groups)
+  const int odd = SWZ ? (grp & 1) : 0;
+  auto roff = [&](int i) { return i + odd < RPL ? GL * (i + odd) : 0; };
+  auto gsum = [](double v) { return GL == 16 ? sum16(v) : sum8(v); };
+  // V: the row blocks before the last one are whole; in the last one (row
+  // rl of this lane) rows past l go to the dummy word when V's columns are
+  // not padded
+  const int rl = gl + GL * (RPL - 1);
+  const bool okl = !vtail || rl < l;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) s_rot = 0;
-    __syncthreads();
-    for (int step = 0; step < lp - 1; ++step) {
-      for (int pr = grp; pr < npairs; pr += ngroups) {
-        // round-robin: position 0 fixed, positions 1..lp-1 rotate
-        auto player = [&](int pos) {
-          if (pos == 0) return 0;
-          int x = pos - 1 + step;
-          if (x >= lp - 1) x -= lp - 1;
-          return 1 + x;
-        };
-        double2* lg = (!WANT_V && rlog && gl == 0)
-                          ? rlog + ((size_t)sweep * (lp - 1) + step) * npairs + pr : nullptr;
-        int p = player(pr), q = player(lp - 1 - pr);
-        if (p >= l || q >= l) {
-          if (lg) *lg = double2{1.0, 0.0};
-          continue;
-        }
-        if (p > q) { int t = p; p = q; q = t; }
-        double* mp = Mc + p * ldm + gl;
-        double* mq = Mc + q * ldm + gl;
-        double x[RPL], y[RPL];
+    if constexpr (CARRY) {
+      // exact squared norms at the start of every sweep (groups of 8 lanes)
+      const int g8 = tid / 8, l8 = tid % 8;
+      for (int c = g8; c < l; c += kJacThreads / 8) {
+        double a = 0.0;
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) { x[i] = mp[GL * i]; y[i] = mq[GL * i]; }
-        double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) { al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i]; }
-        if constexpr (GL == 16) {
-          al = sum16(al); be = sum16(be); ga = sum16(ga);
-        } else {
-          al = sum8(al); be = sum8(be); ga = sum8(ga);
-        }
-        if (!(ga * ga > tol2 * (al * be))) {  // orthogonal enough (or zero column)
-          if (lg) *lg = double2{1.0, 0.0};
-          continue;
-        }
-        // V: the row blocks before the last one are whole; in the last one
-        // (registers vxl, vyl) rows past l go to the dummy word when V's
-        // columns are not padded
-        double vx[RPL], vy[RPL], vxl = 0.0, vyl = 0.0;
-        int ipl = 0, iql = 0;
-        if (WANT_V) {
-          // read before the rotation is formed, so that the latency overlaps
-          // the division and square roots
-#pragma unroll
-          for (int i = 0; i < RPL - 1; ++i) {
-            vx[i] = Vc[p * vld + gl + GL * i];
-            vy[i] = Vc[q * vld + gl + GL * i];
-          }
-          const int rl = gl + GL * (RPL - 1);
-          const bool okl = !vtail || rl < l;
-          ipl = okl ? p * vld + rl : vdummy;
-          iql = okl ? q * vld + rl : vdummy;
-          vxl = Vc[ipl];
-          vyl = Vc[iql];
-        }
-        double c, s;
-        jac_rotation(al, be, ga, c, s);
-        if (lg) *lg = double2{c, s};
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          mp[GL * i] = c * x[i] - s * y[i];
-          mq[GL * i] = s * x[i] + c * y[i];
-        }
-        if (WANT_V) {
-#pragma unroll
-          for (int i = 0; i < RPL - 1; ++i) {
-            Vc[p * vld + gl + GL * i] = c * vx[i] - s * vy[i];
-            Vc[q * vld + gl + GL * i] = s * vx[i] + c * vy[i];
-          }
-          Vc[ipl] = c * vxl - s * vyl;
-          Vc[iql] = s * vxl + c * vyl;
-        }
-        if (gl == 0) s_rot = 1;
+        for (int i = 0; i < NRB; ++i) a += Mc[c * cst + l8 + 8 * i] * Mc[c * cst + l8 + 8 * i];
+        a = sum8(a);
+        if (l8 == 0) nrm[c] = a;
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    int tstep = 0;  // step within the sweep
+    for (int d = 0; d < nlev; ++d) {
+      const int H = jac_level_steps(l, d);
+      const JacSlot sl = jac_slot(l, d, H, grp);
+      const bool has_p = sl.g < sl.a;
+      const int p = has_p ? sl.p : 0;
+      double* mp = Mc + p * cst + gl;
+      // the stationary column (and its squared norm, and its column of V)
+      double x[RPL], vx[RPL], al = 0.0;
+      const int ipl = okl ? p * vld + rl : vdummy;
+      if (has_p) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) x[i] = mp[roff(i)];
+        if constexpr (CARRY) al = nrm[p];
+        if (WANT_V) {
+#pragma unroll
+          for (int i = 0; i < RPL - 1; ++i) vx[i] = Vc[p * vld + gl + GL * i];
+          vx[RPL - 1] = Vc[ipl];
+        }
+      }
+      for (int j = 0; j < H; ++j, ++tstep) {
+        double2* lg = (!WANT_V && rlog && gl == 0)
+                          ? rlog + ((size_t)sweep * nst + tstep) * ngroups + grp : nullptr;
+        int mi = sl.g + j;
+        if (mi >= sl.R) mi -= sl.R;
+        double c = 1.0, s = 0.0;
+        if (has_p && j < sl.R && mi < sl.m) {
+          const int q = sl.s1 + mi;
+          double* mq = Mc + q * cst + gl;
+          double y[RPL];
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) y[i] = mq[roff(i)];
+          double alx, be, ga;
+          if constexpr (CARRY) {
+            // alpha and beta from the carried norms; gamma in three partial
+            // sums (three independent FMA chains instead of one)
+            alx = al;
+            be = nrm[q];
+            double g3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) g3[i % 3] += x[i] * y[i];
+            ga = gsum((g3[0] + g3[1]) + g3[2]);
+          } else {
+            alx = 0.0; be = 0.0; ga = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) { alx += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i]; }
+            alx = gsum(alx); be = gsum(be); ga = gsum(ga);
+          }
+          if (ga * ga > tol2 * (alx * be)) {  // else orthogonal enough (or a zero column)
+            double vy[RPL];
+            const int iql = okl ? q * vld + rl : vdummy;
+            if (WANT_V) {
+              // read before the rotation is formed, so that the latency
+              // overlaps the division and square roots
+#pragma unroll
+              for (int i = 0; i < RPL - 1; ++i) vy[i] = Vc[q * vld + gl + GL * i];
+              vy[RPL - 1] = Vc[iql];
+            }
+            double tr;
+            jac_rotation(alx, be, ga, c, s, tr);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+              const double xi = x[i];
+              x[i] = c * xi - s * y[i];
+              y[i] = s * xi + c * y[i];
+              mq[roff(i)] = y[i];
+            }
+            if constexpr (CARRY) {
+              // the rotated pair's squared norms are the eigenvalues of its
+              // 2 x 2 Gram matrix: alpha - t gamma and beta + t gamma
+              double a2 = fma(-tr, ga, alx), b2 = fma(tr, ga, be);
+              if (!(a2 >= kJacNormKeep * alx && b2 >= kJacNormKeep * be)) {
+                double sa = 0.0, sb = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) { sa += x[i] * x[i]; sb += y[i] * y[i]; }
+                a2 = gsum(sa);
+                b2 = gsum(sb);
+              }
+              al = a2;
+              if (gl == 0) nrm[q] = b2;
+            }
+            if (WANT_V) {
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) {
+                const double xi = vx[i];
+                vx[i] = c * xi - s * vy[i];
+                vy[i] = s * xi + c * vy[i];
+              }
+#pragma unroll
+              for (int i = 0; i < RPL - 1; ++i) Vc[q * vld + gl + GL * i] = vy[i];
+              Vc[iql] = vy[RPL - 1];
+            }
+            if (gl == 0) s_rot = 1;
+          }
+        }
+        if (lg) *lg = double2{c, s};
+        if (j == H - 1 && has_p) {
+          // end of the level: the stationary column back to LDS (no other
+          // group reads it during this level)
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) mp[roff(i)] = x[i];
+          if constexpr (CARRY) if (gl == 0) nrm[p] = al;
+          if (WANT_V) {
+#pragma unroll
+            for (int i = 0; i < RPL - 1; ++i) Vc[p * vld + gl + GL * i] = vx[i];
+            Vc[ipl] = vx[RPL - 1];
+          }
+        }
+        __syncthreads();
+      }
     }
     const int rot = s_rot;
     __syncthreads();
@@ -520,7 +676,7 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
   const int g8 = tid / 8, l8 = tid % 8;
   for (int c = g8; c < l; c += kJacThreads / 8) {
     double a = 0.0;
-    for (int r = l8; r < l; r += 8) a += Mc[c * ldm + r] * Mc[c * ldm + r];
+    for (int r = l8; r < l; r += 8) a += Mc[c * cst + r] * Mc[c * cst + r];
     a = sum8(a);
     if (l8 == 0) sig[c] = sqrt(a);
   }
@@ -534,7 +690,7 @@ __device__ inline void jacobi_body(const double* __restrict__ Min, int nparts, i
     if (rank < k) {
       const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
       for (int r = l8; r < l; r += 8) {
-        Ut[r * ldk + rank] = Mc[c * ldm + r] * inv;
+        Ut[r * ldk + rank] = Mc[c * cst + r] * inv;
         if (WANT_V) Vt[r * ldk + rank] = Vc[c * vld + r];
       }
       if (l8 == 0) sv[rank] = sc;
