@@ -49,7 +49,10 @@ k_jacobi_vapply(const double2* __restrict__ rlog, const int* __restrict__ vperm,
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int r = blockIdx.x * kVapWaves + w;
   const int ng = jac_groups(l), nst = jac_sweep_steps(l), nlev = jac_levels(l);
-  const int sweeps = min(info->sweeps, max_sweeps);
+  // a converged run's last sweep rotated nothing (that is how it ended):
+  // it is not replayed; after the sweep cap every sweep is
+  const int ran = min(info->sweeps, max_sweeps);
+  const int sweeps = (info->flags & kFlagNoConv) ? ran : max(ran - 1, 0);
   const int64_t T = (int64_t)sweeps * nst;
   double* R = rows[w];
   for (int j = lane; j < 128; j += kWave) R[j] = (j == r) ? 1.0 : 0.0;
