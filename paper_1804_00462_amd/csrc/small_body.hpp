@@ -410,24 +410,48 @@ __host__ __device__ inline JacSlot jac_slot(int l, int d, int H, int slot) {
   return r;
 }
 
-// (c, s) of the pair rotation above for gamma != 0, with t in one division:
-// multiplying the numerator and the denominator of t by 2 |gamma| gives
+// (c, s) of the pair rotation above for gamma != 0. Multiplying the
+// numerator and the denominator of t by 2 |gamma| gives
 // t = sign(zeta) 2 |gamma| / (|d| + sqrt(d^2 + 4 gamma^2)), d = beta - alpha,
-// evaluated on d and 2 gamma scaled by the same power of two (the squares can
-// neither overflow nor underflow, and t does not change); sign(zeta) = +1
-// for d = 0. c = rsqrt(1 + t^2) with 1 + t^2 in [1, 2], then (c, s) scaled
-// to unit length.
+// evaluated on d and 2 gamma scaled by the same power of two into [1, 2) for
+// the larger (the squares can neither overflow nor underflow, and t does not
+// change); sign(zeta) = +1 for d = 0. With the arguments in fixed ranges,
+// the square root (of [1, 8)), the reciprocal (of [1, 5)) and
+// c = 1 / sqrt(1 + t^2) (of [1, 2]) take the hardware estimates and Newton
+// steps (a short dependency chain: the rotation sits on the critical path of
+// every Jacobi step); from estimates within 2^-14 the steps reach full
+// precision. Then (c, s) take one Newton step to unit length.
 __device__ inline void jac_rotation(double al, double be, double ga, double& c, double& s, double& t) {
   const double d = be - al, g2 = 2.0 * ga;
   const int e = ilogb(fmax(fabs(d), fabs(g2)));
-  const double ds = ldexp(d, -e), gs = ldexp(g2, -e);
-  const double t0 = fabs(gs) / (fabs(ds) + sqrt(fma(ds, ds, gs * gs)));
+  const double ds = ldexp(d, -e), gs = fabs(ldexp(g2, -e));
+  const double r2 = fma(ds, ds, gs * gs);  // [1, 8)
+  // sqrt(r2): g ~ sqrt, h ~ 1 / (2 sqrt), one coupled step, then a Newton
+  // step on g
+  const double y0 = __builtin_amdgcn_rsq(r2);
+  double g = r2 * y0, h = 0.5 * y0;
+  const double rr = fma(-h, g, 0.5);
+  g = fma(g, rr, g);
+  h = fma(h, rr, h);
+  g = fma(fma(-g, g, r2), h, g);
+  // t0 = gs / den, den = |ds| + sqrt(r2) in [1, 5)
+  const double den = fabs(ds) + g;
+  double q = __builtin_amdgcn_rcp(den);
+  q = fma(q, fma(-den, q, 1.0), q);
+  q = fma(q, fma(-den, q, 1.0), q);
+  double t0 = gs * q;
+  t0 = fma(fma(-den, t0, gs), q, t0);
   t = (d == 0.0 || (d > 0.0) == (ga > 0.0)) ? t0 : -t0;
-  c = rsqrt(fma(t, t, 1.0));
+  // c = 1 / sqrt(u), u = 1 + t^2 in [1, 2]: two Newton steps
+  const double u = fma(t, t, 1.0);
+  double cy = __builtin_amdgcn_rsq(u);
+  cy = fma(0.5 * cy, fma(-u * cy, cy, 1.0), cy);
+  cy = fma(0.5 * cy, fma(-u * cy, cy, 1.0), cy);
+  c = cy;
   s = c * t;
   // one Newton step towards c^2 + s^2 = 1 (eu = c^2 + s^2 - 1 with one
-  // rounding of c^2 - 1): the reciprocal square root's error would otherwise
-  // enter every rotation with the same sign and grow the columns' norms
+  // rounding of c^2 - 1): a rounding of the same sign in every rotation
+  // would otherwise grow the columns' norms
   const double eu = fma(s, s, fma(c, c, -1.0));
   const double f = fma(-0.5, eu, 1.0);
   c *= f;
