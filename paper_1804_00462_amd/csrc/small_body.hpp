@@ -4,7 +4,8 @@
 //   * Cholesky factor and inverse of the l x l Gram matrix (the QR step of
 //     Alg. 3 / Alg. 4 as Cholesky QR: T = Q R with R^T R = T^T T),
 //   * the core SVD of M = Q1^T A Q2 by one-sided (Hestenes) Jacobi rotations
-//     with a round-robin pair order (rank-k truncation of Alg. 3 step 6).
+//     in a pair order of levels with stationary columns (rank-k truncation
+//     of Alg. 3 step 6).
 #pragma once
 #include "common.hpp"
 
