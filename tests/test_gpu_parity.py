@@ -164,7 +164,11 @@ def test_project_fp64(lib):
     assert np.abs(M - osvd.projection(A, Q1, Q2)).max() < 1e-12
 
 
-@pytest.mark.parametrize("l,k", [(20, 20), (100, 100), (64, 10), (128, 128), (7, 3), (1, 1)])
+# widths of every row-block variant (l <= 8, 16, 32, 48, 64, 80, 104, 128) and
+# of uneven level ranges of the pair order; V in the kernel up to 32, rebuilt
+# from the rotation log above
+@pytest.mark.parametrize("l,k", [(20, 20), (100, 100), (64, 10), (128, 128), (7, 3), (1, 1), (2, 2), (3, 3),
+                                 (11, 11), (33, 30), (47, 47), (72, 50), (81, 81), (105, 105)])
 def test_core_svd_against_lapack(lib, l, k):
     gen = W.rng(l * 7 + k)
     Mtx = gen.standard_normal((l, l)) @ np.diag(np.geomspace(1, 1e-6, l)) @ gen.standard_normal((l, l))
