@@ -210,6 +210,23 @@ def test_core_svd_rotation_log_matches_v_in_kernel(lib, l):
     assert np.abs(Mtx @ Vh - host(Ua) * host(sa)[None, :]).max() < 1e-12 * np.abs(host(sa)).max()
 
 
+@pytest.mark.parametrize("l", [40, 100, 128])
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_core_svd_sweep_cap_replays_every_sweep(lib, l, sweeps):
+    """A sweep cap that stops the Jacobi before convergence: the V replay then
+    applies every logged sweep (a converged run's last sweep rotates nothing
+    and is skipped). Whatever the sweep count, the rotated columns are M V and
+    U = (M V) diag(1/s), so M V = U diag(s) to rounding; a sweep left out of V
+    would leave errors of the order of its rotation angles times s_1."""
+    gen = W.rng(200 + l + sweeps)
+    Mtx = gen.standard_normal((l, l)) @ np.diag(np.geomspace(1, 1e-3, l)) @ gen.standard_normal((l, l))
+    Ut, s, Vt, info = lib.step_core_svd(dev(Mtx), l, max_sweeps=sweeps)
+    Ut, s, Vt = host(Ut), host(s), host(Vt)
+    assert info["sweeps"] == sweeps and (info["flags"] & 1)  # stopped at the cap
+    assert np.abs(Vt.T @ Vt - np.eye(l)).max() < 1e-13
+    assert np.abs(Mtx @ Vt - Ut * s[None, :]).max() <= 1e-12 * s[0]
+
+
 def test_core_svd_rotation_log_no_rotation_is_a_permutation(lib):
     """A diagonal M (orthogonal columns) takes no rotation: every logged pair
     is the identity and V is the permutation that sorts the values."""
