@@ -407,7 +407,7 @@ def main():
                     help="also run 3 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).",
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1).",
               file=sys.stderr)
         return 2
 

@@ -46,7 +46,7 @@ typedef enum sorsvd_status {
   SORSVD_ENOCONV = -4,       /* (info flag) Jacobi reached its sweep cap */
   SORSVD_ENONFINITE = -5,    /* (info flag) A holds Inf or NaN */
   SORSVD_ETOL = -6,          /* sorsvd_auto: the tolerance was not met, fallback included */
-  SORSVD_EUNSUPPORTED = -7   /* valid request outside what this build implements */
+  SORSVD_EUNSUPPORTED = -7   /* valid request outside what the library implements */
 } sorsvd_status;
 
 /* Element types. A's type sets the arithmetic of the passes over A:

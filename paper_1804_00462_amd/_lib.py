@@ -18,7 +18,7 @@ SORSVD_F64, SORSVD_F32, SORSVD_BF16, SORSVD_DIAG, SORSVD_F16 = 0, 1, 2, 3, 4
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error",
           -4: "Jacobi sweep cap reached", -5: "non-finite input", -6: "tolerance not met",
-          -7: "unsupported in this build"}
+          -7: "unsupported by the library"}
 
 
 class SorsvdError(RuntimeError):

@@ -1602,7 +1602,7 @@ const char* sorsvd_status_string(int status) {
     case SORSVD_ENOCONV: return "Jacobi sweep cap reached";
     case SORSVD_ENONFINITE: return "non-finite input";
     case SORSVD_ETOL: return "tolerance not met";
-    case SORSVD_EUNSUPPORTED: return "unsupported in this build";
+    case SORSVD_EUNSUPPORTED: return "unsupported by the library";
     default: return "unknown status";
   }
 }
