@@ -102,7 +102,7 @@ def sorsvd(A, k, q=0, seed=0, l=None, mode="canonical", Omega=None, return_all=F
     elif mode == "literal":
         T2 = Omega
         for _ in range(q + 1):                    # Alg. 4 loop, no intermediate QR
-            X = T2                                # the non-updated T2 of this round
+            X = T2                                # the non-updated T2 of this power iteration
             T1 = A @ X
             T2 = A.T @ T1
         Q1, _ = qr_pos(T1)

@@ -23,6 +23,6 @@ def gpu_available():
 
 @pytest.fixture(scope="session")
 def lib():
-    """The HIP library binding; on a GPU machine a missing build is an error, not a skip."""
+    """The HIP library binding; on a machine with a GPU a missing build is an error, not a skip."""
     import paper_1804_00462_amd as P
     return P
