@@ -721,9 +721,16 @@ int run_batch(const sorsvd_batch* b, void* ws, bool timed, hipStream_t st) {
   if ((rc = launch_pass<TA>(b, ws, M_PROJ, -1, b->cfg[2], timed, st))) return rc;
   if ((rc = launch_f64(b, ws, M_PGRAM, -1, 0, st))) return rc;
   // core SVD, truncated to k (Alg. 3 step 6)
-  // (the layout of each problem follows its own l; LDS is sized for the largest)
+  // (the layout of each problem follows its own l. With V in LDS a smaller
+  // problem may take the padded V layout, which can need more than the
+  // largest problem's unpadded one: LDS is sized for the largest need)
   bool v_lds = false;
-  const size_t jshm = jacobi_lds(b->max_l, true, &v_lds);
+  size_t jshm = jacobi_lds(b->max_l, true, &v_lds);
+  if (v_lds)
+    for (const BProb& P : b->probs) {
+      bool vl = false;
+      jshm = std::max(jshm, jacobi_lds(P.l, true, &vl));
+    }
   if (v_lds)
     hipLaunchKernelGGL(k_bjacobi<true>, dim3(np), dim3(kJacThreads), jshm, st, probs, order, b->max_sweeps);
   else

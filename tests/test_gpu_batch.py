@@ -107,6 +107,29 @@ def test_fp64_batch_matches_oracle(lib):
         assert infos[i]["flags"] == (0 if (l or k) < 100 else infos[i]["flags"] & 4), infos[i]
 
 
+def test_batch_core_svd_lds_fits_every_problem(lib):
+    """The batched core SVD keeps V in LDS when the widest problem's fits; a
+    narrower problem may then take the padded V layout, which needs more LDS
+    than the widest one's unpadded layout (l = 97 against l = 99): the launch
+    is sized for the largest need, and both problems match the oracle."""
+    mats, specs = [], []
+    for i, l in enumerate((99, 97)):
+        A, _, _ = W.spectral(400, 300, 0.9 ** np.arange(300), 90 + i)
+        mats.append(A)
+        specs.append((l - 5, l, 1, 300 + i))
+    b, _ = make_batch(lib, mats, specs, torch.float64)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (A, (k, l, q, seed)) in enumerate(zip(mats, specs)):
+        print(f"problem {i}: {A.shape} k={k} l={l} q={q}", flush=True)
+        U, S, V = host(b.U[i]), host(b.S[i]), host(b.V[i])
+        Uo, So, Vo, io = osvd.sorsvd(A, k, q=q, seed=seed, l=l)
+        assert normwise(S, So) <= 1e-10
+        R = (U * S) @ V.T - (Uo * So) @ Vo.T
+        assert np.abs(R).max() <= 1e-10 * np.abs(A).max()
+        assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-12
+
+
 def test_fp64_batch_equals_single_problem_path(lib):
     mats, specs = mixed_inputs(torch.float64, 70)
     b, dmats = make_batch(lib, mats, specs, torch.float64)
